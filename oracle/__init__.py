@@ -1,0 +1,316 @@
+"""FP64 CPU oracle for the multi-scale 1D CWT.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library and never calls it; the only thing both sides use
+is the input generator package ``synth``.
+
+Contents
+--------
+* ``cwt`` / ``cwt_points`` -- the direct O(N * chi * s) sum (Sec. 3,
+  Eq. discreteCWT with the 1/s correlation normalisation), in plain C with
+  OpenMP (``cwt_oracle.c``).
+* ``psi`` / ``chi`` -- the mother wavelets in the time domain.
+* Spline method (Sec. 3.3, App. B, App. C):
+  ``spline_coeffs`` (cubic-spline interpolation coefficients c of the
+  signal, Eq. interp_coeffs, by a banded solve or an FFT division -- not by
+  the recursive filter of App. C), ``wavelet_spline_coeffs`` (d of Eq.
+  beta3_wavelet_approx_m02), ``ae_m`` (Eq. m02cwt_error), ``h_star`` (the
+  step where AE_M = 5e-4, Sec. 4.4), ``spline_delta`` and
+  ``spline_target`` (the exact CWT of the spline interpolant with the
+  spline wavelet, by Gauss-Legendre quadrature).
+
+Readings of the paper that this oracle takes (each is repeated in the
+design notes): scales and positions are in samples; the canonical result is
+the 1/s correlation with conj(psi) as a unit-step sum; chi is the radius
+where |psi| falls below ``rel`` times its maximum; the spline step is
+h_s = delta_s / s with delta_s = max(1, floor(h* s)) so that every knot is
+an integer.
+
+Parity pins: every function above is pinned in ``tests/test_oracle_*.py``
+against closed forms, printed constants of Tables 2 and 3, brute force and
+invariants.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cwt_oracle.c")
+_LIB = os.path.join(_HERE, "libcwt_oracle.so")
+
+MORLET, DOG = 0, 1
+PERIODIC, ZERO = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP, IEEE semantics)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lp = ctypes.POINTER(ctypes.c_long)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.oracle_chi.restype = ctypes.c_double
+        lib.oracle_chi.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        lib.oracle_psi.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_long, dp, dp]
+        lib.oracle_cwt.argtypes = [dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   dp, ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_int]
+        lib.oracle_cwt_points.argtypes = [dp, ctypes.c_long, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, dp, ctypes.c_int, ctypes.c_double,
+                                          ip, lp, ctypes.c_long, dp, dp, ctypes.c_int]
+        lib.oracle_spline_target.argtypes = [dp, ctypes.c_long, ctypes.c_long, dp, dp,
+                                             ctypes.c_long, ctypes.c_long, ctypes.c_double,
+                                             lp, ctypes.c_long, dp, dp, ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _wavelet(wavelet: str, param: float | None):
+    w = wavelet.lower()
+    if w == "morlet":
+        return MORLET, 6.0 if param is None else float(param)
+    if w in ("mexhat", "mexican_hat"):
+        return DOG, 2.0
+    if w == "dog":
+        return DOG, 2.0 if param is None else float(param)
+    raise ValueError(wavelet)
+
+
+def is_complex(wavelet: str) -> bool:
+    return wavelet.lower() == "morlet"
+
+
+def psi(wavelet: str, param: float | None, x) -> np.ndarray:
+    kind, p = _wavelet(wavelet, param)
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+    re = np.empty_like(x)
+    im = np.empty_like(x)
+    _load().oracle_psi(kind, p, _dp(x), x.size, _dp(re), _dp(im))
+    return re + 1j * im if kind == MORLET else re
+
+
+def chi(wavelet: str, param: float | None = None, rel: float = 1e-17) -> float:
+    kind, p = _wavelet(wavelet, param)
+    return float(_load().oracle_chi(kind, p, rel))
+
+
+def cwt(f, boundary: str, wavelet: str, scales, param: float | None = None,
+        rel: float = 1e-17, nthreads: int = 0) -> np.ndarray:
+    """Full direct-sum transform, [S, N] complex128 (Morlet) or float64."""
+    kind, p = _wavelet(wavelet, param)
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+    sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64))
+    n, s = f.size, sc.size
+    re = np.empty((s, n))
+    im = np.empty((s, n)) if kind == MORLET else None
+    bc = PERIODIC if boundary == "periodic" else ZERO
+    _load().oracle_cwt(_dp(f), n, bc, kind, p, _dp(sc), s, rel, _dp(re),
+                       _dp(im) if im is not None else None, nthreads)
+    return re + 1j * im if im is not None else re
+
+
+def cwt_points(f, boundary: str, wavelet: str, scales, scale_idx, pos,
+               param: float | None = None, rel: float = 1e-17, nthreads: int = 0) -> np.ndarray:
+    """Direct-sum transform at the outputs (scale_idx[i], pos[i])."""
+    kind, p = _wavelet(wavelet, param)
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+    sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64))
+    si = np.ascontiguousarray(np.asarray(scale_idx, dtype=np.int32))
+    ps = np.ascontiguousarray(np.asarray(pos, dtype=np.int64))
+    re = np.empty(si.size)
+    im = np.empty(si.size) if kind == MORLET else None
+    bc = PERIODIC if boundary == "periodic" else ZERO
+    _load().oracle_cwt_points(_dp(f), f.size, bc, kind, p, _dp(sc), sc.size, rel,
+                              si.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                              ps.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), si.size,
+                              _dp(re), _dp(im) if im is not None else None, nthreads)
+    return re + 1j * im if im is not None else re
+
+
+# --------------------------------------------------------------------------
+# Spline method (Sec. 3.3, App. B, App. C).
+
+def beta3(x) -> np.ndarray:
+    """Cubic B-spline (App. B, Eq. betan with n = 3)."""
+    a = np.abs(np.asarray(x, dtype=np.float64))
+    out = np.zeros_like(a)
+    m1 = a < 1.0
+    m2 = (a >= 1.0) & (a < 2.0)
+    out[m1] = 2.0 / 3.0 - a[m1] ** 2 + 0.5 * a[m1] ** 3
+    out[m2] = (2.0 - a[m2]) ** 3 / 6.0
+    return out
+
+
+def _solve_b3(rhs: np.ndarray) -> np.ndarray:
+    """Solve (c[n-1] + 4 c[n] + c[n+1]) / 6 = rhs[n] with c = 0 just outside
+    the array (the caller extends the array far enough that this boundary
+    value is irrelevant)."""
+    from scipy.linalg import solve_banded
+    n = rhs.size
+    ab = np.zeros((3, n))
+    ab[0, 1:] = 1.0 / 6.0
+    ab[1, :] = 4.0 / 6.0
+    ab[2, :-1] = 1.0 / 6.0
+    if np.iscomplexobj(rhs):
+        return solve_banded((1, 1), ab, rhs.real) + 1j * solve_banded((1, 1), ab, rhs.imag)
+    return solve_banded((1, 1), ab, rhs)
+
+
+def spline_coeffs(f, boundary: str, pad: int = 48):
+    """Cubic-spline interpolation coefficients c of the samples f (Eq.
+    interp_coeffs): sum_k c[k] beta3(n - k) = f[n] for every integer n.
+
+    periodic: returns (c, 0), c of length N, by dividing the DFT of f by the
+    DFT of the sampled cubic B-spline, (4 + 2 cos w)/6.
+    zero: f is zero outside [0, N); returns (c, -pad) with c on
+    [-pad, N + pad) from a banded solve on that range (the neglected tail is
+    below (2 - sqrt 3)^pad relative)."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.size
+    if boundary == "periodic":
+        w = 2 * np.pi * np.arange(n) / n
+        c = np.fft.ifft(np.fft.fft(f) / ((4.0 + 2.0 * np.cos(w)) / 6.0)).real
+        return c, 0
+    rhs = np.zeros(n + 2 * pad)
+    rhs[pad:pad + n] = f
+    return _solve_b3(rhs), -pad
+
+
+def wavelet_spline_coeffs(wavelet: str, param: float | None, h: float, nd: int):
+    """d[k], k in [-nd, nd]: cubic-spline interpolation coefficients of the
+    samples psi(h k) (Eq. beta3_wavelet_approx_m02, computed as Eq.
+    interp_coeffs).  The samples are taken on a range 40 wider than chi/h on
+    each side; the solution is then truncated to [-nd, nd]."""
+    ch = chi(wavelet, param, 1e-17)
+    kmax = max(nd, int(np.ceil(ch / h))) + 40
+    k = np.arange(-kmax, kmax + 1)
+    smp = psi(wavelet, param, h * k)
+    d = _solve_b3(smp)
+    mid = kmax
+    return d[mid - nd: mid + nd + 1]
+
+
+def spline_approx(d, h: float, x) -> np.ndarray:
+    """psi_h(x) = sum_k d[k] beta3(x/h - k), d indexed from -nd."""
+    d = np.asarray(d)
+    nd = (d.size - 1) // 2
+    x = np.asarray(x, dtype=np.float64)
+    y = x / h
+    out = np.zeros(x.shape, dtype=d.dtype)
+    k0 = np.floor(y).astype(np.int64) - 1
+    for j in range(4):
+        k = k0 + j
+        ok = (k >= -nd) & (k <= nd)
+        kk = np.clip(k, -nd, nd)
+        out = out + np.where(ok, d[kk + nd] * beta3(y - k), 0.0)
+    return out
+
+
+def ae_m(psi_fn, chi_: float, h: float, npts: int = 20001) -> float:
+    """AE_M(h) of Eq. m02cwt_error: sum_n |psi(x_n) - psi_h(x_n)| /
+    sum_n |psi(x_n)| on npts uniform points of [-chi, chi]; psi_h uses the
+    exact (untruncated) spline interpolation of psi(h k)."""
+    kmax = int(np.ceil(chi_ / h)) + 40
+    k = np.arange(-kmax, kmax + 1)
+    d = _solve_b3(psi_fn(h * k))
+    x = np.linspace(-chi_, chi_, npts)
+    approx = spline_approx(d, h, x)
+    ex = psi_fn(x)
+    return float(np.sum(np.abs(ex - approx)) / np.sum(np.abs(ex)))
+
+
+def h_star(psi_fn, chi_: float, target: float = 5e-4) -> float:
+    """Largest-error-below-target step: scan h upward in 0.005 steps until
+    AE_M exceeds the target, then bisect the bracketing interval."""
+    lo = 0.005
+    h = lo
+    while ae_m(psi_fn, chi_, h) < target:
+        lo = h
+        h += 0.005
+        if h > 3.0:
+            raise RuntimeError("AE_M never reaches the target")
+    hi = h
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if ae_m(psi_fn, chi_, mid) < target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+SPLINE_CHI_REL = 1e-14   # Table 2 truncates the non-compact wavelets near 1e-14
+
+
+def spline_h_star(wavelet: str, param: float | None = None) -> float:
+    """h* of a supported wavelet: AE_M = 5e-4 on [-chi, chi], chi the
+    radius where |psi| < 1e-14 max|psi|."""
+    ch = chi(wavelet, param, SPLINE_CHI_REL)
+    return h_star(lambda x: psi(wavelet, param, x), ch)
+
+
+def spline_delta(hstar: float, s: float) -> int:
+    """Integer sample spacing of the wavelet knots at scale s."""
+    return max(1, int(np.floor(hstar * s)))
+
+
+def spline_target(f, boundary: str, wavelet: str, s: float, delta: int, x,
+                  param: float | None = None, nthreads: int = 0) -> np.ndarray:
+    """Exact CWT of the spline interpolant f_c with the spline wavelet
+    psi_h, h = delta/s, at integer positions x (array)."""
+    h = delta / s
+    ch = chi(wavelet, param, 1e-17)
+    nd = int(np.ceil(ch / h - 2.0)) + 2
+    d = wavelet_spline_coeffs(wavelet, param, h, nd)
+    w = spline_target_d(f, boundary, d, delta, s, x, nthreads)
+    return w if is_complex(wavelet) else w.real
+
+
+def spline_target_d(f, boundary: str, d, delta: int, s: float, x,
+                    nthreads: int = 0) -> np.ndarray:
+    """Same as ``spline_target`` with explicit wavelet coefficients d[k],
+    k in [-nd, nd] (complex128 result)."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.size
+    d = np.asarray(d, dtype=np.complex128)
+    nd = (d.size - 1) // 2
+    half = (nd + 2) * delta + 4
+    if boundary == "periodic":
+        c, _ = spline_coeffs(f, "periodic")
+        reps = int(np.ceil(half / n)) + 1
+        cext = np.tile(c, 2 * reps + 1)
+        c0 = -reps * n
+    else:
+        cext, c0 = spline_coeffs(f, "zero")
+    cext = np.ascontiguousarray(cext, dtype=np.float64)
+    dr = np.ascontiguousarray(d.real)
+    di = np.ascontiguousarray(d.imag)
+    xs = np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+    re = np.empty(xs.size)
+    im = np.empty(xs.size)
+    _load().oracle_spline_target(_dp(cext), c0, cext.size, _dp(dr), _dp(di), nd, int(delta),
+                                 float(s), xs.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                                 xs.size, _dp(re), _dp(im), nthreads)
+    return re + 1j * im

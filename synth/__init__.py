@@ -1,0 +1,155 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module only draws inputs.  It holds none of the transform's arithmetic:
+no wavelet, no spectrum of a wavelet, no scale-dependent step.  Both the HIP
+path and the CPU oracle consume what it returns.
+
+Workloads (all seeded with numpy's PCG64):
+
+* ``tones_noise`` -- a periodic three-tone signal plus white noise.  The
+  paper's own accuracy tests use a periodic sum of tones (Sec. 5, Eq.
+  signal_f1); the tone frequencies here are 40, 300 and 900 cycles per 4096
+  samples, scaled with the length.
+* ``lognormal_field`` -- a non-periodic 1D density-like field
+  delta = exp(g - sigma^2/2) - 1 with g a Gaussian random field of power
+  spectrum P(k) ~ k^-1.5 exp(-(k/k_c)^2).  It stands in for the 1D density
+  fields of Sec. 6 (Eq. nonlinear_dens), which are also synthetic; the
+  paper's own field parameters are not given in the text.
+* ``log_scales`` -- scales a * (b/a)^(j/(S-1)), j = 0..S-1, both ends
+  included (the paper discretises scales evenly in log, Sec. 3.1).
+* ``batch_specs`` / ``request_stream`` -- many uneven instances and a
+  Poisson request stream for the batched and served forms.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+SEED_SMALL = 20230209
+SEED_FIELD_1M = 20230210
+SEED_FIELD_4M = 20230211
+SEED_BATCH = 20230212
+SEED_SERVE = 20230213
+
+
+def tones_noise(n: int, seed: int = SEED_SMALL, noise: float = 0.1) -> np.ndarray:
+    """sin(2pi*40x) + 0.5 sin(2pi*300x) + 0.3 sin(2pi*900x) + N(0, noise^2),
+    x = i/n, with the tone counts scaled by n/4096 (rounded)."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(n, dtype=np.float64) / n
+    k = [max(1, round(c * n / 4096)) for c in (40, 300, 900)]
+    f = (np.sin(2 * np.pi * k[0] * x) + 0.5 * np.sin(2 * np.pi * k[1] * x)
+         + 0.3 * np.sin(2 * np.pi * k[2] * x))
+    return f + noise * rng.standard_normal(n)
+
+
+def lognormal_field(n: int, seed: int = SEED_FIELD_1M, sigma_g: float = 1.0,
+                    slope: float = -1.5, kc_per_n: float | None = None) -> np.ndarray:
+    """Lognormal field on n samples.
+
+    g is drawn on a periodic box of 2n samples (so the kept half is not
+    periodic), with integer box wavenumbers k, P(k) = k^slope exp(-(k/k_c)^2),
+    k_c = 2 * kc_per_n (default kc_per_n = n/8 cycles per n samples), the k=0
+    mode set to zero; g is standardised to mean 0 and std sigma_g and
+    delta = exp(g - sigma_g^2/2) - 1."""
+    rng = np.random.default_rng(seed)
+    box = 2 * n
+    if kc_per_n is None:
+        kc_per_n = n / 8
+    kc = 2.0 * kc_per_n
+    k = np.arange(box // 2 + 1, dtype=np.float64)
+    p = np.zeros_like(k)
+    p[1:] = k[1:] ** slope * np.exp(-(k[1:] / kc) ** 2)
+    modes = (rng.standard_normal(k.size) + 1j * rng.standard_normal(k.size)) * np.sqrt(p / 2)
+    modes[0] = 0.0
+    modes[-1] = modes[-1].real
+    g = np.fft.irfft(modes, n=box)[:n]
+    g = (g - g.mean()) / g.std() * sigma_g
+    return np.exp(g - 0.5 * sigma_g ** 2) - 1.0
+
+
+def log_scales(a: float, b: float, s: int) -> np.ndarray:
+    if s == 1:
+        return np.array([a], dtype=np.float64)
+    j = np.arange(s, dtype=np.float64)
+    return a * (b / a) ** (j / (s - 1))
+
+
+@dataclass
+class Instance:
+    """One transform request: signal, boundary, wavelet and scales."""
+    signal: np.ndarray
+    boundary: str          # "periodic" | "zero"
+    wavelet: str           # "morlet" | "mexhat" | "dog"
+    param: float           # omega0 for Morlet, m for DOG (2 for the Mexican hat)
+    scales: np.ndarray
+    arrival: float = 0.0   # seconds (served form only)
+
+    @property
+    def n(self) -> int:
+        return int(self.signal.size)
+
+    @property
+    def coefficients(self) -> int:
+        return int(self.signal.size) * int(self.scales.size)
+
+
+def _scales_for(n: int, s: int) -> np.ndarray:
+    return log_scales(2.0, float(min(n / 8.0, 2.0 ** 16)), s)
+
+
+def batch_specs(count: int = 4096, seed: int = SEED_BATCH, log2_lo: float = 10.0,
+                log2_hi: float = 16.0, s_lo: int = 16, s_hi: int = 96) -> list[Instance]:
+    """Uneven instances: lengths log-uniform in [2^log2_lo, 2^log2_hi], scale
+    counts uniform in [s_lo, s_hi], half periodic tones+noise and half
+    zero-boundary lognormal fields, Morlet(6) / Mexican hat 50/50."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(round(2.0 ** rng.uniform(log2_lo, log2_hi)))
+        s = int(rng.integers(s_lo, s_hi + 1))
+        sub = int(rng.integers(0, 2 ** 31))
+        if i % 2 == 0:
+            sig, bc = tones_noise(n, seed=sub), "periodic"
+        else:
+            sig, bc = lognormal_field(n, seed=sub), "zero"
+        if rng.uniform() < 0.5:
+            wav, par = "morlet", 6.0
+        else:
+            wav, par = "mexhat", 2.0
+        out.append(Instance(sig, bc, wav, par, _scales_for(n, s)))
+    return out
+
+
+def request_stream(count: int, rate_hz: float, seed: int = SEED_SERVE,
+                   log2_lo: float = 12.0, log2_hi: float = 22.0, s_lo: int = 32,
+                   s_hi: int = 256) -> list[Instance]:
+    """Poisson arrivals at rate_hz; lengths log-uniform in [2^12, 2^22],
+    32-256 scales, wavelet uniform over Morlet(6) / Mexican hat / DOG(4),
+    boundary periodic or zero 50/50."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(count):
+        t += rng.exponential(1.0 / rate_hz)
+        n = int(round(2.0 ** rng.uniform(log2_lo, log2_hi)))
+        s = int(rng.integers(s_lo, s_hi + 1))
+        sub = int(rng.integers(0, 2 ** 31))
+        w = int(rng.integers(0, 3))
+        wav, par = [("morlet", 6.0), ("mexhat", 2.0), ("dog", 4.0)][w]
+        if rng.uniform() < 0.5:
+            sig, bc = tones_noise(n, seed=sub), "periodic"
+        else:
+            sig, bc = lognormal_field(n, seed=sub), "zero"
+        out.append(Instance(sig, bc, wav, par, _scales_for(n, s), arrival=t))
+    return out
+
+
+def mean_request_coefficients(log2_lo: float = 12.0, log2_hi: float = 22.0,
+                              s_lo: int = 32, s_hi: int = 256) -> float:
+    """Expected N*S of ``request_stream`` (N log-uniform, S uniform)."""
+    a, b = log2_lo * math.log(2), log2_hi * math.log(2)
+    en = (math.exp(b) - math.exp(a)) / (b - a)
+    return en * 0.5 * (s_lo + s_hi)

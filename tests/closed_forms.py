@@ -1,0 +1,137 @@
+"""Closed forms used by the tests to pin the oracle and the HIP path.
+
+Everything here is derived from the wavelet definitions by hand (Fourier
+transforms, Gaussian integrals) and written independently of both the oracle
+(which works in the time domain) and the HIP library.
+
+FT convention: psi^(w) = int psi(x) e^{-iwx} dx.  For the 1/s correlation
+W(s,b) = (1/s) sum_t f[b+t] conj(psi(t/s)), a tone f[n] = e^{i w1 n} gives
+W = e^{i w1 b} conj(Psi_s(w1)), Psi_s(w) = sum_q psi^(s (w + 2 pi q)) by the
+Poisson summation formula.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def psi_hat(wavelet: str, param: float | None, w) -> np.ndarray:
+    """Analytic Fourier transform of the unit-norm mother wavelets."""
+    w = np.asarray(w, dtype=np.float64)
+    wl = wavelet.lower()
+    if wl == "morlet":
+        w0 = 6.0 if param is None else float(param)
+        c = math.pi ** -0.25 / math.sqrt(1 + math.exp(-w0 * w0) - 2 * math.exp(-0.75 * w0 * w0))
+        return c * math.sqrt(2 * math.pi) * (np.exp(-0.5 * (w - w0) ** 2)
+                                             - math.exp(-0.5 * w0 * w0) * np.exp(-0.5 * w * w))
+    m = 2 if wl in ("mexhat", "mexican_hat") else int(param)
+    # DOG(m) = (-1)^{m+1} Gamma(m+1/2)^{-1/2} d^m/dx^m e^{-x^2/2}
+    return ((-1) ** (m + 1) / math.sqrt(math.gamma(m + 0.5)) * (1j * w) ** m
+            * math.sqrt(2 * math.pi) * np.exp(-0.5 * w * w))
+
+
+def psi_aliased(wavelet: str, param: float | None, s: float, w, q: int = 6) -> np.ndarray:
+    """Psi_s(w) = sum_{|k|<=q} psi^(s (w + 2 pi k)): the DTFT of the sampled,
+    1/s-scaled wavelet."""
+    w = np.asarray(w, dtype=np.float64)
+    acc = np.zeros(w.shape, dtype=np.complex128)
+    for k in range(-q, q + 1):
+        acc = acc + psi_hat(wavelet, param, s * (w + 2 * np.pi * k))
+    return acc
+
+
+def tone_cwt(wavelet, param, s, n, k, kind="cos"):
+    """Periodic CWT of cos(2 pi k t/n) or sin(2 pi k t/n), t = 0..n-1."""
+    w1 = 2 * np.pi * k / n
+    b = np.arange(n)
+    ep = np.exp(1j * w1 * b) * np.conj(psi_aliased(wavelet, param, s, w1))
+    em = np.exp(-1j * w1 * b) * np.conj(psi_aliased(wavelet, param, s, -w1))
+    if kind == "cos":
+        return 0.5 * (ep + em)
+    return (ep - em) / 2j
+
+
+def gaussian_cwt(wavelet, param, s, b, x0, sigma, images=0):
+    """Continuous CWT (1/s) int f(x) conj(psi((x-b)/s)) dx of
+    f = exp(-(x-x0)^2 / (2 sigma^2)).  With a^2 = sigma^2 + s^2, tau = b - x0:
+
+    DOG(m):  (-1)^{m+1} Gamma(m+1/2)^{-1/2} sqrt(2 pi) sigma s^m a^{-m-1}
+             He_m(tau/a) e^{-tau^2/(2a^2)}
+    Morlet:  C sqrt(2 pi) sigma/a e^{-tau^2/(2a^2)}
+             [exp(i w0 tau s/a^2 - w0^2 sigma^2/(2 a^2)) - e^{-w0^2/2}]
+
+    With images=q > 0 (Morlet only) the Poisson images |k| <= q are added, so
+    the result is the unit-step sum over integer x rather than the integral.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    a2 = sigma * sigma + s * s
+    a = math.sqrt(a2)
+    tau = b - x0
+    g = np.exp(-tau * tau / (2 * a2))
+    wl = wavelet.lower()
+    if wl == "morlet":
+        w0 = 6.0 if param is None else float(param)
+        c = math.pi ** -0.25 / math.sqrt(1 + math.exp(-w0 * w0) - 2 * math.exp(-0.75 * w0 * w0))
+
+        def gauss(alpha):
+            # (1/s) int exp(-(u+tau)^2/(2 sigma^2) - u^2/(2 s^2) - i alpha u) du
+            return math.sqrt(2 * math.pi) * sigma / a * np.exp(
+                -tau * tau / (2 * a2) + 1j * alpha * tau * s * s / a2
+                - alpha * alpha * sigma * sigma * s * s / (2 * a2))
+        acc = 0
+        for q in range(-images, images + 1):
+            # image q of the Poisson sum (positions b are integers)
+            acc = acc + gauss(w0 / s + 2 * np.pi * q) - math.exp(-0.5 * w0 * w0) * gauss(2 * np.pi * q)
+        return c * acc
+    m = 2 if wl in ("mexhat", "mexican_hat") else int(param)
+    z = tau / a
+    he = {1: z, 2: z * z - 1, 3: z ** 3 - 3 * z, 4: z ** 4 - 6 * z * z + 3}[m]
+    return ((-1) ** (m + 1) / math.sqrt(math.gamma(m + 0.5)) * math.sqrt(2 * math.pi) * sigma
+            * s ** m * a ** (-m - 1) * he * g)
+
+
+# Wavelets of the paper's Table 2 (used only to pin the oracle's helpers).
+
+def psi_gdw(x):
+    x = np.asarray(x, dtype=np.float64)
+    return (18 * math.pi) ** -0.25 * (2 - x * x) * np.exp(-x * x / 4)
+
+
+def psi_cwgdw(x):
+    x = np.asarray(x, dtype=np.float64)
+    cn = math.sqrt(8 / (1 + 5 * math.e)) / math.pi ** 0.25
+    return cn * ((1 - x * x) * np.cos(x) - x * np.sin(x)) * np.exp((1 - x * x) / 2)
+
+
+def psi_mw(x):
+    x = np.asarray(x, dtype=np.float64)
+    cn = math.exp(8) / math.sqrt(1 - 2 * math.exp(4) + math.exp(16)) / math.pi ** 0.25
+    return cn * (np.exp(-4j * x) - math.exp(-8)) * np.exp(-x * x / 2)
+
+
+def beta_n(n: int, x):
+    """Centered B-spline of degree n by the explicit truncated-power formula
+    beta^n(x) = (1/n!) sum_k (-1)^k C(n+1,k) (x + (n+1)/2 - k)_+^n.
+    Evaluated at -|x| (the B-spline is even), where only the first half of
+    the terms is active, and set to 0 outside the support; this keeps the
+    cancellation in the alternating sum small."""
+    x = -np.abs(np.asarray(x, dtype=np.float64))
+    out = np.zeros_like(x)
+    for k in range(n + 2):
+        t = x + (n + 1) / 2 - k
+        out += (-1) ** k * math.comb(n + 1, k) * np.where(t > 0, t, 0.0) ** n
+    return np.where(x > -(n + 1) / 2, out / math.factorial(n), 0.0)
+
+
+def numeric_ft(psi_fn, w, half=14.0, step=1.0 / 512):
+    """psi^(w) by the trapezoid rule on [-half, half] (spectrally accurate
+    for Gaussian-decaying wavelets)."""
+    x = np.arange(-half, half + step / 2, step)
+    px = psi_fn(x)
+    w = np.atleast_1d(np.asarray(w, dtype=np.float64))
+    out = np.empty(w.size, dtype=np.complex128)
+    for i0 in range(0, w.size, 256):
+        ww = w[i0:i0 + 256]
+        out[i0:i0 + 256] = (np.exp(-1j * np.outer(ww, x)) @ px) * step
+    return out
