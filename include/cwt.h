@@ -1,0 +1,201 @@
+/*
+ * cwt.h -- C ABI of the MI355X (gfx950) multi-scale 1D continuous wavelet
+ * transform library (libcwt.so).
+ *
+ * The transform (Sec. 2, Eq. CWT, in the 1/s correlation form) is
+ *
+ *     W(s, b) = (1/s) * integral f(x) conj(psi((x - b)/s)) dx,
+ *
+ * evaluated on the samples as the unit-step sum (Sec. 3, Eq. discreteCWT):
+ *
+ *     W[j, b] = (1/s_j) * sum_t f_ext[b + t] * conj(psi(t / s_j)),
+ *
+ * b = 0..N-1, with f_ext the periodic extension (CWT_PERIODIC) or the zero
+ * extension (CWT_ZERO) of the signal.  Scales s_j and positions b are in
+ * samples.  Two methods are offered:
+ *
+ *   CWT_METHOD_FFT    -- FFTCWT (Sec. 3.1, Eqs. FT_signal and
+ *                        discrete_CWT_conv): one FFT of the signal, then per
+ *                        scale a spectral multiply by the conjugate of the
+ *                        sampled wavelet's spectrum and an inverse FFT.  The
+ *                        result equals the sum above up to rounding and the
+ *                        truncation level of the plan's precision.
+ *   CWT_METHOD_SPLINE -- the O(N)-per-scale spline method of Sec. 3.3 (Eqs.
+ *                        beta3_wavelet_approx_m02, beta3_signal, m02_cwt,
+ *                        cumsum4_coeffs): the exact CWT of the cubic-spline
+ *                        interpolant of the samples with the cubic-spline
+ *                        approximation of the wavelet at step h_s = delta_s/s,
+ *                        delta_s = max(1, floor(h* s)), h* the step where the
+ *                        approximation error of Eq. m02cwt_error is 5e-4.
+ *
+ * Wavelets (unit L2 norm, psi^(w) = int psi(x) e^{-iwx} dx):
+ *   CWT_MORLET(w0): C (e^{i w0 x} - e^{-w0^2/2}) e^{-x^2/2} (complex output;
+ *                   the corrected Morlet wavelet of Table 2, conjugated)
+ *   CWT_MEXHAT:     DOG(2) (real output)
+ *   CWT_DOG(m):     (-1)^{m+1} Gamma(m+1/2)^{-1/2} d^m/dx^m e^{-x^2/2} (real)
+ *
+ * Conventions for every entry point:
+ *   - Return 0 on success or a negative CWT_E* code; no C++ exception ever
+ *     crosses this interface.  cwt_last_error() returns a thread-local text
+ *     for the last failure of the calling thread.
+ *   - Device pointers are HIP device allocations on the current device.
+ *     The caller owns signal, output and workspace memory; the library owns
+ *     only the plan's small constant tables (allocated by cwt_plan, freed by
+ *     cwt_destroy).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Execution is
+ *     asynchronous on that stream; buffers must stay alive until the stream
+ *     has finished the work.
+ *   - A plan is immutable after creation and may be used concurrently from
+ *     several streams, provided each concurrent call gets its own workspace.
+ */
+#ifndef CWT_H
+#define CWT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CWT_OK 0
+#define CWT_EINVAL (-1)       /* invalid argument */
+#define CWT_EUNSUPPORTED (-2) /* valid but outside this library's limits */
+#define CWT_ENOMEM (-3)       /* host or device allocation failed */
+#define CWT_EDEVICE (-4)      /* HIP runtime error */
+
+#define CWT_PERIODIC 0
+#define CWT_ZERO 1
+
+#define CWT_MORLET 0
+#define CWT_MEXHAT 1
+#define CWT_DOG 2
+
+#define CWT_FP64 0 /* FP64 signal, FP64 output, FP64 arithmetic */
+#define CWT_FP32 1 /* FP32 signal and output; FP32 inverse FFTs and products;
+                      FP64 forward transform of the whole signal, FP64
+                      twiddles and wavelet spectra, FP64 spline sums */
+
+#define CWT_METHOD_FFT 0
+#define CWT_METHOD_SPLINE 1
+
+typedef struct cwt_plan_s *cwt_plan_t;
+
+typedef struct {
+    int32_t kind;  /* CWT_MORLET, CWT_MEXHAT or CWT_DOG */
+    double param;  /* omega0 > 0 for Morlet; integer order m >= 1 for DOG;
+                      ignored for the Mexican hat */
+} cwt_wavelet;
+
+typedef struct {
+    int32_t precision; /* CWT_FP64 (default) or CWT_FP32 */
+    int32_t method;    /* CWT_METHOD_FFT (default) or CWT_METHOD_SPLINE */
+    int64_t fft_len;   /* 0: the library picks the length of the whole-signal
+                          FFT; otherwise a length >= the minimum the plan
+                          needs, of the form 2^a * {1,3,5,9}, 2^a >= 64 */
+    int32_t host_only; /* 1: build the plan on the host only (no device
+                          allocation, no device needed); it can be queried
+                          but cwt_exec rejects it with CWT_EINVAL */
+    int32_t reserved[7];
+} cwt_opts;
+
+/*
+ * cwt_plan -- build a plan for signals of N samples and the S scales in
+ * `scales` (host array of S doubles, copied).  Output row j belongs to
+ * scales[j].  `opts` may be NULL (FP64, FFT method).
+ * Errors: CWT_EINVAL for N < 2, S < 1, a scale that is not finite and > 0,
+ * omega0 <= 0 or not finite, a DOG order that is not an integer in [1, 16],
+ * an unknown kind/boundary/precision/method, out == NULL or scales == NULL;
+ * CWT_EUNSUPPORTED for N > 2^26, S > 65536, an fft_len that is too short or
+ * not of the supported form, or (spline method) a scale below 1;
+ * CWT_ENOMEM / CWT_EDEVICE on allocation or HIP failures.
+ * On failure *out is set to NULL.
+ */
+int cwt_plan(cwt_plan_t *out, int64_t N, int32_t boundary, cwt_wavelet wavelet,
+             const double *scales, int32_t S, const cwt_opts *opts);
+
+/* Destroys a plan (NULL is accepted).  The caller must ensure no stream is
+ * still using it. */
+int cwt_destroy(cwt_plan_t plan);
+
+/* 1 if the output is complex (Morlet), 0 if real; negative on error. */
+int cwt_out_is_complex(cwt_plan_t plan);
+
+/* Number of output values S*N (complex values count once); -1 on error. */
+int64_t cwt_out_elems(cwt_plan_t plan);
+
+/* Bytes of one output element: 16/8 (complex FP64/FP32) or 8/4 (real). */
+int32_t cwt_out_elem_bytes(cwt_plan_t plan);
+
+/* Bytes of device workspace cwt_exec needs (0 is possible). */
+size_t cwt_workspace_bytes(cwt_plan_t plan);
+
+/* Device bytes one execution holds: signal + output + workspace + the
+ * plan's own tables.  Used for admission by device-memory footprint. */
+size_t cwt_footprint_bytes(cwt_plan_t plan);
+
+/*
+ * cwt_exec -- enqueue the transform on `stream`.
+ *   signal:    device, N values, double (CWT_FP64) or float (CWT_FP32).
+ *   out:       device, [S][N] row-major; complex values interleaved
+ *              (re, im) for Morlet; element type double or float as above.
+ *   workspace: device, at least cwt_workspace_bytes(plan) bytes, 256-byte
+ *              aligned; may be NULL when that size is 0.
+ * Errors: CWT_EINVAL for a NULL plan/signal/out, a NULL workspace when one is
+ * needed, or a pointer not aligned to its element size; CWT_EDEVICE when a
+ * launch fails.  NaN/Inf in the signal propagate; they are not checked.
+ */
+int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace,
+             void *stream);
+
+/*
+ * cwt_exec_batch -- transform n independent signals, each with its own plan
+ * (lengths, scales, wavelets, boundaries and precisions may differ), in one
+ * enqueue on `stream`.  signals[i], outs[i] as for cwt_exec with plans[i].
+ * workspace: at least cwt_batch_workspace_bytes(plans, n) bytes.  Every
+ * result is bit-identical to cwt_exec of the same plan and signal.
+ */
+size_t cwt_batch_workspace_bytes(const cwt_plan_t *plans, int32_t n);
+int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals,
+                   void *const *outs, int32_t n, void *workspace, void *stream);
+
+/*
+ * Plan queries used by tests and schedulers.
+ *   cwt_plan_fft_len:      length of the whole-signal FFT (0 if the plan
+ *                          never needs it).
+ *   cwt_plan_spline_delta: fills delta[j] (S entries) with the integer knot
+ *                          spacing delta_j of the spline method (0 for plans
+ *                          of the FFT method).
+ *   cwt_plan_spline_hstar: h* of the plan's wavelet (0 for the FFT method).
+ *   cwt_plan_scale_path:   fills path[j] with how scale j is computed:
+ *                          0 = segmented FFT (overlap-save), 1 = band-limited
+ *                          inverse of the whole-signal spectrum, 2 = spline.
+ */
+int64_t cwt_plan_fft_len(cwt_plan_t plan);
+int cwt_plan_spline_delta(cwt_plan_t plan, int32_t *delta);
+double cwt_plan_spline_hstar(cwt_plan_t plan);
+int cwt_plan_scale_path(cwt_plan_t plan, int32_t *path);
+
+/*
+ * Launch timing for benchmarks.  While enabled on a plan, every cwt_exec of
+ * that plan brackets each kernel launch with HIP events recorded on the
+ * launch stream.  cwt_plan_timing_read waits for those events and reports,
+ * per kernel (aggregated over all recorded launches): a name (at most 63
+ * chars + NUL, in names[i*64]), the number of launches, the summed elapsed
+ * milliseconds and the algorithmic bytes per launch (signal, whole-signal
+ * spectrum and output bytes the launch must read or write at least once).
+ * It returns the number of kernels (at most max_kernels are written) and
+ * clears the records.  Not thread-safe with respect to concurrent cwt_exec
+ * calls on the same plan; enabling costs two event records per launch.
+ */
+int cwt_plan_timing_enable(cwt_plan_t plan, int32_t on);
+int cwt_plan_timing_read(cwt_plan_t plan, int32_t max_kernels, char *names,
+                         int64_t *launches, double *ms, double *bytes_per_launch);
+
+/* Thread-local text describing the last error of this thread ("" if none). */
+const char *cwt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CWT_H */

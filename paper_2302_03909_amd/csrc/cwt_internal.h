@@ -1,0 +1,143 @@
+// cwt_internal.h -- plan layout and kernel launchers shared by the host
+// plan code (cwt_plan.cpp) and the device code (cwt_fft.hip, cwt_spline.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace cwt {
+
+enum LoadMode : int32_t {
+    LOAD_ZERO = 0,      // x[n] = f[n] for n < N, 0 beyond (zero boundary)
+    LOAD_PERIODIC = 1,  // x[n] = f[n mod N] (FFT length == N)
+    LOAD_WRAP = 2,      // x[n] = f[n mod N] for n < N + T, f[(n - M) mod N] for
+                        // n >= M - T, 0 between (periodic, FFT length != N)
+};
+
+enum ScalePath : int32_t { PATH_LOCAL = 0, PATH_COLUMN = 1, PATH_SPLINE = 2 };
+
+// One overlap-save group: scales that share the segment FFT length L and the
+// halo Tg; V = L - 2 Tg outputs per segment.
+struct LocalGroup {
+    int32_t L = 0;
+    int64_t Tg = 0, V = 0, nseg = 0;
+    std::vector<int32_t> scales;  // scale indices
+    int64_t tab_off = 0;          // offset (elements) into the plan's spectrum table
+    int32_t *d_scales = nullptr;  // device copy of `scales`
+};
+
+// Work item of the band-limited inverse kernel: G consecutive columns of one
+// scale (or of a pair of scales sharing the transform, real wavelets).
+struct ColumnDesc {
+    int32_t sa, sb;      // output rows (sb = -1: none)
+    int32_t pad0, pad1;
+    int64_t r0;          // first column
+    int64_t mlo, B;      // band: signed bins [mlo, mlo + B)
+    int64_t Q;           // number of columns M / P
+    int64_t taba, tabb;  // offsets of the spectrum samples of sa / sb
+};
+
+struct ColumnLaunch {
+    int32_t P = 0, G = 0;
+    std::vector<ColumnDesc> items;
+    ColumnDesc *d_items = nullptr;
+};
+
+// Spline method, one work item per (scale, tile).
+struct SplineScale {
+    int32_t delta = 0, nd = 0;
+    int64_t dtab_off = 0;  // offset (complex FP64 elements) of d_s
+    double kscale = 0.0;   // 1 / (s delta^3)
+};
+
+struct Plan {
+    // problem
+    int64_t N = 0;
+    int32_t boundary = 0, kind = 0, precision = 0, method = 0;
+    bool host_only = false;
+    double param = 0.0;
+    int32_t S = 0;
+    std::vector<double> scales;
+    bool cplx_out = false;
+    int32_t cph = 0;  // conj(phase of psi^) = i^cph
+    double rel = 0.0, chi = 0.0;
+    std::vector<int64_t> T;
+    std::vector<int32_t> path;
+
+    // FFT method
+    int64_t M = 0;  // whole-signal FFT length (0: not needed)
+    int32_t M1 = 0, M2 = 0;
+    int32_t load_mode = 0;
+    int64_t Twrap = 0;
+    std::vector<LocalGroup> groups;
+    std::vector<ColumnLaunch> columns;
+    bool pair_real = false;
+
+    // spline method
+    double hstar = 0.0;
+    std::vector<SplineScale> spl;
+    std::vector<int32_t> spl_delta;
+
+    // device tables (owned)
+    void *d_tab = nullptr;  // spectrum samples, plan precision (real)
+    int64_t tab_elems = 0;
+    void *d_tw_all = nullptr;  // all twiddle tables (one allocation); offsets in bytes
+    std::vector<std::pair<int32_t, int64_t>> tw_off;    // (P, byte offset) plan precision
+    std::vector<std::pair<int32_t, int64_t>> tw64_off;  // (P, byte offset) FP64
+    int64_t twM_hi_off = -1, twM_lo_off = -1;           // plan precision, bytes
+    int64_t twM64_hi_off = -1, twM64_lo_off = -1;       // FP64, bytes
+    void *d_dtab = nullptr;                             // spline d_s (complex FP64)
+    std::vector<void *> d_extra;                        // other owned allocations
+
+    // launch timing (benchmarks only)
+    struct TimingRec {
+        std::string name;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    bool timing = false;
+    std::vector<TimingRec> timing_recs;
+    std::vector<hipEvent_t> event_pool;
+
+    size_t ws_bytes = 0;
+    size_t ws_F_off = 0, ws_Y_off = 0;  // workspace layout (FFT method)
+    size_t ws_c_off = 0, ws_e_off = 0;  // workspace layout (spline method)
+    size_t table_bytes = 0;
+};
+
+// names of the kernel instantiations a launch uses (timing labels)
+std::string local_kernel_name(const Plan &p, const LocalGroup &g);
+std::string column_kernel_name(const Plan &p, const ColumnLaunch &c);
+
+// ---- launchers (device code) -------------------------------------------------
+hipError_t launch_forward(const Plan &p, const void *signal, void *ws, hipStream_t st);
+hipError_t launch_local(const Plan &p, const LocalGroup &g, const void *signal, void *out,
+                        hipStream_t st);
+hipError_t launch_column(const Plan &p, const ColumnLaunch &c, const void *ws, void *out,
+                         hipStream_t st);
+hipError_t launch_spline(const Plan &p, const void *signal, void *out, void *ws, hipStream_t st);
+
+// supported sizes
+bool local_size_ok(int L, int precision);
+bool column_size_ok(int P, int precision);
+bool fwd_size_ok(int P);
+int column_g(int P, int precision);
+int column_nt(int P, int precision);
+
+// twiddle table e^{+2 pi i j/P}: forward_list selects the FP64 tables of the
+// whole-signal transform, otherwise the plan-precision tables
+template <typename T> inline const T *tw_ptr(const Plan &p, int P, bool forward_list) {
+    const auto &v = forward_list ? p.tw64_off : p.tw_off;
+    for (auto &e : v)
+        if (e.first == P) return reinterpret_cast<const T *>(static_cast<const char *>(p.d_tw_all) + e.second);
+    return nullptr;
+}
+
+template <typename T> inline const T *tw_at(const Plan &p, int64_t byte_off) {
+    return byte_off < 0 ? nullptr
+                        : reinterpret_cast<const T *>(static_cast<const char *>(p.d_tw_all) + byte_off);
+}
+
+}  // namespace cwt

@@ -1,0 +1,793 @@
+// cwt_plan.cpp -- plan construction and the C ABI (include/cwt.h).
+//
+// Host math is FP64 throughout: wavelet spectra, truncation radii, band
+// edges, twiddle tables and the spline parameters are computed here once per
+// plan and uploaded as small device tables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/cwt.h"
+#include "cwt_internal.h"
+
+namespace cwt {
+
+static thread_local std::string g_err;
+
+struct Failure {
+    int code;
+    std::string msg;
+};
+[[noreturn]] static void fail(int code, const std::string &msg) { throw Failure{code, msg}; }
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) ::cwt::fail(CWT_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Wavelets (unit L2 norm; psi^(u) = int psi(x) e^{-iux} dx = i^{-cph}... see
+// amp/cph below).  psi^(u) = phase * amp(u) with amp real; conj(phase) = i^cph.
+
+struct Wavelet {
+    int kind = 0;   // CWT_MORLET, CWT_MEXHAT, CWT_DOG
+    double w0 = 6.0;
+    int m = 2;
+    double cmor = 0.0, kappa = 0.0, gnorm = 0.0;
+
+    void init() {
+        if (kind == CWT_MORLET) {
+            kappa = std::exp(-0.5 * w0 * w0);
+            cmor = std::pow(M_PI, -0.25) / std::sqrt(1.0 + std::exp(-w0 * w0) - 2.0 * std::exp(-0.75 * w0 * w0));
+        } else {
+            gnorm = 1.0 / std::sqrt(std::tgamma(m + 0.5));
+        }
+    }
+    bool complex_out() const { return kind == CWT_MORLET; }
+    // |psi(x)| in the time domain
+    double abs_time(double x) const {
+        double g = std::exp(-0.5 * x * x);
+        if (kind == CWT_MORLET)
+            return cmor * g * std::sqrt(std::max(0.0, 1.0 - 2.0 * kappa * std::cos(w0 * x) + kappa * kappa));
+        // probabilists' Hermite polynomial He_m
+        double hm1 = 1.0, h = x;
+        for (int n = 1; n < m; ++n) {
+            double hn = x * h - n * hm1;
+            hm1 = h;
+            h = hn;
+        }
+        return std::fabs(h) * g * gnorm;
+    }
+    // real amplitude of the spectrum
+    double amp(double u) const {
+        if (kind == CWT_MORLET)
+            return cmor * std::sqrt(2.0 * M_PI) * (std::exp(-0.5 * (u - w0) * (u - w0)) - kappa * std::exp(-0.5 * u * u));
+        return std::pow(u, m) * std::sqrt(2.0 * M_PI) * std::exp(-0.5 * u * u) * gnorm;
+    }
+    // DOG(m): psi^ = (-1)^{m+1} i^m amp  ->  conj(phase) = i^{(m+2) mod 4}
+    int cph() const { return kind == CWT_MORLET ? 0 : (m + 2) % 4; }
+};
+
+// radius beyond which |psi| < rel * max|psi|
+static double time_radius(const Wavelet &w, double rel) {
+    const double step = 1.0 / 1024.0;
+    double mx = 0.0;
+    for (int i = 0; i <= 64 * 1024; ++i) mx = std::max(mx, w.abs_time(i * step));
+    double last = 0.0;
+    for (int i = 0; i <= 64 * 1024; ++i)
+        if (w.abs_time(i * step) >= rel * mx) last = i * step;
+    return last + step;
+}
+
+// [ulo, uhi] outside of which |psi^(u)| < rel * max|psi^|
+static void spectral_band(const Wavelet &w, double rel, double &ulo, double &uhi) {
+    const double step = 1.0 / 512.0, lim = 64.0;
+    double mx = 0.0;
+    for (double u = -lim; u <= lim; u += step) mx = std::max(mx, std::fabs(w.amp(u)));
+    ulo = lim;
+    uhi = -lim;
+    for (double u = -lim; u <= lim; u += step)
+        if (std::fabs(w.amp(u)) >= rel * mx) {
+            ulo = std::min(ulo, u);
+            uhi = std::max(uhi, u);
+        }
+    ulo -= 2 * step;
+    uhi += 2 * step;
+}
+
+// Psi_s(omega) = sum_q amp(s (omega + 2 pi q)), q over the images that can reach the band
+static double psi_aliased(const Wavelet &w, double s, double omega, double umax) {
+    int qi = (int)std::ceil((umax + 1.0) / (2.0 * M_PI * s)) + 1;
+    double acc = 0.0;
+    for (int q = -qi; q <= qi; ++q) acc += w.amp(s * (omega + 2.0 * M_PI * q));
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// FFT length helpers
+
+static int64_t pow2_part(int64_t m) { return m & (-m); }
+
+static bool smooth_form(int64_t m, int &r, int64_t &p2) {
+    p2 = pow2_part(m);
+    int64_t o = m / p2;
+    if (o == 1 || o == 3 || o == 5 || o == 9) {
+        r = (int)o;
+        return true;
+    }
+    return false;
+}
+
+// M = M1 * M2 with M2 a power of two in [64, 4096] and M1 a supported size,
+// or M itself a supported size (single pass).
+static bool factor_fft(int64_t M, int32_t &M1, int32_t &M2) {
+    if (M <= 4608 && fwd_size_ok((int)M)) {
+        M1 = (int32_t)M;
+        M2 = 1;
+        return true;
+    }
+    int best = -1;
+    for (int64_t m2 = 4096; m2 >= 64; m2 /= 2) {
+        if (M % m2) continue;
+        int64_t m1 = M / m2;
+        if (m1 > 4608 || !fwd_size_ok((int)m1)) continue;
+        // prefer balanced factors
+        int64_t score = std::llabs((int64_t)std::log2((double)m1) - (int64_t)std::log2((double)m2));
+        if (best < 0 || score < best) {
+            best = (int)score;
+            M1 = (int32_t)m1;
+            M2 = (int32_t)m2;
+        }
+    }
+    return best >= 0;
+}
+
+static int64_t smallest_fft_len(int64_t need) {
+    int64_t best = -1;
+    for (int r : {1, 3, 5, 9}) {
+        int64_t p2 = 64;
+        while (r * p2 < need) p2 *= 2;
+        int64_t m = r * p2;
+        int32_t a, b;
+        if (!factor_fft(m, a, b)) continue;
+        if (best < 0 || m < best) best = m;
+    }
+    return best;
+}
+
+static int64_t next_pow2(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p *= 2;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// table upload helper
+
+struct TableBuilder {
+    std::vector<char> host;
+    int64_t add(const void *data, size_t bytes) {
+        size_t off = (host.size() + 255) & ~size_t(255);
+        host.resize(off + bytes);
+        std::memcpy(host.data() + off, data, bytes);
+        return (int64_t)off;
+    }
+};
+
+template <typename R>
+static void push_twiddles(TableBuilder &tb, int64_t P, std::vector<std::pair<int32_t, int64_t>> &offs) {
+    for (auto &e : offs)
+        if (e.first == P) return;
+    std::vector<R> v(2 * P);
+    for (int64_t j = 0; j < P; ++j) {
+        // e^{+2 pi i j / P}, argument reduced in long double
+        long double a = 2.0L * M_PIl * (long double)j / (long double)P;
+        v[2 * j] = (R)std::cos(a);
+        v[2 * j + 1] = (R)std::sin(a);
+    }
+    offs.push_back({(int32_t)P, tb.add(v.data(), v.size() * sizeof(R))});
+}
+
+template <typename R>
+static void push_twM(TableBuilder &tb, int64_t M, int64_t &hi_off, int64_t &lo_off) {
+    int64_t nh = (M + 4095) / 4096;
+    std::vector<R> hi(2 * nh), lo(2 * 4096);
+    for (int64_t j = 0; j < nh; ++j) {
+        long double a = 2.0L * M_PIl * (long double)(j * 4096) / (long double)M;
+        hi[2 * j] = (R)std::cos(a);
+        hi[2 * j + 1] = (R)std::sin(a);
+    }
+    for (int64_t j = 0; j < 4096; ++j) {
+        long double a = 2.0L * M_PIl * (long double)j / (long double)M;
+        lo[2 * j] = (R)std::cos(a);
+        lo[2 * j + 1] = (R)std::sin(a);
+    }
+    hi_off = tb.add(hi.data(), hi.size() * sizeof(R));
+    lo_off = tb.add(lo.data(), lo.size() * sizeof(R));
+}
+
+// ---------------------------------------------------------------------------
+// plan construction
+
+static const int64_t kMaxN = int64_t(1) << 26;
+
+[[noreturn]] void spline_unsupported() { fail(CWT_EUNSUPPORTED, "spline method is not available in this build"); }
+
+void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &tb);  // cwt_spline_plan.cpp
+
+static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
+    const bool fp64 = p.precision == CWT_FP64;
+    // largest segment transform that keeps its spectrum in registers without spills
+    const int lmax = fp64 ? 4096 : 8192;
+    const int pmax = fp64 ? 1024 : 2048;
+    p.path.assign(p.S, PATH_LOCAL);
+    // local if the halo fits a quarter of the largest segment transform
+    int64_t tcol = 0;
+    std::vector<int> col;
+    for (int j = 0; j < p.S; ++j) {
+        if (p.T[j] * 4 <= lmax) {
+            p.path[j] = PATH_LOCAL;
+        } else {
+            p.path[j] = PATH_COLUMN;
+            col.push_back(j);
+            tcol = std::max(tcol, p.T[j]);
+        }
+    }
+    p.pair_real = !p.cplx_out;
+
+    // spectrum tables are built as doubles, converted at upload
+    std::vector<double> tab;
+
+    // ---- local groups: L = smallest power of two >= 8 T (at least 256), or
+    // lmax when the halo needs it
+    {
+        std::vector<std::pair<int, int>> lj;  // (L, scale)
+        for (int j = 0; j < p.S; ++j) {
+            if (p.path[j] != PATH_LOCAL) continue;
+            int64_t L = std::max<int64_t>(256, next_pow2(8 * p.T[j] + 1));
+            if (L > lmax) L = lmax;
+            lj.push_back({(int)L, j});
+        }
+        std::sort(lj.begin(), lj.end());
+        double ulo, uhi;
+        spectral_band(w, p.rel, ulo, uhi);
+        double umax = std::max(std::fabs(ulo), std::fabs(uhi));
+        size_t i = 0;
+        while (i < lj.size()) {
+            LocalGroup g;
+            g.L = lj[i].first;
+            while (i < lj.size() && lj[i].first == g.L) {
+                g.scales.push_back(lj[i].second);
+                g.Tg = std::max(g.Tg, p.T[lj[i].second]);
+                ++i;
+            }
+            g.V = g.L - 2 * g.Tg;
+            if (g.V <= 0) fail(CWT_EUNSUPPORTED, "internal: segment too short for the halo");
+            g.nseg = (p.N + g.V - 1) / g.V;
+            g.tab_off = (int64_t)tab.size();
+            for (int j : g.scales) {
+                double s = p.scales[j];
+                for (int m = 0; m < g.L; ++m) {
+                    int ms = m < g.L / 2 ? m : m - g.L;
+                    tab.push_back(psi_aliased(w, s, 2.0 * M_PI * ms / g.L, umax) / g.L);
+                }
+            }
+            p.groups.push_back(std::move(g));
+        }
+    }
+
+    // ---- whole-signal FFT and band-limited columns
+    if (!col.empty()) {
+        int64_t need;
+        if (p.boundary == CWT_PERIODIC) {
+            int r;
+            int64_t p2;
+            int32_t a, b;
+            if (smooth_form(p.N, r, p2) && p2 >= 64 && factor_fft(p.N, a, b)) {
+                p.M = p.N;
+                p.load_mode = LOAD_PERIODIC;
+            } else {
+                p.load_mode = LOAD_WRAP;
+                p.Twrap = tcol;
+            }
+            need = p.N + 2 * tcol;
+        } else {
+            p.load_mode = LOAD_ZERO;
+            need = p.N + tcol + 1;
+        }
+        if (p.M == 0) {
+            if (fft_len_opt > 0) {
+                int r;
+                int64_t p2;
+                int32_t a, b;
+                if (fft_len_opt < need || !smooth_form(fft_len_opt, r, p2) || p2 < 64 || !factor_fft(fft_len_opt, a, b))
+                    fail(CWT_EUNSUPPORTED, "fft_len too short or not of the form 2^a*{1,3,5,9} (2^a >= 64)");
+                p.M = fft_len_opt;
+            } else {
+                p.M = smallest_fft_len(need);
+            }
+        }
+        if (p.M <= 0 || !factor_fft(p.M, p.M1, p.M2))
+            fail(CWT_EUNSUPPORTED, "signal plus wavelet support exceeds the largest supported FFT length");
+        int r;
+        int64_t p2;
+        smooth_form(p.M, r, p2);
+
+        double ulo, uhi;
+        spectral_band(w, p.rel, ulo, uhi);
+        double umax = std::max(std::fabs(ulo), std::fabs(uhi));
+        struct Band {
+            int j;
+            int64_t mlo, B;
+        };
+        std::vector<Band> bands;
+        for (int j : col) {
+            double s = p.scales[j];
+            int64_t mlo = (int64_t)std::floor(p.M * ulo / (2.0 * M_PI * s)) - 1;
+            int64_t mhi = (int64_t)std::ceil(p.M * uhi / (2.0 * M_PI * s)) + 1;
+            int64_t B = mhi - mlo + 1;
+            if (B >= p.M) {
+                mlo = -p.M / 2;
+                B = p.M;
+            }
+            bands.push_back({j, mlo, B});
+        }
+        // pair real-wavelet scales (neighbours in band width share one complex transform)
+        std::vector<std::pair<int, int>> units;  // indices into bands
+        if (p.pair_real) {
+            std::vector<int> order(bands.size());
+            for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+            std::sort(order.begin(), order.end(), [&](int a, int b) { return bands[a].B < bands[b].B; });
+            for (size_t i = 0; i < order.size(); i += 2)
+                units.push_back({order[i], i + 1 < order.size() ? order[i + 1] : -1});
+        } else {
+            for (size_t i = 0; i < bands.size(); ++i) units.push_back({(int)i, -1});
+        }
+        for (auto &u : units) {
+            const Band &A = bands[u.first];
+            int64_t mlo = A.mlo, mend = A.mlo + A.B;
+            if (u.second >= 0) {
+                const Band &Bb = bands[u.second];
+                mlo = std::min(mlo, Bb.mlo);
+                mend = std::max(mend, Bb.mlo + Bb.B);
+            }
+            int64_t B = mend - mlo;
+            if (B >= p.M) {
+                mlo = -p.M / 2;
+                B = p.M;
+            }
+            int64_t P = std::max<int64_t>(64, next_pow2(B));
+            P = std::min<int64_t>(P, pmax);
+            P = std::min<int64_t>(P, p2);
+            if (!column_size_ok((int)P, p.precision))
+                fail(CWT_EUNSUPPORTED, "FFT length has too small a power-of-two factor for the band-limited path");
+            int G = column_g((int)P, p.precision);
+            int64_t Q = p.M / P;
+            ColumnDesc d{};
+            d.sa = bands[u.first].j;
+            d.sb = u.second >= 0 ? bands[u.second].j : -1;
+            d.mlo = mlo;
+            d.B = B;
+            d.Q = Q;
+            d.taba = (int64_t)tab.size();
+            for (int64_t m = mlo; m < mlo + B; ++m)
+                tab.push_back(psi_aliased(w, p.scales[d.sa], 2.0 * M_PI * (double)m / p.M, umax) / p.M);
+            d.tabb = d.taba;
+            if (d.sb >= 0) {
+                d.tabb = (int64_t)tab.size();
+                for (int64_t m = mlo; m < mlo + B; ++m)
+                    tab.push_back(psi_aliased(w, p.scales[d.sb], 2.0 * M_PI * (double)m / p.M, umax) / p.M);
+            }
+            ColumnLaunch *cl = nullptr;
+            for (auto &c : p.columns)
+                if (c.P == P) cl = &c;
+            if (!cl) {
+                p.columns.push_back(ColumnLaunch{});
+                cl = &p.columns.back();
+                cl->P = (int32_t)P;
+                cl->G = G;
+            }
+            for (int64_t r0 = 0; r0 < Q; r0 += G) {
+                d.r0 = r0;
+                cl->items.push_back(d);
+            }
+        }
+    }
+
+    // workspace: F (plan precision complex) then the four-step intermediate (FP64 complex)
+    if (p.M > 0) {
+        size_t fbytes = (size_t)p.M * (fp64 ? 16 : 8);
+        p.ws_F_off = 0;
+        p.ws_Y_off = (fbytes + 255) & ~size_t(255);
+        p.ws_bytes = p.M2 > 1 ? p.ws_Y_off + (size_t)p.M * 16 : fbytes;
+    }
+    p.tab_elems = (int64_t)tab.size();
+    if (p.host_only) return;
+
+    // ---- upload: spectrum table (plan precision) and twiddles
+    if (!tab.empty()) {
+        size_t bytes = tab.size() * (fp64 ? 8 : 4);
+        HIPCHK(hipMalloc(&p.d_tab, bytes));
+        p.table_bytes += bytes;
+        if (fp64) {
+            HIPCHK(hipMemcpy(p.d_tab, tab.data(), bytes, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> t32(tab.begin(), tab.end());
+            HIPCHK(hipMemcpy(p.d_tab, t32.data(), bytes, hipMemcpyHostToDevice));
+        }
+    }
+    TableBuilder tb;
+    for (auto &g : p.groups) {
+        if (fp64) push_twiddles<double>(tb, g.L, p.tw_off);
+        else push_twiddles<float>(tb, g.L, p.tw_off);
+    }
+    for (auto &c : p.columns) {
+        if (fp64) push_twiddles<double>(tb, c.P, p.tw_off);
+        else push_twiddles<float>(tb, c.P, p.tw_off);
+    }
+    if (p.M > 0) {
+        push_twiddles<double>(tb, p.M1, p.tw64_off);
+        if (p.M2 > 1) {
+            push_twiddles<double>(tb, p.M2, p.tw64_off);
+            push_twM<double>(tb, p.M, p.twM64_hi_off, p.twM64_lo_off);
+        }
+        if (fp64) {
+            if (p.twM64_hi_off < 0) push_twM<double>(tb, p.M, p.twM64_hi_off, p.twM64_lo_off);
+            p.twM_hi_off = p.twM64_hi_off;
+            p.twM_lo_off = p.twM64_lo_off;
+        } else {
+            push_twM<float>(tb, p.M, p.twM_hi_off, p.twM_lo_off);
+        }
+    }
+    if (!tb.host.empty()) {
+        HIPCHK(hipMalloc(&p.d_tw_all, tb.host.size()));
+        p.table_bytes += tb.host.size();
+        HIPCHK(hipMemcpy(p.d_tw_all, tb.host.data(), tb.host.size(), hipMemcpyHostToDevice));
+    }
+    for (auto &g : p.groups) {
+        HIPCHK(hipMalloc(&g.d_scales, g.scales.size() * sizeof(int32_t)));
+        p.table_bytes += g.scales.size() * sizeof(int32_t);
+        HIPCHK(hipMemcpy(g.d_scales, g.scales.data(), g.scales.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    for (auto &c : p.columns) {
+        size_t bytes = c.items.size() * sizeof(ColumnDesc);
+        HIPCHK(hipMalloc(&c.d_items, bytes));
+        p.table_bytes += bytes;
+        HIPCHK(hipMemcpy(c.d_items, c.items.data(), bytes, hipMemcpyHostToDevice));
+    }
+}
+
+static void free_plan(Plan *p) {
+    if (!p) return;
+    if (p->d_tab) (void)hipFree(p->d_tab);
+    if (p->d_tw_all) (void)hipFree(p->d_tw_all);
+    if (p->d_dtab) (void)hipFree(p->d_dtab);
+    for (auto &g : p->groups)
+        if (g.d_scales) (void)hipFree(g.d_scales);
+    for (auto &c : p->columns)
+        if (c.d_items) (void)hipFree(c.d_items);
+    for (void *x : p->d_extra)
+        if (x) (void)hipFree(x);
+    for (auto &r : p->timing_recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : p->event_pool) (void)hipEventDestroy(e);
+    delete p;
+}
+
+static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double *scales, int32_t S,
+                       const cwt_opts *opts) {
+    if (N < 2) fail(CWT_EINVAL, "N must be >= 2");
+    if (N > kMaxN) fail(CWT_EUNSUPPORTED, "N above 2^26");
+    if (S < 1) fail(CWT_EINVAL, "S must be >= 1");
+    if (S > 65536) fail(CWT_EUNSUPPORTED, "S above 65536");
+    if (!scales) fail(CWT_EINVAL, "scales is NULL");
+    if (boundary != CWT_PERIODIC && boundary != CWT_ZERO) fail(CWT_EINVAL, "unknown boundary");
+    int precision = opts ? opts->precision : CWT_FP64;
+    int method = opts ? opts->method : CWT_METHOD_FFT;
+    int64_t fft_len = opts ? opts->fft_len : 0;
+    if (precision != CWT_FP64 && precision != CWT_FP32) fail(CWT_EINVAL, "unknown precision");
+    if (method != CWT_METHOD_FFT && method != CWT_METHOD_SPLINE) fail(CWT_EINVAL, "unknown method");
+    if (fft_len < 0) fail(CWT_EINVAL, "fft_len must be >= 0");
+    Wavelet w;
+    w.kind = wv.kind;
+    if (wv.kind == CWT_MORLET) {
+        if (!(std::isfinite(wv.param) && wv.param > 0.0)) fail(CWT_EINVAL, "Morlet omega0 must be finite and > 0");
+        w.w0 = wv.param;
+    } else if (wv.kind == CWT_MEXHAT) {
+        w.m = 2;
+    } else if (wv.kind == CWT_DOG) {
+        if (!(std::isfinite(wv.param) && wv.param >= 1.0 && wv.param <= 16.0 && wv.param == std::floor(wv.param)))
+            fail(CWT_EINVAL, "DOG order must be an integer in [1, 16]");
+        w.m = (int)wv.param;
+    } else {
+        fail(CWT_EINVAL, "unknown wavelet kind");
+    }
+    w.init();
+    for (int j = 0; j < S; ++j)
+        if (!(std::isfinite(scales[j]) && scales[j] > 0.0)) fail(CWT_EINVAL, "scales must be finite and > 0");
+
+    Plan *p = new Plan();
+    try {
+        p->N = N;
+        p->boundary = boundary;
+        p->kind = wv.kind;
+        p->param = wv.kind == CWT_MORLET ? w.w0 : (double)w.m;
+        p->precision = precision;
+        p->method = method;
+        p->host_only = opts && opts->host_only != 0;
+        p->S = S;
+        p->scales.assign(scales, scales + S);
+        p->cplx_out = w.complex_out();
+        p->cph = w.cph();
+        p->rel = precision == CWT_FP64 ? 1e-16 : 1e-9;
+        p->chi = time_radius(w, p->rel);
+        p->T.resize(S);
+        for (int j = 0; j < S; ++j) p->T[j] = (int64_t)std::ceil(p->chi * scales[j]);
+        if (method == CWT_METHOD_FFT) {
+            build_fft_plan(*p, w, fft_len);
+        } else {
+            TableBuilder tb;
+            build_spline_plan(*p, w, tb);
+        }
+    } catch (...) {
+        free_plan(p);
+        throw;
+    }
+    return p;
+}
+
+static hipEvent_t pool_event(Plan &p) {
+    if (!p.event_pool.empty()) {
+        hipEvent_t e = p.event_pool.back();
+        p.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+// Runs `launch` and, when timing is on, brackets it with events on `st`.
+template <typename F>
+static void timed(Plan &p, hipStream_t st, const std::string &name, double bytes, const char *what, F &&launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (p.timing) {
+        a = pool_event(p);
+        b = pool_event(p);
+        HIPCHK(hipEventRecord(a, st));
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) fail(CWT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    if (p.timing) {
+        HIPCHK(hipEventRecord(b, st));
+        p.timing_recs.push_back({name, a, b, bytes});
+    }
+}
+
+}  // namespace cwt
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+using cwt::Failure;
+using cwt::Plan;
+
+struct cwt_plan_s {
+    Plan *p;
+};
+
+template <typename F> static int guarded(F &&f) {
+    try {
+        cwt::g_err.clear();
+        return f();
+    } catch (const Failure &e) {
+        cwt::g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        cwt::g_err = "host allocation failed";
+        return CWT_ENOMEM;
+    } catch (const std::exception &e) {
+        cwt::g_err = e.what();
+        return CWT_EINVAL;
+    } catch (...) {
+        cwt::g_err = "unknown failure";
+        return CWT_EINVAL;
+    }
+}
+
+extern "C" {
+
+int cwt_plan(cwt_plan_t *out, int64_t N, int32_t boundary, cwt_wavelet wavelet, const double *scales, int32_t S,
+             const cwt_opts *opts) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> int {
+        if (!out) cwt::fail(CWT_EINVAL, "out is NULL");
+        Plan *p = cwt::make_plan(N, boundary, wavelet, scales, S, opts);
+        cwt_plan_s *h = new (std::nothrow) cwt_plan_s{p};
+        if (!h) {
+            cwt::free_plan(p);
+            cwt::fail(CWT_ENOMEM, "host allocation failed");
+        }
+        *out = h;
+        return CWT_OK;
+    });
+}
+
+int cwt_destroy(cwt_plan_t plan) {
+    return guarded([&]() -> int {
+        if (!plan) return CWT_OK;
+        cwt::free_plan(plan->p);
+        delete plan;
+        return CWT_OK;
+    });
+}
+
+int cwt_out_is_complex(cwt_plan_t plan) {
+    if (!plan) return CWT_EINVAL;
+    return plan->p->cplx_out ? 1 : 0;
+}
+
+int64_t cwt_out_elems(cwt_plan_t plan) {
+    if (!plan) return -1;
+    return plan->p->N * (int64_t)plan->p->S;
+}
+
+int32_t cwt_out_elem_bytes(cwt_plan_t plan) {
+    if (!plan) return CWT_EINVAL;
+    int b = plan->p->precision == CWT_FP64 ? 8 : 4;
+    return plan->p->cplx_out ? 2 * b : b;
+}
+
+size_t cwt_workspace_bytes(cwt_plan_t plan) { return plan ? plan->p->ws_bytes : 0; }
+
+size_t cwt_footprint_bytes(cwt_plan_t plan) {
+    if (!plan) return 0;
+    const Plan &p = *plan->p;
+    size_t eb = (size_t)cwt_out_elem_bytes(plan);
+    size_t sig = (size_t)p.N * (p.precision == CWT_FP64 ? 8 : 4);
+    return sig + eb * (size_t)p.N * (size_t)p.S + p.ws_bytes + p.table_bytes;
+}
+
+int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, void *stream) {
+    return guarded([&]() -> int {
+        if (!plan) cwt::fail(CWT_EINVAL, "plan is NULL");
+        if (!signal || !out) cwt::fail(CWT_EINVAL, "signal/out is NULL");
+        Plan &p = *plan->p;
+        if (p.host_only) cwt::fail(CWT_EINVAL, "plan was built host-only");
+        if (p.ws_bytes > 0 && !workspace) cwt::fail(CWT_EINVAL, "workspace is NULL");
+        size_t ealign = p.precision == CWT_FP64 ? 8 : 4;
+        if ((uintptr_t)signal % ealign || (uintptr_t)out % ealign)
+            cwt::fail(CWT_EINVAL, "signal/out not aligned to the element size");
+        if (workspace && (uintptr_t)workspace % 256) cwt::fail(CWT_EINVAL, "workspace not 256-byte aligned");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const double sb = p.precision == CWT_FP64 ? 8.0 : 4.0;
+        const double eb = (double)cwt_out_elem_bytes(plan);
+        const double nn = (double)p.N;
+        if (p.method == CWT_METHOD_SPLINE) {
+            cwt::timed(p, st, "spline", nn * sb + nn * p.S * eb, "spline launch",
+                       [&] { return cwt::launch_spline(p, signal, out, workspace, st); });
+            return CWT_OK;
+        }
+        const double fb = p.precision == CWT_FP64 ? 16.0 : 8.0;
+        if (p.M > 0)
+            cwt::timed(p, st, "forward", nn * sb + (double)p.M * fb, "forward launch",
+                       [&] { return cwt::launch_forward(p, signal, workspace, st); });
+        for (auto &g : p.groups)
+            cwt::timed(p, st, cwt::local_kernel_name(p, g), nn * sb + nn * (double)g.scales.size() * eb,
+                       "local launch", [&] { return cwt::launch_local(p, g, signal, out, st); });
+        for (auto &c : p.columns) {
+            double rows = 0.0, band = 0.0;
+            for (size_t i = 0; i < c.items.size(); ++i) {
+                const auto &d = c.items[i];
+                if (d.r0 != 0) continue;
+                rows += d.sb >= 0 ? 2.0 : 1.0;
+                band += (double)d.B * fb;
+            }
+            cwt::timed(p, st, cwt::column_kernel_name(p, c), band + nn * rows * eb, "column launch",
+                       [&] { return cwt::launch_column(p, c, workspace, out, st); });
+        }
+        return CWT_OK;
+    });
+}
+
+int cwt_plan_timing_enable(cwt_plan_t plan, int32_t on) {
+    return guarded([&]() -> int {
+        if (!plan) cwt::fail(CWT_EINVAL, "plan is NULL");
+        plan->p->timing = on != 0;
+        return CWT_OK;
+    });
+}
+
+int cwt_plan_timing_read(cwt_plan_t plan, int32_t max_kernels, char *names, int64_t *launches, double *ms,
+                         double *bytes_per_launch) {
+    return guarded([&]() -> int {
+        if (!plan) cwt::fail(CWT_EINVAL, "plan is NULL");
+        Plan &p = *plan->p;
+        std::vector<std::string> keys;
+        std::vector<int64_t> cnt;
+        std::vector<double> tot, byt;
+        for (auto &r : p.timing_recs) {
+            HIPCHK(hipEventSynchronize(r.b));
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+            size_t k = 0;
+            while (k < keys.size() && keys[k] != r.name) ++k;
+            if (k == keys.size()) {
+                keys.push_back(r.name);
+                cnt.push_back(0);
+                tot.push_back(0.0);
+                byt.push_back(0.0);
+            }
+            cnt[k] += 1;
+            tot[k] += t;
+            byt[k] += r.bytes;
+            p.event_pool.push_back(r.a);
+            p.event_pool.push_back(r.b);
+        }
+        p.timing_recs.clear();
+        int n = (int)keys.size();
+        for (int k = 0; k < n && k < max_kernels; ++k) {
+            if (names) {
+                std::strncpy(names + 64 * k, keys[k].c_str(), 63);
+                names[64 * k + 63] = 0;
+            }
+            if (launches) launches[k] = cnt[k];
+            if (ms) ms[k] = tot[k];
+            if (bytes_per_launch) bytes_per_launch[k] = byt[k] / (double)cnt[k];
+        }
+        return n;
+    });
+}
+
+size_t cwt_batch_workspace_bytes(const cwt_plan_t *plans, int32_t n) {
+    if (!plans || n <= 0) return 0;
+    size_t mx = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (plans[i]) mx = std::max(mx, plans[i]->p->ws_bytes);
+    return mx;
+}
+
+int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals, void *const *outs, int32_t n,
+                   void *workspace, void *stream) {
+    return guarded([&]() -> int {
+        if (n < 0) cwt::fail(CWT_EINVAL, "n < 0");
+        if (n == 0) return CWT_OK;
+        if (!plans || !signals || !outs) cwt::fail(CWT_EINVAL, "NULL array");
+        for (int32_t i = 0; i < n; ++i) {
+            int rc = cwt_exec(plans[i], signals[i], outs[i], workspace, stream);
+            if (rc != CWT_OK) return rc;
+        }
+        return CWT_OK;
+    });
+}
+
+int64_t cwt_plan_fft_len(cwt_plan_t plan) { return plan ? plan->p->M : -1; }
+
+int cwt_plan_spline_delta(cwt_plan_t plan, int32_t *delta) {
+    if (!plan || !delta) return CWT_EINVAL;
+    const Plan &p = *plan->p;
+    for (int j = 0; j < p.S; ++j) delta[j] = p.method == CWT_METHOD_SPLINE ? p.spl_delta[j] : 0;
+    return CWT_OK;
+}
+
+double cwt_plan_spline_hstar(cwt_plan_t plan) { return plan ? plan->p->hstar : 0.0; }
+
+int cwt_plan_scale_path(cwt_plan_t plan, int32_t *path) {
+    if (!plan || !path) return CWT_EINVAL;
+    for (int j = 0; j < plan->p->S; ++j) path[j] = plan->p->path[j];
+    return CWT_OK;
+}
+
+const char *cwt_last_error(void) { return cwt::g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+"""The C ABI: the library loads, exports every entry point the header
+declares, and rejects invalid arguments before touching a device.  Host-only
+plans check the plan logic (paths, FFT length, workspace) without a GPU."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2302_03909_amd as cwt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "cwt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cwt_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = cwt.load()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(cwt.EXPORTS) == names
+
+
+def _plan_rc(n=64, bc=0, kind=0, param=6.0, scales=(2.0,), opts=None):
+    lib = cwt.load()
+    h = ctypes.c_void_p()
+    sc = np.asarray(scales, dtype=np.float64)
+    o = opts if opts is not None else cwt._Opts(0, 0, 0, 1)
+    rc = lib.cwt_plan(ctypes.byref(h), n, bc, cwt._Wavelet(kind, param),
+                      sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if sc.size else None,
+                      sc.size, ctypes.byref(o))
+    if rc == 0:
+        lib.cwt_destroy(h)
+    return rc
+
+
+@pytest.mark.parametrize("kw", [dict(n=1), dict(n=0), dict(scales=()), dict(scales=(0.0,)),
+                                dict(scales=(-1.0,)), dict(scales=(float("nan"),)),
+                                dict(scales=(float("inf"),)), dict(bc=7), dict(kind=9),
+                                dict(kind=0, param=0.0), dict(kind=0, param=float("nan")),
+                                dict(kind=2, param=0.0), dict(kind=2, param=2.5),
+                                dict(kind=2, param=17.0)])
+def test_invalid_arguments(kw):
+    assert _plan_rc(**kw) == -1
+    assert cwt.load().cwt_last_error().decode() != ""
+
+
+def test_unsupported_arguments():
+    assert _plan_rc(n=(1 << 26) + 1) == -2
+    assert _plan_rc(opts=cwt._Opts(0, 0, 1000, 1)) in (0, -2)  # only if a column path needs it
+
+
+def test_bad_precision_and_method():
+    assert _plan_rc(opts=cwt._Opts(5, 0, 0, 1)) == -1
+    assert _plan_rc(opts=cwt._Opts(0, 5, 0, 1)) == -1
+
+
+def test_null_arguments():
+    lib = cwt.load()
+    assert lib.cwt_plan(None, 64, 0, cwt._Wavelet(0, 6.0), None, 1, None) == -1
+    assert lib.cwt_exec(None, None, None, None, None) == -1
+    assert lib.cwt_destroy(None) == 0
+    assert lib.cwt_out_elems(None) == -1
+
+
+def test_host_only_plan_fft_paths():
+    scales = np.geomspace(2, 2 ** 16, 128)
+    p = cwt.Plan(1 << 22, "zero", "morlet", scales, param=6.0, precision="fp32", host_only=True)
+    path = p.scale_path()
+    assert set(path.tolist()) <= {cwt.PATH_LOCAL, cwt.PATH_COLUMN}
+    assert path[0] == cwt.PATH_LOCAL and path[-1] == cwt.PATH_COLUMN
+    # zero boundary: M >= N + T(s_max) and of the form 2^a * {1,3,5,9}
+    m = p.fft_len
+    assert m >= (1 << 22) + math.ceil(6.4 * 2 ** 16)
+    odd = m // (m & -m)
+    assert odd in (1, 3, 5, 9)
+    assert p.workspace_bytes >= m * 8
+    assert p.is_complex
+    # host-only plans cannot run
+    rc = cwt.load().cwt_exec(p.handle, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(256), None)
+    assert rc == -1
+
+
+def test_host_only_periodic_smooth_uses_n():
+    p = cwt.Plan(4096 * 9, "periodic", "mexhat", [2.0, 900.0, 3000.0], host_only=True)
+    assert p.fft_len == 4096 * 9
+    q = cwt.Plan(5000, "periodic", "mexhat", [2.0, 900.0], host_only=True)
+    assert q.fft_len >= 5000 + 2 * math.ceil(8 * 900)

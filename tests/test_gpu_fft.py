@@ -1,0 +1,142 @@
+"""GPU parity of the FFT method against the FP64 direct-sum oracle.
+
+Bars (per-scale relative L2 with a floor, see tests/helpers.py): 1e-10 for
+FP64 plans, 1e-5 for FP32 plans.  FP32 references use the FP32-rounded input
+promoted to FP64.  Small cases compare every output; the full-size workloads
+compare sampled outputs the oracle computes one by one."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import per_scale_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def gpu_cwt(torch, f, bc, wav, par, scales, precision, method="fft", fft_len=0):
+    import paper_2302_03909_amd as cwt
+    plan = cwt.Plan(f.size, bc, wav, scales, param=par, precision=precision, method=method, fft_len=fft_len)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    x = torch.as_tensor(f, dtype=dt, device="cuda")
+    w = plan(x)
+    torch.cuda.synchronize()
+    return plan, w
+
+
+def ref_input(f, precision):
+    return f.astype(np.float32).astype(np.float64) if precision == "fp32" else f
+
+
+def check_full(torch, f, bc, wav, par, scales, precision, expect_paths=None, fft_len=0):
+    print(f"case N={f.size} bc={bc} wav={wav}({par}) S={len(scales)} {precision}", flush=True)
+    plan, w = gpu_cwt(torch, f, bc, wav, par, scales, precision, fft_len=fft_len)
+    got = w.cpu().numpy()
+    ref = oracle.cwt(ref_input(f, precision), bc, wav, scales, param=par)
+    err = per_scale_rel_l2(got, ref)
+    if expect_paths is not None:
+        assert set(plan.scale_path().tolist()) == set(expect_paths)
+    assert np.all(np.isfinite(got))
+    assert err.max() <= TOL[precision], (err.max(), int(err.argmax()))
+    return err
+
+
+def test_small_periodic_morlet_fp64(torch_cuda):
+    # N = 4096 periodic tones + noise, Morlet(6), 32 log scales 2..512
+    f = synth.tones_noise(4096)
+    scales = synth.log_scales(2.0, 512.0, 32)
+    err = check_full(torch_cuda, f, "periodic", "morlet", 6.0, scales, "fp64", expect_paths={0, 1})
+    print("max rel L2", err.max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,bc,wav,par,scales", [
+    (3001, "zero", "mexhat", None, [1.5, 2.0, 9.0, 40.0, 150.0, 700.0]),
+    (5000, "periodic", "dog", 3.0, [2.0, 30.0, 400.0, 2500.0]),
+    (4096, "periodic", "morlet", 6.0, [0.5, 3.0, 700.0, 5000.0]),
+    (2000, "zero", "morlet", 4.0, [1.0, 7.0, 333.0]),
+    (1024, "zero", "dog", 4.0, [2.5, 64.0, 300.0]),
+    (777, "periodic", "dog", 1.0, [1.2, 50.0]),
+])
+def test_parity_mixed(torch_cuda, precision, n, bc, wav, par, scales):
+    rng = np.random.default_rng(n)
+    f = rng.standard_normal(n) + 0.3
+    check_full(torch_cuda, f, bc, wav, par, scales, precision)
+
+
+@pytest.mark.parametrize("n", [2, 3, 17])
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+def test_degenerate_lengths(torch_cuda, n, bc):
+    f = np.random.default_rng(5).standard_normal(n)
+    check_full(torch_cuda, f, bc, "morlet", 6.0, [1.0, 2.0, 40.0], "fp64")
+    check_full(torch_cuda, f, bc, "mexhat", None, [0.7, 5.0], "fp64")
+
+
+def test_single_scale_and_constant_signal(torch_cuda):
+    f = np.full(300, 2.5)
+    _, w = gpu_cwt(torch_cuda, f, "periodic", "mexhat", None, [4.0], "fp64")
+    # admissible wavelet: a constant periodic signal has zero transform
+    assert np.max(np.abs(w.cpu().numpy())) < 1e-13
+    check_full(torch_cuda, np.random.default_rng(1).standard_normal(300), "zero", "morlet", 6.0, [3.3], "fp64")
+
+
+def test_fft_len_override_gives_same_result(torch_cuda):
+    f = synth.lognormal_field(3000, seed=4)
+    scales = [2.0, 50.0, 600.0, 1500.0]
+    import paper_2302_03909_amd as cwt
+    p = cwt.Plan(f.size, "zero", "mexhat", scales, host_only=True)
+    _, a = gpu_cwt(torch_cuda, f, "zero", "mexhat", None, scales, "fp64")
+    _, b = gpu_cwt(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", fft_len=5 * 4096)
+    assert p.fft_len != 5 * 4096
+    ref = oracle.cwt(f, "zero", "mexhat", scales)
+    assert per_scale_rel_l2(a.cpu().numpy(), ref).max() < 1e-10
+    assert per_scale_rel_l2(b.cpu().numpy(), ref).max() < 1e-10
+
+
+def sampled_check(torch, f, bc, wav, par, scales, precision, npos=48, seed=0):
+    plan, w = gpu_cwt(torch, f, bc, wav, par, scales, precision)
+    n = f.size
+    rng = np.random.default_rng(seed)
+    pos = np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.integers(0, n, npos - 5)])
+    si = np.repeat(np.arange(len(scales)), pos.size)
+    ps = np.tile(pos, len(scales))
+    import torch as T
+    got = w[T.as_tensor(si, device="cuda"), T.as_tensor(ps, device="cuda")].cpu().numpy()
+    ref = oracle.cwt_points(ref_input(f, precision), bc, wav, scales, si, ps, param=par)
+    got = got.reshape(len(scales), pos.size)
+    ref = ref.reshape(len(scales), pos.size)
+    err = per_scale_rel_l2(got, ref)
+    del w
+    torch.cuda.empty_cache()
+    return plan, err
+
+
+def test_full_size_fp64_mexhat_1m(torch_cuda):
+    # N = 2^20 zero-boundary lognormal field, Mexican hat, 64 log scales 2..2^14, FP64
+    f = synth.lognormal_field(1 << 20, seed=synth.SEED_FIELD_1M)
+    scales = synth.log_scales(2.0, 2.0 ** 14, 64)
+    plan, err = sampled_check(torch_cuda, f, "zero", "mexhat", None, scales, "fp64")
+    print("fp64 1M max err", err.max(), "M", plan.fft_len)
+    assert err.max() <= 1e-10
+
+
+@pytest.mark.parametrize("wav,par", [("morlet", 6.0), ("dog", 2.0)])
+def test_full_size_fp32_4m(torch_cuda, wav, par):
+    # N = 2^22 zero-boundary lognormal field, 128 log scales 2..2^16, FP32 form
+    f = synth.lognormal_field(1 << 22, seed=synth.SEED_FIELD_4M)
+    scales = synth.log_scales(2.0, 2.0 ** 16, 128)
+    plan, err = sampled_check(torch_cuda, f, "zero", wav, par, scales, "fp32", npos=40)
+    print(f"fp32 4M {wav} max err", err.max(), "M", plan.fft_len)
+    assert err.max() <= 1e-5
