@@ -79,6 +79,18 @@ extern "C" {
 #define CWT_METHOD_FFT 0
 #define CWT_METHOD_SPLINE 1
 
+/* How the FFT method organises the transform:
+ *   CWT_FFT_SEGMENTED -- overlap-save segments of L = 2^l samples per group of
+ *                        scales (L about 8x the wavelet half-support); each
+ *                        segment's spectrum is taken once per group, only on
+ *                        the band the group's wavelets occupy, and inverted
+ *                        per scale with short band-limited FFTs.
+ *   CWT_FFT_WHOLE     -- the transform as written in Sec. 3.1: one FFT of
+ *                        the whole (zero- or wrap-padded) signal, then per
+ *                        scale a band-limited inverse of length M. */
+#define CWT_FFT_SEGMENTED 0
+#define CWT_FFT_WHOLE 1
+
 typedef struct cwt_plan_s *cwt_plan_t;
 
 typedef struct {
@@ -96,7 +108,10 @@ typedef struct {
     int32_t host_only; /* 1: build the plan on the host only (no device
                           allocation, no device needed); it can be queried
                           but cwt_exec rejects it with CWT_EINVAL */
-    int32_t reserved[7];
+    int32_t fft_mode;  /* FFT method only: CWT_FFT_SEGMENTED (default) or
+                          CWT_FFT_WHOLE; both give the same transform up to
+                          rounding */
+    int32_t reserved[6];
 } cwt_opts;
 
 /*

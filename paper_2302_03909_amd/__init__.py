@@ -40,7 +40,7 @@ class _Wavelet(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("fft_len", ctypes.c_int64), ("host_only", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("fft_mode", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 EXPORTS = ["cwt_plan", "cwt_destroy", "cwt_out_is_complex", "cwt_out_elems", "cwt_out_elem_bytes",
@@ -99,6 +99,7 @@ def _check(rc: int):
 _BOUNDARY = {"periodic": CWT_PERIODIC, "zero": CWT_ZERO}
 _PRECISION = {"fp64": CWT_FP64, "fp32": CWT_FP32}
 _METHOD = {"fft": CWT_METHOD_FFT, "spline": CWT_METHOD_SPLINE}
+_FFT_MODE = {"segmented": 0, "whole": 1}
 
 
 def _wavelet(name: str, param):
@@ -119,11 +120,12 @@ class Plan:
 
     def __init__(self, n: int, boundary: str, wavelet: str, scales, param=None,
                  precision: str = "fp64", method: str = "fft", fft_len: int = 0,
-                 host_only: bool = False):
+                 host_only: bool = False, fft_mode: str = "segmented"):
         lib = load()
         kind, par = _wavelet(wavelet, param)
         sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64).ravel())
-        opts = _Opts(_PRECISION[precision], _METHOD[method], int(fft_len), 1 if host_only else 0)
+        opts = _Opts(_PRECISION[precision], _METHOD[method], int(fft_len), 1 if host_only else 0,
+                     _FFT_MODE[fft_mode])
         h = ctypes.c_void_p()
         _check(lib.cwt_plan(ctypes.byref(h), int(n), _BOUNDARY[boundary], _Wavelet(kind, par),
                             sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sc.size,
@@ -136,6 +138,7 @@ class Plan:
         self.param = par
         self.precision = precision
         self.method = method
+        self.fft_mode = fft_mode
         self.is_complex = bool(lib.cwt_out_is_complex(h))
         self.workspace_bytes = int(lib.cwt_workspace_bytes(h))
         self.footprint_bytes = int(lib.cwt_footprint_bytes(h))

@@ -39,6 +39,33 @@ struct ColumnDesc {
     int64_t taba, tabb;  // offsets of the spectrum samples of sa / sb
 };
 
+// Work item of the segmented inverse: one segment, one scale (or a pair of
+// real-wavelet scales sharing the transform) and 16 consecutive columns.
+struct SegItem {
+    int32_t seg, sa, sb, r0;
+    int64_t ka, kb;  // offsets of the spectrum samples of sa / sb
+};
+
+// A group of scales transformed with the same segment length L = 2^lgL.
+//   LOCAL: full L-point spectrum, fused kernel (NCOL segments per workgroup)
+//   BAND:  spectrum needed on [klo, klo + B) only, B <= P, L = P * Q
+struct SegGroup {
+    enum Kind { LOCAL = 0, BAND = 1 };
+    int32_t kind = LOCAL;
+    int32_t L = 0, lgL = 0, P = 0;
+    int64_t Tg = 0, V = 0, nseg = 0;
+    int64_t klo = 0;
+    int32_t B = 0, nchunk = 1, iters = 1;
+    std::vector<int32_t> scales;  // LOCAL: scale indices (table rows in order)
+    int64_t tab_off = 0;          // LOCAL: offset (elements) of the L-point tables
+    int32_t *d_scales = nullptr;
+    std::vector<SegItem> items;  // BAND
+    SegItem *d_items = nullptr;
+    int64_t twl_off = -1;  // per-pass LDS twiddle table of size L (LOCAL) or P (BAND), bytes
+    int64_t gtw_off = -1;  // BAND: w_L^{m g}, g < 16, m in band, bytes
+    size_t ws_xp_off = 0, ws_x_off = 0;
+};
+
 struct ColumnLaunch {
     int32_t P = 0, G = 0;
     std::vector<ColumnDesc> items;
@@ -73,6 +100,9 @@ struct Plan {
     int64_t Twrap = 0;
     std::vector<LocalGroup> groups;
     std::vector<ColumnLaunch> columns;
+    std::vector<SegGroup> segs;
+    int32_t fft_mode = 0;  // 0 segmented, 1 whole signal
+    int64_t w23_hi_off = -1, w23_lo_off = -1;  // FP64 w_{2^23} tables, bytes
     bool pair_real = false;
 
     // spline method
@@ -106,6 +136,15 @@ struct Plan {
     size_t ws_c_off = 0, ws_e_off = 0;  // workspace layout (spline method)
     size_t table_bytes = 0;
 };
+
+hipError_t launch_local2(const Plan &p, const SegGroup &g, const void *signal, void *out, hipStream_t st);
+// phase 0: segment spectra (forward + reduce); phase 1: inverse (BAND groups)
+hipError_t launch_seg(const Plan &p, const SegGroup &g, const void *signal, void *ws, void *out, hipStream_t st,
+                      int phase);
+std::string seg_kernel_name(const Plan &p, const SegGroup &g, int phase);
+bool local2_size_ok(int L, int precision);
+bool seg_size_ok(int P, int precision);
+int local2_segs_per_block(int L, bool pair);
 
 // names of the kernel instantiations a launch uses (timing labels)
 std::string local_kernel_name(const Plan &p, const LocalGroup &g);

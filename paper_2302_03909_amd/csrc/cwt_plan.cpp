@@ -217,6 +217,56 @@ static void push_twM(TableBuilder &tb, int64_t M, int64_t &hi_off, int64_t &lo_o
 // ---------------------------------------------------------------------------
 // plan construction
 
+
+// per-pass twiddle table of a P-point transform (layout of fft_cols.h):
+// pass j with radix R_j and sub-size Ns_j > 1 stores e^{+2 pi i r k/(R_j Ns_j)}
+// at (r - 1) Ns_j + k
+static int host_odd_part(int p) { return (p % 9 == 0) ? 9 : (p % 5 == 0) ? 5 : (p % 3 == 0) ? 3 : 1; }
+static std::vector<int> host_radices(int p) {
+    std::vector<int> r;
+    int o = host_odd_part(p);
+    int k = 0;
+    while ((o << k) < p) ++k;
+    if (o > 1) r.push_back(o);
+    for (int i = 0; i < k / 4; ++i) r.push_back(16);
+    if (k % 4) r.push_back(1 << (k % 4));
+    return r;
+}
+template <typename R>
+static int64_t push_pass_twiddles(TableBuilder &tb, int P) {
+    std::vector<R> v;
+    int ns = 1;
+    for (int rad : host_radices(P)) {
+        if (ns > 1)
+            for (int r = 1; r < rad; ++r)
+                for (int k = 0; k < ns; ++k) {
+                    long double a = 2.0L * M_PIl * (long double)(r * k) / (long double)(rad * ns);
+                    v.push_back((R)std::cos(a));
+                    v.push_back((R)std::sin(a));
+                }
+        ns *= rad;
+    }
+    if (v.empty()) v.assign(2, (R)0);
+    return tb.add(v.data(), v.size() * sizeof(R));
+}
+// w_{2^23}^x = hi[x >> 11] * lo[x & 2047] (FP64)
+static void push_w23(TableBuilder &tb, int64_t &hi_off, int64_t &lo_off) {
+    const int64_t L = int64_t(1) << 23;
+    std::vector<double> hi(2 * 4096), lo(2 * 2048);
+    for (int64_t j = 0; j < 4096; ++j) {
+        long double a = 2.0L * M_PIl * (long double)(j * 2048) / (long double)L;
+        hi[2 * j] = (double)std::cos(a);
+        hi[2 * j + 1] = (double)std::sin(a);
+    }
+    for (int64_t j = 0; j < 2048; ++j) {
+        long double a = 2.0L * M_PIl * (long double)j / (long double)L;
+        lo[2 * j] = (double)std::cos(a);
+        lo[2 * j + 1] = (double)std::sin(a);
+    }
+    hi_off = tb.add(hi.data(), hi.size() * sizeof(double));
+    lo_off = tb.add(lo.data(), lo.size() * sizeof(double));
+}
+
 static const int64_t kMaxN = int64_t(1) << 26;
 
 [[noreturn]] void spline_unsupported() { fail(CWT_EUNSUPPORTED, "spline method is not available in this build"); }
@@ -465,6 +515,191 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
     }
 }
 
+
+// Segmented FFT plan.  Every scale gets a segment length L = 2^l >= 8 T
+// (T its half-support, at least 64 samples).  If the spectrum of its wavelet
+// at that length spans a sixteenth of L or more, the scale joins a LOCAL
+// group (full-spectrum fused kernel); otherwise a BAND group keyed by (L, P)
+// with P >= the band width.
+static void build_seg_plan(Plan &p, const Wavelet &w) {
+    const bool fp64 = p.precision == CWT_FP64;
+    const int lmax_local = fp64 ? 4096 : 8192;
+    const int pmax = fp64 ? 512 : 1024;
+    const int lg_max = 23;
+    double ulo, uhi;
+    spectral_band(w, p.rel, ulo, uhi);
+    double umax = std::max(std::fabs(ulo), std::fabs(uhi));
+    p.pair_real = !p.cplx_out;
+    p.path.assign(p.S, PATH_LOCAL);
+
+    struct Cand {
+        int j, lg;
+        int64_t klo, khi;
+    };
+    std::vector<Cand> loc, band;
+    for (int j = 0; j < p.S; ++j) {
+        double s = p.scales[j];
+        int64_t L = std::max<int64_t>(64, next_pow2(8 * p.T[j] + 1));
+        int lg = 0;
+        while ((int64_t(1) << lg) < L) ++lg;
+        if (lg > lg_max) fail(CWT_EUNSUPPORTED, "scale too large for the segmented transform (wavelet support above 2^20 samples)");
+        int64_t klo = (int64_t)std::floor(L * ulo / (2.0 * M_PI * s)) - 1;
+        int64_t khi = (int64_t)std::ceil(L * uhi / (2.0 * M_PI * s)) + 1;
+        int64_t B = khi - klo + 1;
+        int64_t P = std::max<int64_t>(64, next_pow2(B));
+        if (P * 16 > L || P > pmax) {
+            if (L > lmax_local) fail(CWT_EUNSUPPORTED, "wavelet band too wide for the segment length");
+            loc.push_back({j, lg, 0, 0});
+        } else {
+            band.push_back({j, lg, klo, khi});
+            p.path[j] = PATH_COLUMN;
+        }
+    }
+    std::vector<double> tab;
+    TableBuilder tb;
+    push_w23(tb, p.w23_hi_off, p.w23_lo_off);
+    size_t ws = 0;
+    auto ws_take = [&](size_t bytes) {
+        size_t off = (ws + 255) & ~size_t(255);
+        ws = off + bytes;
+        return off;
+    };
+
+    // LOCAL groups by L
+    std::sort(loc.begin(), loc.end(), [](const Cand &a, const Cand &b) { return a.lg < b.lg || (a.lg == b.lg && a.j < b.j); });
+    for (size_t i = 0; i < loc.size();) {
+        SegGroup g;
+        g.kind = SegGroup::LOCAL;
+        g.lgL = loc[i].lg;
+        g.L = 1 << g.lgL;
+        while (i < loc.size() && loc[i].lg == g.lgL) {
+            g.scales.push_back(loc[i].j);
+            g.Tg = std::max(g.Tg, p.T[loc[i].j]);
+            ++i;
+        }
+        g.V = g.L - 2 * g.Tg;
+        if (g.V <= 0) fail(CWT_EUNSUPPORTED, "internal: segment too short for the halo");
+        g.nseg = (p.N + g.V - 1) / g.V;
+        g.tab_off = (int64_t)tab.size();
+        for (int j : g.scales)
+            for (int m = 0; m < g.L; ++m) {
+                int ms = m < g.L / 2 ? m : m - g.L;
+                tab.push_back(psi_aliased(w, p.scales[j], 2.0 * M_PI * ms / g.L, umax) / g.L);
+            }
+        g.twl_off = fp64 ? push_pass_twiddles<double>(tb, g.L) : push_pass_twiddles<float>(tb, g.L);
+        p.segs.push_back(std::move(g));
+    }
+
+    // BAND groups by (L, P)
+    std::sort(band.begin(), band.end(), [](const Cand &a, const Cand &b) { return a.lg < b.lg || (a.lg == b.lg && a.j < b.j); });
+    for (size_t i = 0; i < band.size();) {
+        SegGroup g;
+        g.kind = SegGroup::BAND;
+        g.lgL = band[i].lg;
+        g.L = 1 << g.lgL;
+        int64_t klo = band[i].klo, khi = band[i].khi;
+        std::vector<int> js;
+        // add scales of the same L while the union band still fits P (capped at pmax and L/16)
+        while (i < band.size() && band[i].lg == g.lgL) {
+            int64_t nlo = std::min(klo, band[i].klo), nhi = std::max(khi, band[i].khi);
+            int64_t P = std::max<int64_t>(64, next_pow2(nhi - nlo + 1));
+            if (!js.empty() && (P > pmax || P * 16 > g.L)) break;
+            klo = nlo;
+            khi = nhi;
+            js.push_back(band[i].j);
+            ++i;
+        }
+        g.klo = klo;
+        g.B = (int32_t)(khi - klo + 1);
+        g.P = (int32_t)std::max<int64_t>(64, next_pow2(g.B));
+        for (int j : js) g.Tg = std::max(g.Tg, p.T[j]);
+        g.V = g.L - 2 * g.Tg;
+        g.nseg = (p.N + g.V - 1) / g.V;
+        const int64_t Q = g.L / g.P;
+        const int64_t iters_total = Q / 16;
+        int64_t nchunk = 1;
+        while (nchunk * 2 <= iters_total && g.nseg * nchunk < 1024 && iters_total / (nchunk * 2) >= 2) nchunk *= 2;
+        g.nchunk = (int32_t)nchunk;
+        g.iters = (int32_t)(iters_total / nchunk);
+        // spectrum samples of each scale on the group band
+        std::vector<int64_t> koff(js.size());
+        for (size_t u = 0; u < js.size(); ++u) {
+            koff[u] = (int64_t)tab.size();
+            for (int64_t m = g.klo; m < g.klo + g.B; ++m)
+                tab.push_back(psi_aliased(w, p.scales[js[u]], 2.0 * M_PI * (double)m / g.L, umax) / g.L);
+        }
+        // w_L^{m g}, g < 16
+        {
+            std::vector<double> gt(2 * 16 * (size_t)g.B);
+            for (int gg = 0; gg < 16; ++gg)
+                for (int k = 0; k < g.B; ++k) {
+                    int64_t x = ((g.klo + k) * gg) & (int64_t)(g.L - 1);
+                    long double a = 2.0L * M_PIl * (long double)x / (long double)g.L;
+                    gt[2 * ((size_t)gg * g.B + k)] = (double)std::cos(a);
+                    gt[2 * ((size_t)gg * g.B + k) + 1] = (double)std::sin(a);
+                }
+            if (fp64) g.gtw_off = tb.add(gt.data(), gt.size() * sizeof(double));
+            else {
+                std::vector<float> g32(gt.begin(), gt.end());
+                g.gtw_off = tb.add(g32.data(), g32.size() * sizeof(float));
+            }
+        }
+        g.twl_off = fp64 ? push_pass_twiddles<double>(tb, g.P) : push_pass_twiddles<float>(tb, g.P);
+        // work items: segment x (scale | scale pair) x 16-column chunk
+        std::vector<std::pair<int, int>> units;
+        if (p.pair_real) {
+            for (size_t u = 0; u < js.size(); u += 2) units.push_back({(int)u, u + 1 < js.size() ? (int)u + 1 : -1});
+        } else {
+            for (size_t u = 0; u < js.size(); ++u) units.push_back({(int)u, -1});
+        }
+        for (int64_t sg = 0; sg < g.nseg; ++sg)
+            for (auto &un : units)
+                for (int64_t r0 = 0; r0 < Q; r0 += 16) {
+                    SegItem it{};
+                    it.seg = (int32_t)sg;
+                    it.sa = js[un.first];
+                    it.sb = un.second >= 0 ? js[un.second] : -1;
+                    it.r0 = (int32_t)r0;
+                    it.ka = koff[un.first];
+                    it.kb = un.second >= 0 ? koff[un.second] : koff[un.first];
+                    g.items.push_back(it);
+                }
+        g.ws_xp_off = ws_take((size_t)g.nseg * g.nchunk * g.B * 16);
+        g.ws_x_off = ws_take((size_t)g.nseg * g.B * 16);
+        p.segs.push_back(std::move(g));
+    }
+    p.ws_bytes = ws;
+    p.tab_elems = (int64_t)tab.size();
+    if (p.host_only) return;
+
+    if (!tab.empty()) {
+        size_t bytes = tab.size() * (fp64 ? 8 : 4);
+        HIPCHK(hipMalloc(&p.d_tab, bytes));
+        p.table_bytes += bytes;
+        if (fp64) {
+            HIPCHK(hipMemcpy(p.d_tab, tab.data(), bytes, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> t32(tab.begin(), tab.end());
+            HIPCHK(hipMemcpy(p.d_tab, t32.data(), bytes, hipMemcpyHostToDevice));
+        }
+    }
+    HIPCHK(hipMalloc(&p.d_tw_all, tb.host.size()));
+    p.table_bytes += tb.host.size();
+    HIPCHK(hipMemcpy(p.d_tw_all, tb.host.data(), tb.host.size(), hipMemcpyHostToDevice));
+    for (auto &g : p.segs) {
+        if (g.kind == SegGroup::LOCAL) {
+            HIPCHK(hipMalloc(&g.d_scales, g.scales.size() * sizeof(int32_t)));
+            p.table_bytes += g.scales.size() * sizeof(int32_t);
+            HIPCHK(hipMemcpy(g.d_scales, g.scales.data(), g.scales.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        } else {
+            size_t bytes = g.items.size() * sizeof(SegItem);
+            HIPCHK(hipMalloc(&g.d_items, bytes));
+            p.table_bytes += bytes;
+            HIPCHK(hipMemcpy(g.d_items, g.items.data(), bytes, hipMemcpyHostToDevice));
+        }
+    }
+}
+
 static void free_plan(Plan *p) {
     if (!p) return;
     if (p->d_tab) (void)hipFree(p->d_tab);
@@ -474,6 +709,10 @@ static void free_plan(Plan *p) {
         if (g.d_scales) (void)hipFree(g.d_scales);
     for (auto &c : p->columns)
         if (c.d_items) (void)hipFree(c.d_items);
+    for (auto &g : p->segs) {
+        if (g.d_scales) (void)hipFree(g.d_scales);
+        if (g.d_items) (void)hipFree(g.d_items);
+    }
     for (void *x : p->d_extra)
         if (x) (void)hipFree(x);
     for (auto &r : p->timing_recs) {
@@ -498,6 +737,8 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
     if (precision != CWT_FP64 && precision != CWT_FP32) fail(CWT_EINVAL, "unknown precision");
     if (method != CWT_METHOD_FFT && method != CWT_METHOD_SPLINE) fail(CWT_EINVAL, "unknown method");
     if (fft_len < 0) fail(CWT_EINVAL, "fft_len must be >= 0");
+    if (opts && opts->fft_mode != CWT_FFT_SEGMENTED && opts->fft_mode != CWT_FFT_WHOLE)
+        fail(CWT_EINVAL, "unknown fft_mode");
     Wavelet w;
     w.kind = wv.kind;
     if (wv.kind == CWT_MORLET) {
@@ -534,7 +775,9 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
         p->T.resize(S);
         for (int j = 0; j < S; ++j) p->T[j] = (int64_t)std::ceil(p->chi * scales[j]);
         if (method == CWT_METHOD_FFT) {
-            build_fft_plan(*p, w, fft_len);
+            p->fft_mode = opts ? opts->fft_mode : CWT_FFT_SEGMENTED;
+            if (p->fft_mode == CWT_FFT_WHOLE) build_fft_plan(*p, w, fft_len);
+            else build_seg_plan(*p, w);
         } else {
             TableBuilder tb;
             build_spline_plan(*p, w, tb);
@@ -679,6 +922,20 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, vo
             return CWT_OK;
         }
         const double fb = p.precision == CWT_FP64 ? 16.0 : 8.0;
+        for (auto &g : p.segs) {
+            if (g.kind == cwt::SegGroup::LOCAL) {
+                cwt::timed(p, st, cwt::seg_kernel_name(p, g, 1), nn * sb + nn * (double)g.scales.size() * eb,
+                           "local launch", [&] { return cwt::launch_local2(p, g, signal, out, st); });
+            } else {
+                double rows = 0.0;
+                for (auto &it : g.items)
+                    if (it.seg == 0 && it.r0 == 0) rows += it.sb >= 0 ? 2.0 : 1.0;
+                cwt::timed(p, st, cwt::seg_kernel_name(p, g, 0), nn * sb + (double)g.nseg * g.B * 16.0,
+                           "segment spectra launch", [&] { return cwt::launch_seg(p, g, signal, workspace, out, st, 0); });
+                cwt::timed(p, st, cwt::seg_kernel_name(p, g, 1), nn * rows * eb + (double)g.nseg * g.B * 16.0,
+                           "segment inverse launch", [&] { return cwt::launch_seg(p, g, signal, workspace, out, st, 1); });
+            }
+        }
         if (p.M > 0)
             cwt::timed(p, st, "forward", nn * sb + (double)p.M * fb, "forward launch",
                        [&] { return cwt::launch_forward(p, signal, workspace, st); });

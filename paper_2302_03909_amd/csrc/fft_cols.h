@@ -1,0 +1,133 @@
+// fft_cols.h -- workgroup FFT of NCOL columns of length P held in LDS, with
+// per-pass twiddle tables in LDS and a last pass that hands every output to
+// a caller functor straight from registers (no final LDS round trip).
+//
+// Pass j has radix R_j (radix_of), sub-transform size Ns_j (ns_before); its
+// twiddles e^{+2 pi i r k / (R_j Ns_j)}, r in [1, R_j), k in [0, Ns_j), sit
+// at twl[twl_off(P, j) + (r - 1) Ns_j + k], so the threads of a wave read
+// consecutive entries.  The table is generated in FP64 on the host and stored
+// in the kernel's precision.
+#pragma once
+#include "fft_device.h"
+
+namespace cwt {
+
+constexpr int twl_off(int P, int pass) {
+    int off = 0;
+    for (int j = 0; j < pass; ++j) {
+        int ns = ns_before(P, j);
+        if (ns > 1) off += (radix_of(P, j) - 1) * ns;
+    }
+    return off;
+}
+constexpr int twl_len(int P) { return twl_off(P, num_passes(P)) > 0 ? twl_off(P, num_passes(P)) : 1; }
+
+// middle pass: LDS -> LDS, column-major thread mapping (consecutive threads
+// take consecutive butterflies of one column)
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS>
+__device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
+    constexpr int R = radix_of(P, PASS);
+    constexpr int NS = ns_before(P, PASS);
+    constexpr int NB = NCOL * (P / R);
+    constexpr int PER = (NB + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    C v[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int gb = tid + q * NT;
+        if (NB % NT == 0 || gb < NB) {
+            int c = gb / (P / R), i = gb % (P / R);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[c * LD + lidx(i + r * (P / R))];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int gb = tid + q * NT;
+        if (NB % NT == 0 || gb < NB) {
+            int c = gb / (P / R), i = gb % (P / R);
+            int k = i % NS;
+            if constexpr (NS > 1) {
+                const C *tp = twl + twl_off(P, PASS) + k;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = tp[(r - 1) * NS];
+                    v[q][r] = SIGN > 0 ? cmul(v[q][r], w) : cmulc(v[q][r], w);
+                }
+            }
+            dftR<R, SIGN>(v[q]);
+            int base = (i - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[c * LD + lidx(base + r * NS)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// last pass: column-fastest thread mapping (consecutive threads take the same
+// butterfly of consecutive columns), outputs go to emit(col, p, value).
+// SYNC: barrier between the LDS reads and the emits (needed when emit writes
+// back into buf).
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC, class F>
+__device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
+    constexpr int PASS = num_passes(P) - 1;
+    constexpr int R = radix_of(P, PASS);
+    constexpr int NS = ns_before(P, PASS);  // = P / R
+    constexpr int NB = NCOL * (P / R);
+    constexpr int PER = (NB + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    C v[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int gb = tid + q * NT;
+        if (NB % NT == 0 || gb < NB) {
+            int c = gb % NCOL, i = gb / NCOL;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[c * LD + lidx(i + r * (P / R))];
+        }
+    }
+    if constexpr (SYNC) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int gb = tid + q * NT;
+        if (NB % NT == 0 || gb < NB) {
+            int c = gb % NCOL, i = gb / NCOL;
+            if constexpr (NS > 1) {
+                const C *tp = twl + twl_off(P, PASS) + i;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = tp[(r - 1) * NS];
+                    v[q][r] = SIGN > 0 ? cmul(v[q][r], w) : cmulc(v[q][r], w);
+                }
+            }
+            dftR<R, SIGN>(v[q]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) emit(c, i + r * NS, v[q][r]);
+        }
+    }
+}
+
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS>
+__device__ __forceinline__ void cols_mid_from(C *buf, const C *twl) {
+    if constexpr (PASS + 1 < num_passes(P)) {
+        cols_pass_mid<C, P, NCOL, NT, LD, SIGN, PASS>(buf, twl);
+        cols_mid_from<C, P, NCOL, NT, LD, SIGN, PASS + 1>(buf, twl);
+    }
+}
+
+// Full transform of NCOL columns in buf (filled and synchronised by the
+// caller).  Outputs are emitted in natural order positions p.
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC_LAST, class F>
+__device__ __forceinline__ void cols_fft(C *buf, const C *twl, F &emit) {
+    cols_mid_from<C, P, NCOL, NT, LD, SIGN, 0>(buf, twl);
+    cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST>(buf, twl, emit);
+}
+
+// copy a per-pass twiddle table from global memory into LDS
+template <typename C, int P, int NT>
+__device__ __forceinline__ void load_twl(C *twl_s, const C *__restrict__ twl_g) {
+    for (int j = threadIdx.x; j < twl_len(P); j += NT) twl_s[j] = twl_g[j];
+}
+
+}  // namespace cwt

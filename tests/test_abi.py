@@ -71,9 +71,26 @@ def test_null_arguments():
     assert lib.cwt_out_elems(None) == -1
 
 
-def test_host_only_plan_fft_paths():
+def test_host_only_plan_segmented_paths():
+    # default (segmented) mode: small scales full-spectrum segments, the rest band-limited
     scales = np.geomspace(2, 2 ** 16, 128)
     p = cwt.Plan(1 << 22, "zero", "morlet", scales, param=6.0, precision="fp32", host_only=True)
+    path = p.scale_path()
+    assert path[0] == cwt.PATH_LOCAL and path[-1] == cwt.PATH_COLUMN
+    assert np.all(np.diff(path) >= 0)  # monotone in scale
+    assert p.fft_len == 0
+    assert 0 < p.workspace_bytes < 256 << 20
+
+
+def test_unknown_fft_mode_rejected():
+    o = cwt._Opts(0, 0, 0, 1, 7)
+    assert _plan_rc(opts=o) == -1
+
+
+def test_host_only_plan_fft_paths():
+    scales = np.geomspace(2, 2 ** 16, 128)
+    p = cwt.Plan(1 << 22, "zero", "morlet", scales, param=6.0, precision="fp32", host_only=True,
+                 fft_mode="whole")
     path = p.scale_path()
     assert set(path.tolist()) <= {cwt.PATH_LOCAL, cwt.PATH_COLUMN}
     assert path[0] == cwt.PATH_LOCAL and path[-1] == cwt.PATH_COLUMN
@@ -90,7 +107,7 @@ def test_host_only_plan_fft_paths():
 
 
 def test_host_only_periodic_smooth_uses_n():
-    p = cwt.Plan(4096 * 9, "periodic", "mexhat", [2.0, 900.0, 3000.0], host_only=True)
+    p = cwt.Plan(4096 * 9, "periodic", "mexhat", [2.0, 900.0, 3000.0], host_only=True, fft_mode="whole")
     assert p.fft_len == 4096 * 9
-    q = cwt.Plan(5000, "periodic", "mexhat", [2.0, 900.0], host_only=True)
+    q = cwt.Plan(5000, "periodic", "mexhat", [2.0, 900.0], host_only=True, fft_mode="whole")
     assert q.fft_len >= 5000 + 2 * math.ceil(8 * 900)

@@ -26,9 +26,10 @@ def torch_cuda():
     return torch
 
 
-def gpu_cwt(torch, f, bc, wav, par, scales, precision, method="fft", fft_len=0):
+def gpu_cwt(torch, f, bc, wav, par, scales, precision, method="fft", fft_len=0, fft_mode="segmented"):
     import paper_2302_03909_amd as cwt
-    plan = cwt.Plan(f.size, bc, wav, scales, param=par, precision=precision, method=method, fft_len=fft_len)
+    plan = cwt.Plan(f.size, bc, wav, scales, param=par, precision=precision, method=method, fft_len=fft_len,
+                    fft_mode=fft_mode)
     dt = torch.float64 if precision == "fp64" else torch.float32
     x = torch.as_tensor(f, dtype=dt, device="cuda")
     w = plan(x)
@@ -40,9 +41,9 @@ def ref_input(f, precision):
     return f.astype(np.float32).astype(np.float64) if precision == "fp32" else f
 
 
-def check_full(torch, f, bc, wav, par, scales, precision, expect_paths=None, fft_len=0):
-    print(f"case N={f.size} bc={bc} wav={wav}({par}) S={len(scales)} {precision}", flush=True)
-    plan, w = gpu_cwt(torch, f, bc, wav, par, scales, precision, fft_len=fft_len)
+def check_full(torch, f, bc, wav, par, scales, precision, expect_paths=None, fft_len=0, fft_mode="segmented"):
+    print(f"case N={f.size} bc={bc} wav={wav}({par}) S={len(scales)} {precision} {fft_mode}", flush=True)
+    plan, w = gpu_cwt(torch, f, bc, wav, par, scales, precision, fft_len=fft_len, fft_mode=fft_mode)
     got = w.cpu().numpy()
     ref = oracle.cwt(ref_input(f, precision), bc, wav, scales, param=par)
     err = per_scale_rel_l2(got, ref)
@@ -53,14 +54,17 @@ def check_full(torch, f, bc, wav, par, scales, precision, expect_paths=None, fft
     return err
 
 
-def test_small_periodic_morlet_fp64(torch_cuda):
+@pytest.mark.parametrize("fft_mode", ["segmented", "whole"])
+def test_small_periodic_morlet_fp64(torch_cuda, fft_mode):
     # N = 4096 periodic tones + noise, Morlet(6), 32 log scales 2..512
     f = synth.tones_noise(4096)
     scales = synth.log_scales(2.0, 512.0, 32)
-    err = check_full(torch_cuda, f, "periodic", "morlet", 6.0, scales, "fp64", expect_paths={0, 1})
+    err = check_full(torch_cuda, f, "periodic", "morlet", 6.0, scales, "fp64", expect_paths={0, 1},
+                     fft_mode=fft_mode)
     print("max rel L2", err.max())
 
 
+@pytest.mark.parametrize("fft_mode", ["segmented", "whole"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("n,bc,wav,par,scales", [
     (3001, "zero", "mexhat", None, [1.5, 2.0, 9.0, 40.0, 150.0, 700.0]),
@@ -70,18 +74,19 @@ def test_small_periodic_morlet_fp64(torch_cuda):
     (1024, "zero", "dog", 4.0, [2.5, 64.0, 300.0]),
     (777, "periodic", "dog", 1.0, [1.2, 50.0]),
 ])
-def test_parity_mixed(torch_cuda, precision, n, bc, wav, par, scales):
+def test_parity_mixed(torch_cuda, precision, n, bc, wav, par, scales, fft_mode):
     rng = np.random.default_rng(n)
     f = rng.standard_normal(n) + 0.3
-    check_full(torch_cuda, f, bc, wav, par, scales, precision)
+    check_full(torch_cuda, f, bc, wav, par, scales, precision, fft_mode=fft_mode)
 
 
+@pytest.mark.parametrize("fft_mode", ["segmented", "whole"])
 @pytest.mark.parametrize("n", [2, 3, 17])
 @pytest.mark.parametrize("bc", ["periodic", "zero"])
-def test_degenerate_lengths(torch_cuda, n, bc):
+def test_degenerate_lengths(torch_cuda, n, bc, fft_mode):
     f = np.random.default_rng(5).standard_normal(n)
-    check_full(torch_cuda, f, bc, "morlet", 6.0, [1.0, 2.0, 40.0], "fp64")
-    check_full(torch_cuda, f, bc, "mexhat", None, [0.7, 5.0], "fp64")
+    check_full(torch_cuda, f, bc, "morlet", 6.0, [1.0, 2.0, 40.0], "fp64", fft_mode=fft_mode)
+    check_full(torch_cuda, f, bc, "mexhat", None, [0.7, 5.0], "fp64", fft_mode=fft_mode)
 
 
 def test_single_scale_and_constant_signal(torch_cuda):
@@ -97,16 +102,17 @@ def test_fft_len_override_gives_same_result(torch_cuda):
     scales = [2.0, 50.0, 600.0, 1500.0]
     import paper_2302_03909_amd as cwt
     p = cwt.Plan(f.size, "zero", "mexhat", scales, host_only=True)
-    _, a = gpu_cwt(torch_cuda, f, "zero", "mexhat", None, scales, "fp64")
-    _, b = gpu_cwt(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", fft_len=5 * 4096)
+    p = cwt.Plan(f.size, "zero", "mexhat", scales, host_only=True, fft_mode="whole")
+    _, a = gpu_cwt(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", fft_mode="whole")
+    _, b = gpu_cwt(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", fft_len=5 * 4096, fft_mode="whole")
     assert p.fft_len != 5 * 4096
     ref = oracle.cwt(f, "zero", "mexhat", scales)
     assert per_scale_rel_l2(a.cpu().numpy(), ref).max() < 1e-10
     assert per_scale_rel_l2(b.cpu().numpy(), ref).max() < 1e-10
 
 
-def sampled_check(torch, f, bc, wav, par, scales, precision, npos=48, seed=0):
-    plan, w = gpu_cwt(torch, f, bc, wav, par, scales, precision)
+def sampled_check(torch, f, bc, wav, par, scales, precision, npos=48, seed=0, fft_mode="segmented"):
+    plan, w = gpu_cwt(torch, f, bc, wav, par, scales, precision, fft_mode=fft_mode)
     n = f.size
     rng = np.random.default_rng(seed)
     pos = np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.integers(0, n, npos - 5)])
@@ -123,20 +129,23 @@ def sampled_check(torch, f, bc, wav, par, scales, precision, npos=48, seed=0):
     return plan, err
 
 
-def test_full_size_fp64_mexhat_1m(torch_cuda):
+@pytest.mark.parametrize("fft_mode", ["segmented", "whole"])
+def test_full_size_fp64_mexhat_1m(torch_cuda, fft_mode):
     # N = 2^20 zero-boundary lognormal field, Mexican hat, 64 log scales 2..2^14, FP64
     f = synth.lognormal_field(1 << 20, seed=synth.SEED_FIELD_1M)
     scales = synth.log_scales(2.0, 2.0 ** 14, 64)
-    plan, err = sampled_check(torch_cuda, f, "zero", "mexhat", None, scales, "fp64")
+    plan, err = sampled_check(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", fft_mode=fft_mode)
     print("fp64 1M max err", err.max(), "M", plan.fft_len)
     assert err.max() <= 1e-10
 
 
+@pytest.mark.parametrize("fft_mode", ["segmented", "whole"])
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
 @pytest.mark.parametrize("wav,par", [("morlet", 6.0), ("dog", 2.0)])
-def test_full_size_fp32_4m(torch_cuda, wav, par):
-    # N = 2^22 zero-boundary lognormal field, 128 log scales 2..2^16, FP32 form
+def test_full_size_fp32_4m(torch_cuda, wav, par, bc, fft_mode):
+    # N = 2^22 lognormal field, 128 log scales 2..2^16, FP32 form
     f = synth.lognormal_field(1 << 22, seed=synth.SEED_FIELD_4M)
     scales = synth.log_scales(2.0, 2.0 ** 16, 128)
-    plan, err = sampled_check(torch_cuda, f, "zero", wav, par, scales, "fp32", npos=40)
-    print(f"fp32 4M {wav} max err", err.max(), "M", plan.fft_len)
+    plan, err = sampled_check(torch_cuda, f, bc, wav, par, scales, "fp32", npos=40, fft_mode=fft_mode)
+    print(f"fp32 4M {wav} {bc} {fft_mode} max err", err.max(), "median", np.median(err))
     assert err.max() <= 1e-5
