@@ -39,13 +39,6 @@ struct ColumnDesc {
     int64_t taba, tabb;  // offsets of the spectrum samples of sa / sb
 };
 
-// Work item of the segmented inverse: one segment, one scale (or a pair of
-// real-wavelet scales sharing the transform) and 16 consecutive columns.
-struct SegItem {
-    int32_t seg, sa, sb, r0;
-    int64_t ka, kb;  // offsets of the spectrum samples of sa / sb
-};
-
 // A group of scales transformed with the same segment length L = 2^lgL.
 //   LOCAL: full L-point spectrum, fused kernel (NCOL segments per workgroup)
 //   BAND:  spectrum needed on [klo, klo + B) only, B <= P, L = P * Q
@@ -56,14 +49,47 @@ struct SegGroup {
     int64_t Tg = 0, V = 0, nseg = 0;
     int64_t klo = 0;
     int32_t B = 0, nchunk = 1, iters = 1;
-    std::vector<int32_t> scales;  // LOCAL: scale indices (table rows in order)
+    std::vector<int32_t> scales;  // scale indices (LOCAL: table rows in order)
     int64_t tab_off = 0;          // LOCAL: offset (elements) of the L-point tables
     int32_t *d_scales = nullptr;
-    std::vector<SegItem> items;  // BAND
-    SegItem *d_items = nullptr;
-    int64_t twl_off = -1;  // per-pass LDS twiddle table of size L (LOCAL) or P (BAND), bytes
+    int64_t twl_off = -1;  // LOCAL: per-pass LDS twiddle table of size L, bytes
     int64_t gtw_off = -1;  // BAND: w_L^{m g}, g < 16, m in band, bytes
     size_t ws_xp_off = 0, ws_x_off = 0;
+    int32_t unit0 = 0, nunits = 0;  // BAND: range in Plan::units
+};
+
+// device copy of a BAND group's parameters
+struct SegGroupDev {
+    int32_t lgL, B, nchunk, iters;
+    int32_t unit0, nunits;
+    int64_t V, Tg, klo, nseg;
+    int64_t xp_off, x_off;  // workspace byte offsets of the partial and reduced band spectra
+    int64_t gtw_off;        // byte offset of w_L^{m g} in the twiddle allocation
+};
+
+// one output unit of a BAND group: a scale, or a pair of real-wavelet scales
+// sharing one complex transform (sb = -1: none)
+struct SegUnit {
+    int32_t sa, sb;
+    int64_t ka, kb;  // offsets of their spectrum samples in the spectrum table
+};
+
+// one workgroup of a fused launch: group g, segment seg, and idx = column
+// chunk (forward), 16-bin block (reduce) or first column r0 (inverse)
+struct SegWork {
+    int32_t g, seg, idx, pad;
+};
+
+// all BAND groups that share P, launched together
+struct SegLaunch {
+    int32_t P = 0;
+    int64_t twl_off = -1;  // per-pass twiddle table of size P, bytes
+    std::vector<int32_t> groups;  // indices into Plan::segs
+    std::vector<SegGroupDev> gdev;
+    std::vector<SegWork> fwd, red, inv;
+    SegGroupDev *d_groups = nullptr;
+    SegWork *d_fwd = nullptr, *d_red = nullptr, *d_inv = nullptr;
+    double out_rows = 0.0;  // output rows written by the launch (for timing)
 };
 
 struct ColumnLaunch {
@@ -101,6 +127,9 @@ struct Plan {
     std::vector<LocalGroup> groups;
     std::vector<ColumnLaunch> columns;
     std::vector<SegGroup> segs;
+    std::vector<SegLaunch> seg_launches;
+    std::vector<SegUnit> units;
+    SegUnit *d_units = nullptr;
     int32_t fft_mode = 0;  // 0 segmented, 1 whole signal
     int64_t w23_hi_off = -1, w23_lo_off = -1;  // FP64 w_{2^23} tables, bytes
     bool pair_real = false;
@@ -138,10 +167,11 @@ struct Plan {
 };
 
 hipError_t launch_local2(const Plan &p, const SegGroup &g, const void *signal, void *out, hipStream_t st);
-// phase 0: segment spectra (forward + reduce); phase 1: inverse (BAND groups)
-hipError_t launch_seg(const Plan &p, const SegGroup &g, const void *signal, void *ws, void *out, hipStream_t st,
+// phase 0: band spectra of the segments (forward), 1: their reduction, 2: inverse
+hipError_t launch_seg(const Plan &p, const SegLaunch &l, const void *signal, void *ws, void *out, hipStream_t st,
                       int phase);
-std::string seg_kernel_name(const Plan &p, const SegGroup &g, int phase);
+std::string local2_kernel_name(const Plan &p, const SegGroup &g);
+std::string seg_kernel_name(const Plan &p, const SegLaunch &l, int phase);
 bool local2_size_ok(int L, int precision);
 bool seg_size_ok(int P, int precision);
 int local2_segs_per_block(int L, bool pair);

@@ -521,10 +521,17 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
 // at that length spans a sixteenth of L or more, the scale joins a LOCAL
 // group (full-spectrum fused kernel); otherwise a BAND group keyed by (L, P)
 // with P >= the band width.
+// Halo of a segment group, rounded up to 16 samples: the kept outputs of
+// every segment then start on a 16-sample boundary (V = L - 2 Tg is a
+// multiple of 16 too), so the 16-column output runs of the kernels fill whole
+// cache lines instead of straddling two.  Any halo >= the largest T of the
+// group gives the same outputs.
+static int64_t align_halo(int64_t t) { return (t + 15) & ~int64_t(15); }
+
 static void build_seg_plan(Plan &p, const Wavelet &w) {
     const bool fp64 = p.precision == CWT_FP64;
     const int lmax_local = fp64 ? 4096 : 8192;
-    const int pmax = fp64 ? 512 : 1024;
+    const int pmax = 512;
     const int lg_max = 23;
     double ulo, uhi;
     spectral_band(w, p.rel, ulo, uhi);
@@ -577,6 +584,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             g.Tg = std::max(g.Tg, p.T[loc[i].j]);
             ++i;
         }
+        g.Tg = align_halo(g.Tg);
         g.V = g.L - 2 * g.Tg;
         if (g.V <= 0) fail(CWT_EUNSUPPORTED, "internal: segment too short for the halo");
         g.nseg = (p.N + g.V - 1) / g.V;
@@ -590,8 +598,10 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         p.segs.push_back(std::move(g));
     }
 
-    // BAND groups by (L, P)
+    // BAND groups by (L, P), at most kMaxUnits output units each
+    const int kMaxUnits = 32;
     std::sort(band.begin(), band.end(), [](const Cand &a, const Cand &b) { return a.lg < b.lg || (a.lg == b.lg && a.j < b.j); });
+    const int per_unit = p.pair_real ? 2 : 1;
     for (size_t i = 0; i < band.size();) {
         SegGroup g;
         g.kind = SegGroup::BAND;
@@ -600,25 +610,39 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         int64_t klo = band[i].klo, khi = band[i].khi;
         std::vector<int> js;
         // add scales of the same L while the union band still fits P (capped at pmax and L/16)
-        while (i < band.size() && band[i].lg == g.lgL) {
+        while (i < band.size() && band[i].lg == g.lgL && (int)js.size() < kMaxUnits * per_unit) {
             int64_t nlo = std::min(klo, band[i].klo), nhi = std::max(khi, band[i].khi);
             int64_t P = std::max<int64_t>(64, next_pow2(nhi - nlo + 1));
             if (!js.empty() && (P > pmax || P * 16 > g.L)) break;
+            // the inverse stages all spectrum samples of a group in 16 KiB of LDS
+            int64_t kls_cap = std::max<int64_t>(2 * P, 16384 / (fp64 ? 8 : 4));
+            // (a real-wavelet pair takes two tables even when its second scale is absent)
+            int64_t ntab = ((int64_t)js.size() + 1 + per_unit - 1) / per_unit * per_unit;
+            if (!js.empty() && ntab * (nhi - nlo + 1) > kls_cap) break;
             klo = nlo;
             khi = nhi;
             js.push_back(band[i].j);
             ++i;
         }
+        g.scales.assign(js.begin(), js.end());
         g.klo = klo;
         g.B = (int32_t)(khi - klo + 1);
         g.P = (int32_t)std::max<int64_t>(64, next_pow2(g.B));
+        {
+            int64_t ntab = ((int64_t)js.size() + per_unit - 1) / per_unit * per_unit;
+            if (ntab * g.B > std::max<int64_t>(2 * g.P, 16384 / (fp64 ? 8 : 4)))
+                fail(CWT_EUNSUPPORTED, "internal: band group tables exceed the staging area");
+        }
         for (int j : js) g.Tg = std::max(g.Tg, p.T[j]);
+        g.Tg = align_halo(g.Tg);
         g.V = g.L - 2 * g.Tg;
         g.nseg = (p.N + g.V - 1) / g.V;
         const int64_t Q = g.L / g.P;
         const int64_t iters_total = Q / 16;
+        // column chunks of the forward: enough workgroups to fill the device,
+        // at most 256 partial sums per bin
         int64_t nchunk = 1;
-        while (nchunk * 2 <= iters_total && g.nseg * nchunk < 1024 && iters_total / (nchunk * 2) >= 2) nchunk *= 2;
+        while (nchunk * 2 <= iters_total && nchunk * 2 <= 256 && g.nseg * nchunk < 2048) nchunk *= 2;
         g.nchunk = (int32_t)nchunk;
         g.iters = (int32_t)(iters_total / nchunk);
         // spectrum samples of each scale on the group band
@@ -644,28 +668,57 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
                 g.gtw_off = tb.add(g32.data(), g32.size() * sizeof(float));
             }
         }
-        g.twl_off = fp64 ? push_pass_twiddles<double>(tb, g.P) : push_pass_twiddles<float>(tb, g.P);
-        // work items: segment x (scale | scale pair) x 16-column chunk
-        std::vector<std::pair<int, int>> units;
-        if (p.pair_real) {
-            for (size_t u = 0; u < js.size(); u += 2) units.push_back({(int)u, u + 1 < js.size() ? (int)u + 1 : -1});
-        } else {
-            for (size_t u = 0; u < js.size(); ++u) units.push_back({(int)u, -1});
+        // output units: single scales (complex output) or pairs (real output)
+        g.unit0 = (int32_t)p.units.size();
+        for (size_t u = 0; u < js.size(); u += per_unit) {
+            SegUnit un{};
+            un.sa = js[u];
+            un.ka = koff[u];
+            if (p.pair_real && u + 1 < js.size()) {
+                un.sb = js[u + 1];
+                un.kb = koff[u + 1];
+            } else {
+                un.sb = -1;
+                un.kb = koff[u];
+            }
+            p.units.push_back(un);
         }
-        for (int64_t sg = 0; sg < g.nseg; ++sg)
-            for (auto &un : units)
-                for (int64_t r0 = 0; r0 < Q; r0 += 16) {
-                    SegItem it{};
-                    it.seg = (int32_t)sg;
-                    it.sa = js[un.first];
-                    it.sb = un.second >= 0 ? js[un.second] : -1;
-                    it.r0 = (int32_t)r0;
-                    it.ka = koff[un.first];
-                    it.kb = un.second >= 0 ? koff[un.second] : koff[un.first];
-                    g.items.push_back(it);
-                }
+        g.nunits = (int32_t)p.units.size() - g.unit0;
         g.ws_xp_off = ws_take((size_t)g.nseg * g.nchunk * g.B * 16);
         g.ws_x_off = ws_take((size_t)g.nseg * g.B * 16);
+        // attach to the launch of its P
+        SegLaunch *sl = nullptr;
+        for (auto &l : p.seg_launches)
+            if (l.P == g.P) sl = &l;
+        if (!sl) {
+            p.seg_launches.push_back(SegLaunch{});
+            sl = &p.seg_launches.back();
+            sl->P = g.P;
+            sl->twl_off = fp64 ? push_pass_twiddles<double>(tb, g.P) : push_pass_twiddles<float>(tb, g.P);
+        }
+        const int32_t gi = (int32_t)sl->gdev.size();
+        SegGroupDev gd{};
+        gd.lgL = g.lgL;
+        gd.B = g.B;
+        gd.nchunk = g.nchunk;
+        gd.iters = g.iters;
+        gd.unit0 = g.unit0;
+        gd.nunits = g.nunits;
+        gd.V = g.V;
+        gd.Tg = g.Tg;
+        gd.klo = g.klo;
+        gd.nseg = g.nseg;
+        gd.xp_off = (int64_t)g.ws_xp_off;
+        gd.x_off = (int64_t)g.ws_x_off;
+        gd.gtw_off = g.gtw_off;
+        sl->gdev.push_back(gd);
+        sl->groups.push_back((int32_t)p.segs.size());
+        sl->out_rows += (double)js.size();
+        for (int64_t sg = 0; sg < g.nseg; ++sg) {
+            for (int32_t c = 0; c < g.nchunk; ++c) sl->fwd.push_back({gi, (int32_t)sg, c, 0});
+            for (int32_t kb = 0; kb * 16 < g.B; ++kb) sl->red.push_back({gi, (int32_t)sg, kb, 0});
+            for (int64_t r0 = 0; r0 < Q; r0 += 16) sl->inv.push_back({gi, (int32_t)sg, (int32_t)r0, 0});
+        }
         p.segs.push_back(std::move(g));
     }
     p.ws_bytes = ws;
@@ -686,17 +739,21 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     HIPCHK(hipMalloc(&p.d_tw_all, tb.host.size()));
     p.table_bytes += tb.host.size();
     HIPCHK(hipMemcpy(p.d_tw_all, tb.host.data(), tb.host.size(), hipMemcpyHostToDevice));
-    for (auto &g : p.segs) {
-        if (g.kind == SegGroup::LOCAL) {
-            HIPCHK(hipMalloc(&g.d_scales, g.scales.size() * sizeof(int32_t)));
-            p.table_bytes += g.scales.size() * sizeof(int32_t);
-            HIPCHK(hipMemcpy(g.d_scales, g.scales.data(), g.scales.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        } else {
-            size_t bytes = g.items.size() * sizeof(SegItem);
-            HIPCHK(hipMalloc(&g.d_items, bytes));
-            p.table_bytes += bytes;
-            HIPCHK(hipMemcpy(g.d_items, g.items.data(), bytes, hipMemcpyHostToDevice));
-        }
+    auto upload = [&](const void *src, size_t bytes, void **dst) {
+        if (bytes == 0) return;
+        HIPCHK(hipMalloc(dst, bytes));
+        p.table_bytes += bytes;
+        HIPCHK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    };
+    for (auto &g : p.segs)
+        if (g.kind == SegGroup::LOCAL)
+            upload(g.scales.data(), g.scales.size() * sizeof(int32_t), reinterpret_cast<void **>(&g.d_scales));
+    upload(p.units.data(), p.units.size() * sizeof(SegUnit), reinterpret_cast<void **>(&p.d_units));
+    for (auto &l : p.seg_launches) {
+        upload(l.gdev.data(), l.gdev.size() * sizeof(SegGroupDev), reinterpret_cast<void **>(&l.d_groups));
+        upload(l.fwd.data(), l.fwd.size() * sizeof(SegWork), reinterpret_cast<void **>(&l.d_fwd));
+        upload(l.red.data(), l.red.size() * sizeof(SegWork), reinterpret_cast<void **>(&l.d_red));
+        upload(l.inv.data(), l.inv.size() * sizeof(SegWork), reinterpret_cast<void **>(&l.d_inv));
     }
 }
 
@@ -709,9 +766,14 @@ static void free_plan(Plan *p) {
         if (g.d_scales) (void)hipFree(g.d_scales);
     for (auto &c : p->columns)
         if (c.d_items) (void)hipFree(c.d_items);
-    for (auto &g : p->segs) {
+    for (auto &g : p->segs)
         if (g.d_scales) (void)hipFree(g.d_scales);
-        if (g.d_items) (void)hipFree(g.d_items);
+    if (p->d_units) (void)hipFree(p->d_units);
+    for (auto &l : p->seg_launches) {
+        if (l.d_groups) (void)hipFree(l.d_groups);
+        if (l.d_fwd) (void)hipFree(l.d_fwd);
+        if (l.d_red) (void)hipFree(l.d_red);
+        if (l.d_inv) (void)hipFree(l.d_inv);
     }
     for (void *x : p->d_extra)
         if (x) (void)hipFree(x);
@@ -922,19 +984,19 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, vo
             return CWT_OK;
         }
         const double fb = p.precision == CWT_FP64 ? 16.0 : 8.0;
-        for (auto &g : p.segs) {
-            if (g.kind == cwt::SegGroup::LOCAL) {
-                cwt::timed(p, st, cwt::seg_kernel_name(p, g, 1), nn * sb + nn * (double)g.scales.size() * eb,
+        for (auto &g : p.segs)
+            if (g.kind == cwt::SegGroup::LOCAL)
+                cwt::timed(p, st, cwt::local2_kernel_name(p, g), nn * sb + nn * (double)g.scales.size() * eb,
                            "local launch", [&] { return cwt::launch_local2(p, g, signal, out, st); });
-            } else {
-                double rows = 0.0;
-                for (auto &it : g.items)
-                    if (it.seg == 0 && it.r0 == 0) rows += it.sb >= 0 ? 2.0 : 1.0;
-                cwt::timed(p, st, cwt::seg_kernel_name(p, g, 0), nn * sb + (double)g.nseg * g.B * 16.0,
-                           "segment spectra launch", [&] { return cwt::launch_seg(p, g, signal, workspace, out, st, 0); });
-                cwt::timed(p, st, cwt::seg_kernel_name(p, g, 1), nn * rows * eb + (double)g.nseg * g.B * 16.0,
-                           "segment inverse launch", [&] { return cwt::launch_seg(p, g, signal, workspace, out, st, 1); });
-            }
+        for (auto &l : p.seg_launches) {
+            double xbytes = 0.0;
+            for (auto &gd : l.gdev) xbytes += (double)gd.nseg * gd.B * 16.0;
+            cwt::timed(p, st, cwt::seg_kernel_name(p, l, 0), nn * sb * (double)l.gdev.size() + xbytes,
+                       "segment spectra launch", [&] { return cwt::launch_seg(p, l, signal, workspace, out, st, 0); });
+            cwt::timed(p, st, cwt::seg_kernel_name(p, l, 1), 2.0 * xbytes, "segment reduce launch",
+                       [&] { return cwt::launch_seg(p, l, signal, workspace, out, st, 1); });
+            cwt::timed(p, st, cwt::seg_kernel_name(p, l, 2), nn * l.out_rows * eb + xbytes, "segment inverse launch",
+                       [&] { return cwt::launch_seg(p, l, signal, workspace, out, st, 2); });
         }
         if (p.M > 0)
             cwt::timed(p, st, "forward", nn * sb + (double)p.M * fb, "forward launch",

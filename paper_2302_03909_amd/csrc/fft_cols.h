@@ -124,6 +124,27 @@ __device__ __forceinline__ void cols_fft(C *buf, const C *twl, F &emit) {
     cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST>(buf, twl, emit);
 }
 
+// Pass 0 (radix 16, Ns = 1) from registers: thread t owns butterfly
+// (c, i) = (t / (P/16), t % (P/16)) with inputs v[r] = x_c[i + r P/16]; the
+// outputs go to LDS and the function ends with a barrier.
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN>
+__device__ __forceinline__ void cols_pass0_regs(C *buf, C *v) {
+    static_assert(radix_of(P, 0) == 16 && NCOL * (P / 16) == NT, "one radix-16 butterfly per thread");
+    const int c = threadIdx.x / (P / 16), i = threadIdx.x % (P / 16);
+    dftR<16, SIGN>(v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[c * LD + lidx(i * 16 + r)] = v[r];
+    __syncthreads();
+}
+
+// remaining passes after cols_pass0_regs
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC_LAST, class F>
+__device__ __forceinline__ void cols_fft_after0(C *buf, const C *twl, F &emit) {
+    static_assert(num_passes(P) >= 2, "at least two passes");
+    cols_mid_from<C, P, NCOL, NT, LD, SIGN, 1>(buf, twl);
+    cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST>(buf, twl, emit);
+}
+
 // copy a per-pass twiddle table from global memory into LDS
 template <typename C, int P, int NT>
 __device__ __forceinline__ void load_twl(C *twl_s, const C *__restrict__ twl_g) {
