@@ -8,7 +8,7 @@ lognormal field, complex Morlet (omega0 = 6), 128 log-spaced scales 2..2^16,
 FP32 form.  Prints one JSON line (see the fields below).
 
     python bench.py [--steps K] [--warmup W] [--wavelet morlet|dog2]
-                    [--boundary zero|periodic] [--no-cpu-baseline]
+                    [--boundary zero|periodic] [--no-cpu-baseline] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -26,11 +26,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
 def kernel_source_hash() -> str:
+    """Hash of every kernel and plan source: counter figures taken on other
+    sources are not reported."""
     h = hashlib.sha256()
-    for f in ("cwt_fft.hip", "fft_device.h", "cwt_plan.cpp", "cwt_spline.hip"):
-        p = os.path.join(HERE, "paper_2302_03909_amd", "csrc", f)
-        if os.path.exists(p):
-            h.update(open(p, "rb").read())
+    d = os.path.join(HERE, "paper_2302_03909_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -50,7 +53,7 @@ def measured_traffic(kernel: str, workload: str):
     return e.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(f, boundary, wavelet, param, scales, seconds=12.0):
+def cpu_baseline(f, boundary, wavelet, param, scales, seconds=10.0):
     """The FP64 oracle on a uniform random sample of the workload's outputs
     (scale, position), so the per-output cost matches the whole workload."""
     import numpy as np
@@ -67,11 +70,12 @@ def cpu_baseline(f, boundary, wavelet, param, scales, seconds=12.0):
         oracle.cwt_points(f64, boundary, wavelet, scales, si, ps, param=param, nthreads=threads)
         return time.perf_counter() - t0
 
-    count = 4000
-    t = run(count)
-    if t < seconds / 3:
-        count = int(count * min(200.0, seconds / max(t, 1e-3)))
+    count = 2000
+    while True:
         t = run(count)
+        if t >= seconds:
+            break
+        count = int(count * min(8.0, max(1.5, 1.2 * seconds / max(t, 1e-3))))
     return {"value": count / t, "unit": "coefficients/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} outputs drawn uniformly over the {s} x {n} outputs of the workload "
                       f"(FP64 direct sum), {t:.1f} s"}
@@ -85,6 +89,9 @@ def main():
     ap.add_argument("--wavelet", default="morlet", choices=["morlet", "dog2"])
     ap.add_argument("--boundary", default="zero", choices=["zero", "periodic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, copy 1 GiB device-to-device 3 times (a plain copy "
+                         "kernel of known size, for scaling HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -141,6 +148,14 @@ def main():
     whole = {"output_bytes": out_bytes, "hbm_frac_of_output_write": round(out_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "kernels": {k: {"launches": v[0], "ms_per_step": round(v[1] / args.steps, 4),
                              "bytes_per_launch": v[2]} for k, v in kern.items()}}
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
