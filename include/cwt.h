@@ -26,7 +26,15 @@
  *                        interpolant of the samples with the cubic-spline
  *                        approximation of the wavelet at step h_s = delta_s/s,
  *                        delta_s = max(1, floor(h* s)), h* the step where the
- *                        approximation error of Eq. m02cwt_error is 5e-4.
+ *                        approximation error of Eq. m02cwt_error is 5e-4
+ *                        (the wavelet's truncation radius taken where |psi|
+ *                        falls below 1e-14 of its maximum).  Its coefficients
+ *                        d_s interpolate psi(h_s k), |k| <= N_d with N_d =
+ *                        ceil(chi / h_s - 2) + 2, chi at 1e-17.  The running
+ *                        sums of Eq. cumsum4_coeffs are exact (128-bit
+ *                        fixed point), so the result matches that exact
+ *                        spline CWT to FP64 rounding at any N; the output is
+ *                        FP64 or FP32 (precision), the arithmetic FP64.
  *
  * Wavelets (unit L2 norm, psi^(w) = int psi(x) e^{-iwx} dx):
  *   CWT_MORLET(w0): C (e^{i w0 x} - e^{-w0^2/2}) e^{-x^2/2} (complex output;
@@ -122,7 +130,11 @@ typedef struct {
  * omega0 <= 0 or not finite, a DOG order that is not an integer in [1, 16],
  * an unknown kind/boundary/precision/method, out == NULL or scales == NULL;
  * CWT_EUNSUPPORTED for N > 2^26, S > 65536, an fft_len that is too short or
- * not of the supported form, or (spline method) a scale below 1;
+ * not of the supported form, or (spline method) a knot spacing delta_s
+ * above about 2^18.4 (the 128-bit running sums then keep fewer than 40
+ * fixed-point bits), more
+ * than 4081 wavelet coefficients at one scale, or N + 2 (N_d + 3) delta_s
+ * above 2^31;
  * CWT_ENOMEM / CWT_EDEVICE on allocation or HIP failures.
  * On failure *out is set to NULL.
  */

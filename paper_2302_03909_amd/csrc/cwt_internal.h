@@ -98,11 +98,20 @@ struct ColumnLaunch {
     ColumnDesc *d_items = nullptr;
 };
 
-// Spline method, one work item per (scale, tile).
-struct SplineScale {
-    int32_t delta = 0, nd = 0;
-    int64_t dtab_off = 0;  // offset (complex FP64 elements) of d_s
-    double kscale = 0.0;   // 1 / (s delta^3)
+// Spline method (Sec. 3.3 with integer knot spacing, see cwt_spline.hip).
+// Per scale: knot spacing delta, wavelet coefficients d'[n] = conj(d[n - nd]) /
+// (5040 s delta^3), n < ntap (2 nd + 1 taps, zero-padded to a multiple of 16),
+// and the tile shape: R columns (consecutive positions) x I rows (stride delta).
+struct SplineScaleDev {
+    int32_t delta, nd, ntap, R, I, pad;
+    int64_t d_off;  // complex FP64 elements into the plan's coefficient table
+};
+
+// one workgroup of the tap-sum launch: scale j, rows [i0, i0 + I), columns
+// [r0, r0 + R) of the (row = x / delta, column = x mod delta) view of x
+struct SplineWork {
+    int32_t j, r0, R, pad;
+    int64_t i0;
 };
 
 struct Plan {
@@ -136,8 +145,17 @@ struct Plan {
 
     // spline method
     double hstar = 0.0;
-    std::vector<SplineScale> spl;
+    std::vector<SplineScaleDev> spl;
+    std::vector<SplineWork> spl_work;
     std::vector<int32_t> spl_delta;
+    int64_t spl_E = 0;      // the running sums cover positions [-E, N + E)
+    int64_t spl_len = 0;    // N + 2E
+    int32_t spl_qbits = 0;  // bits of the fixed-point coefficients
+    int32_t spl_nb0 = 0;    // blocks of the max|f| reduction
+    int32_t spl_nblk = 0;   // blocks of the running sums
+    SplineScaleDev *d_spl = nullptr;
+    SplineWork *d_spl_work = nullptr;
+    size_t ws_maxp_off = 0, ws_fx_off = 0, ws_state_off = 0, ws_carry_off = 0, ws_H_off = 0;
 
     // device tables (owned)
     void *d_tab = nullptr;  // spectrum samples, plan precision (real)
@@ -162,7 +180,6 @@ struct Plan {
 
     size_t ws_bytes = 0;
     size_t ws_F_off = 0, ws_Y_off = 0;  // workspace layout (FFT method)
-    size_t ws_c_off = 0, ws_e_off = 0;  // workspace layout (spline method)
     size_t table_bytes = 0;
 };
 
@@ -186,7 +203,9 @@ hipError_t launch_local(const Plan &p, const LocalGroup &g, const void *signal, 
                         hipStream_t st);
 hipError_t launch_column(const Plan &p, const ColumnLaunch &c, const void *ws, void *out,
                          hipStream_t st);
-hipError_t launch_spline(const Plan &p, const void *signal, void *out, void *ws, hipStream_t st);
+// phase 0: fixed-point running sums of the spline coefficients, 1: tap sums
+hipError_t launch_spline(const Plan &p, const void *signal, void *out, void *ws, hipStream_t st, int phase);
+std::string spline_kernel_name(const Plan &p, int phase);
 
 // supported sizes
 bool local_size_ok(int L, int precision);

@@ -16,65 +16,11 @@
 
 #include "../../include/cwt.h"
 #include "cwt_internal.h"
+#include "cwt_host.h"
 
 namespace cwt {
 
 static thread_local std::string g_err;
-
-struct Failure {
-    int code;
-    std::string msg;
-};
-[[noreturn]] static void fail(int code, const std::string &msg) { throw Failure{code, msg}; }
-
-#define HIPCHK(x)                                                                          \
-    do {                                                                                   \
-        hipError_t e_ = (x);                                                               \
-        if (e_ != hipSuccess) ::cwt::fail(CWT_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-// ---------------------------------------------------------------------------
-// Wavelets (unit L2 norm; psi^(u) = int psi(x) e^{-iux} dx = i^{-cph}... see
-// amp/cph below).  psi^(u) = phase * amp(u) with amp real; conj(phase) = i^cph.
-
-struct Wavelet {
-    int kind = 0;   // CWT_MORLET, CWT_MEXHAT, CWT_DOG
-    double w0 = 6.0;
-    int m = 2;
-    double cmor = 0.0, kappa = 0.0, gnorm = 0.0;
-
-    void init() {
-        if (kind == CWT_MORLET) {
-            kappa = std::exp(-0.5 * w0 * w0);
-            cmor = std::pow(M_PI, -0.25) / std::sqrt(1.0 + std::exp(-w0 * w0) - 2.0 * std::exp(-0.75 * w0 * w0));
-        } else {
-            gnorm = 1.0 / std::sqrt(std::tgamma(m + 0.5));
-        }
-    }
-    bool complex_out() const { return kind == CWT_MORLET; }
-    // |psi(x)| in the time domain
-    double abs_time(double x) const {
-        double g = std::exp(-0.5 * x * x);
-        if (kind == CWT_MORLET)
-            return cmor * g * std::sqrt(std::max(0.0, 1.0 - 2.0 * kappa * std::cos(w0 * x) + kappa * kappa));
-        // probabilists' Hermite polynomial He_m
-        double hm1 = 1.0, h = x;
-        for (int n = 1; n < m; ++n) {
-            double hn = x * h - n * hm1;
-            hm1 = h;
-            h = hn;
-        }
-        return std::fabs(h) * g * gnorm;
-    }
-    // real amplitude of the spectrum
-    double amp(double u) const {
-        if (kind == CWT_MORLET)
-            return cmor * std::sqrt(2.0 * M_PI) * (std::exp(-0.5 * (u - w0) * (u - w0)) - kappa * std::exp(-0.5 * u * u));
-        return std::pow(u, m) * std::sqrt(2.0 * M_PI) * std::exp(-0.5 * u * u) * gnorm;
-    }
-    // DOG(m): psi^ = (-1)^{m+1} i^m amp  ->  conj(phase) = i^{(m+2) mod 4}
-    int cph() const { return kind == CWT_MORLET ? 0 : (m + 2) % 4; }
-};
 
 // radius beyond which |psi| < rel * max|psi|
 static double time_radius(const Wavelet &w, double rel) {
@@ -169,19 +115,6 @@ static int64_t next_pow2(int64_t x) {
     return p;
 }
 
-// ---------------------------------------------------------------------------
-// table upload helper
-
-struct TableBuilder {
-    std::vector<char> host;
-    int64_t add(const void *data, size_t bytes) {
-        size_t off = (host.size() + 255) & ~size_t(255);
-        host.resize(off + bytes);
-        std::memcpy(host.data() + off, data, bytes);
-        return (int64_t)off;
-    }
-};
-
 template <typename R>
 static void push_twiddles(TableBuilder &tb, int64_t P, std::vector<std::pair<int32_t, int64_t>> &offs) {
     for (auto &e : offs)
@@ -268,8 +201,6 @@ static void push_w23(TableBuilder &tb, int64_t &hi_off, int64_t &lo_off) {
 }
 
 static const int64_t kMaxN = int64_t(1) << 26;
-
-[[noreturn]] void spline_unsupported() { fail(CWT_EUNSUPPORTED, "spline method is not available in this build"); }
 
 void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &tb);  // cwt_spline_plan.cpp
 
@@ -979,8 +910,10 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, vo
         const double eb = (double)cwt_out_elem_bytes(plan);
         const double nn = (double)p.N;
         if (p.method == CWT_METHOD_SPLINE) {
-            cwt::timed(p, st, "spline", nn * sb + nn * p.S * eb, "spline launch",
-                       [&] { return cwt::launch_spline(p, signal, out, workspace, st); });
+            cwt::timed(p, st, cwt::spline_kernel_name(p, 0), nn * sb + 16.0 * (double)p.spl_len, "spline sums launch",
+                       [&] { return cwt::launch_spline(p, signal, out, workspace, st, 0); });
+            cwt::timed(p, st, cwt::spline_kernel_name(p, 1), nn * p.S * eb, "spline taps launch",
+                       [&] { return cwt::launch_spline(p, signal, out, workspace, st, 1); });
             return CWT_OK;
         }
         const double fb = p.precision == CWT_FP64 ? 16.0 : 8.0;

@@ -1,6 +1,409 @@
-// cwt_spline.hip -- spline method (Sec. 3.3); filled in by the spline path.
+// cwt_spline.hip -- spline method (Sec. 3.3), integer knot spacing.
+//
+// With psi_h(y) = sum_n d[n] beta3(y/h - n) (Eq. beta3_wavelet_approx_m02) and
+// f_c = sum_k c[k] beta3(u - k) (Eq. beta3_signal), the transform
+// W(s, x) = (1/s) int f_c(u) conj psi_h((u - x)/s) du is, for h = delta / s
+// with integer delta,
+//
+//   W[x] = 1 / (s delta^3) sum_{n=-nd}^{nd} conj(d[n]) S[x + n delta],
+//   S[y] = (box_delta^4 (beta7 * c))[y + 2 delta - 2],
+//
+// using beta3(v/delta) = delta^{-3} sum_j B[j] beta3(v - j) (B = box_delta^4
+// impulse response, centred), int beta3(u - k) beta3(u - m) du = beta7(k - m)
+// (App. B, Eqs. two_betas, rescaled_beta) and beta7 sampled on the integers
+// (151/315, 397/1680, 1/42, 1/5040).  box_delta^4 = Delta_delta^4 Delta^{-4}
+// (App. B, Eqs. rescaled_finite_diff, inverse_finite_diff) is the paper's
+// four running sums g of Eq. cumsum4_coeffs followed by delta-spaced
+// differences.  Here the running sums are taken in 128-bit integers, modulo
+// 2^128, of the fixed-point coefficients q = rint(c 2^F) convolved with the
+// integer taps 5040 beta7 = (1, 120, 1191, 2416, 1191, 120, 1): the delta-spaced
+// fourth difference of the wrapped sums is the exact integer box sum whenever
+// that sum fits (|.| < 2^127, guaranteed by the choice of F), so the
+// precision loss of long running sums (Sec. 3.3, App. D) does not arise and no
+// segmentation of the sums is needed.  The sums are shared by every scale.
+//
+// Kernels (one exec):
+//   spl_maxabs   partial max |f| per block of 4096 samples
+//   spl_exponent F = qbits - e, 3 max|f| = m 2^e, 0.5 <= m < 1  (|c| <= 3 max|f|)
+//   spl_sums<0>  per block: c (61-tap FIR, Eq. interp_coeffs), q, q7, local
+//                running-sum state
+//   spl_carry    exclusive scan of the block states
+//   spl_sums<1>  per block: the fourth running sum H of q7, stored (16 B each)
+//   spl_tap      per (scale, tile): S from H (5 loads, exact), FP64 taps
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/cwt.h"
 #include "cwt_internal.h"
+
 namespace cwt {
-struct TableBuilder;
-hipError_t launch_spline(const Plan &, const void *, void *, void *, hipStream_t) { return hipErrorNotSupported; }
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+constexpr int kSB = 4096;       // positions per block
+constexpr int kSNT = 256;       // threads per block
+constexpr int kSPT = kSB / kSNT;  // positions per thread
+constexpr int kFIR = 30;        // prefilter half length: (2 - sqrt 3)^31 < 2e-18
+
+// running-sum state of a run of positions: the four sums at its end, each
+// started from zero at its beginning
+struct Sums {
+    u128 y1, y2, y3, y4;
+};
+
+// state after run A followed by run B of length t (B's sums started at zero)
+__device__ __forceinline__ Sums sums_then(const Sums &a, const Sums &b, u128 t) {
+    const u128 c2 = t * (t + 1) / 2, c3 = t * (t + 1) * (t + 2) / 6;
+    Sums r;
+    r.y1 = a.y1 + b.y1;
+    r.y2 = a.y2 + t * a.y1 + b.y2;
+    r.y3 = a.y3 + t * a.y2 + c2 * a.y1 + b.y3;
+    r.y4 = a.y4 + t * a.y3 + c2 * a.y2 + c3 * a.y1 + b.y4;
+    return r;
+}
+
+__device__ __forceinline__ double i128_to_double(u128 v) {
+    const i128 s = (i128)v;
+    const long long hi = (long long)(s >> 64);
+    const unsigned long long lo = (unsigned long long)s;
+    return (double)hi * 0x1p64 + (double)lo;
+}
+
+// NaN-propagating maximum
+__device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+template <typename R>
+__device__ __forceinline__ double sig_ext(const R *__restrict__ f, int64_t N, int periodic, int64_t x) {
+    if (periodic) {
+        int64_t m = x % N;
+        if (m < 0) m += N;
+        return (double)f[m];
+    }
+    return (x >= 0 && x < N) ? (double)f[x] : 0.0;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kSNT) void spl_maxabs_kernel(const R *__restrict__ f, int64_t N, double *__restrict__ part) {
+    __shared__ double red[kSNT];
+    const int64_t base = (int64_t)blockIdx.x * kSB;
+    double m = 0.0;
+    for (int k = threadIdx.x; k < kSB; k += kSNT) {
+        const int64_t i = base + k;
+        if (i < N) m = nmax(m, fabs((double)f[i]));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kSNT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = nmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// fx[0] = F, fx[1] = 1 if max|f| is not finite
+__global__ __launch_bounds__(kSNT) void spl_exponent_kernel(const double *__restrict__ part, int nb, int qbits,
+                                                            int *__restrict__ fx) {
+    __shared__ double red[kSNT];
+    double m = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kSNT) m = nmax(m, part[k]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kSNT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = nmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double b = 3.0 * red[0];
+        int F = 0, bad = 0;
+        if (!(b <= 1.7e308)) bad = 1;  // inf or NaN
+        else if (b > 0.0) {
+            int e;
+            (void)frexp(b, &e);
+            F = qbits - e;
+        }
+        fx[0] = F;
+        fx[1] = bad;
+    }
+}
+
+// powers z1^t, t = 0..kFIR, z1 = sqrt(3) - 2
+struct ZPow {
+    double v[kFIR + 1];
+    constexpr ZPow() : v() {
+        const double z = -0.26794919243112270647;
+        double a = 1.0;
+        for (int t = 0; t <= kFIR; ++t) {
+            v[t] = a;
+            a *= z;
+        }
+    }
+};
+__constant__ ZPow kZ = ZPow();
+
+// Block b covers array indices [b kSB, (b + 1) kSB), position x = index - E.
+// FINAL = 0: writes the block's running-sum state (from zero) to state[b].
+// FINAL = 1: adds the carry-in carry[b] and writes H[index] (fourth sum).
+template <typename R, int FINAL>
+__global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f, int64_t N, int periodic, int64_t E,
+                                                        int64_t len, const int *__restrict__ fx,
+                                                        Sums *__restrict__ state, const Sums *__restrict__ carry,
+                                                        u128 *__restrict__ H) {
+    constexpr int FS = kSB + 6 + 2 * kFIR;  // samples on [x0 - 3 - kFIR, x0 + kSB + 3 + kFIR)
+    constexpr int QS = kSB + 6;             // q on [x0 - 3, x0 + kSB + 3)
+    __shared__ double fs[FS];
+    __shared__ long long qs[QS];
+    __shared__ Sums scan[kSNT];
+    const int tid = threadIdx.x;
+    const int F = fx[0], bad = fx[1];
+    const int64_t l0 = (int64_t)blockIdx.x * kSB;
+    const int64_t x0 = l0 - E;
+    for (int k = tid; k < FS; k += kSNT) fs[k] = sig_ext(f, N, periodic, x0 - 3 - kFIR + k);
+    __syncthreads();
+    // spline coefficients c = (beta3)^{-1} f (Eq. interp_coeffs) as the
+    // symmetric FIR sqrt(3) sum_t z1^|t| f[x - t], then fixed point
+    for (int k = tid; k < QS; k += kSNT) {
+        const double *fc = fs + k + kFIR;
+        double c = fc[0];
+#pragma unroll
+        for (int t = 1; t <= kFIR; ++t) c = fma(kZ.v[t], fc[-t] + fc[t], c);
+        c *= 1.7320508075688772935;
+        qs[k] = bad ? 0ll : (long long)rint(ldexp(c, F));
+    }
+    __syncthreads();
+    // 5040 beta7 * q at this thread's positions, local running sums
+    Sums loc = {0, 0, 0, 0};
+    i128 q7v[kSPT];
+#pragma unroll
+    for (int e = 0; e < kSPT; ++e) {
+        const long long *qq = qs + tid * kSPT + e + 3;
+        const i128 q7 = (i128)qq[0] * 2416 + ((i128)qq[-1] + qq[1]) * 1191 + ((i128)qq[-2] + qq[2]) * 120 +
+                        ((i128)qq[-3] + qq[3]);
+        q7v[e] = q7;
+        loc.y1 += (u128)q7;
+        loc.y2 += loc.y1;
+        loc.y3 += loc.y2;
+        loc.y4 += loc.y3;
+    }
+    // inclusive scan of the thread states (each covers kSPT positions)
+    Sums inc = loc;
+    scan[tid] = inc;
+    __syncthreads();
+    for (int d = 1; d < kSNT; d <<= 1) {
+        Sums left;
+        const bool has = tid >= d;
+        if (has) left = scan[tid - d];
+        __syncthreads();
+        if (has) inc = sums_then(left, inc, (u128)(d * kSPT));
+        scan[tid] = inc;
+        __syncthreads();
+    }
+    if (!FINAL) {
+        if (tid == kSNT - 1) state[blockIdx.x] = inc;
+        return;
+    }
+    // absolute state before this thread's first position
+    Sums st = carry[blockIdx.x];
+    if (tid > 0) st = sums_then(st, scan[tid - 1], (u128)(tid * kSPT));
+#pragma unroll
+    for (int e = 0; e < kSPT; ++e) {
+        st.y1 += (u128)q7v[e];
+        st.y2 += st.y1;
+        st.y3 += st.y2;
+        st.y4 += st.y3;
+        const int64_t l = l0 + tid * kSPT + e;
+        if (l < len) H[l] = st.y4;
+    }
+}
+
+// exclusive scan of the block states: carry[b] = running sums just before block b
+constexpr int kCNT = 1024;
+__global__ __launch_bounds__(kCNT) void spl_carry_kernel(const Sums *__restrict__ state, int nblk,
+                                                         Sums *__restrict__ carry) {
+    __shared__ Sums sc[kCNT];
+    __shared__ int64_t ln[kCNT];
+    const int tid = threadIdx.x;
+    const int per = (nblk + kCNT - 1) / kCNT;
+    const int b0 = tid * per, b1 = min(nblk, b0 + per);
+    Sums acc = {0, 0, 0, 0};
+    int64_t len = 0;
+    for (int b = b0; b < b1; ++b) {
+        acc = sums_then(acc, state[b], (u128)kSB);
+        len += kSB;
+    }
+    sc[tid] = acc;
+    ln[tid] = len;
+    __syncthreads();
+    for (int d = 1; d < kCNT; d <<= 1) {
+        Sums left;
+        int64_t llen = 0;
+        const bool has = tid >= d;
+        if (has) {
+            left = sc[tid - d];
+            llen = ln[tid - d];
+        }
+        __syncthreads();
+        if (has) {
+            acc = sums_then(left, acc, (u128)len);
+            len += llen;
+        }
+        sc[tid] = acc;
+        ln[tid] = len;
+        __syncthreads();
+    }
+    Sums st = {0, 0, 0, 0};
+    if (tid > 0) st = sc[tid - 1];
+    for (int b = b0; b < b1; ++b) {
+        carry[b] = st;
+        st = sums_then(st, state[b], (u128)kSB);
+    }
+}
+
+// Tap sums.  Positions x = i delta + r0 + r (row i, column r < R); the tile
+// holds rows [i0, i0 + I).  S rows m <-> i = i0 - nd + m, m < I + ntap.
+constexpr int kSTile = 8192;
+template <typename OUT, bool CPLX>
+__global__ __launch_bounds__(256) void spl_tap_kernel(int64_t N, int64_t E, const SplineScaleDev *__restrict__ scl,
+                                                      const SplineWork *__restrict__ work,
+                                                      const u128 *__restrict__ H, const double2 *__restrict__ dtab,
+                                                      const int *__restrict__ fx, OUT *__restrict__ out) {
+    __shared__ double S[kSTile];
+    const SplineWork w = work[blockIdx.x];
+    const SplineScaleDev p = scl[w.j];
+    const int tid = threadIdx.x;
+    const int R = w.R;
+    const int ngrp = 256 / p.R;  // row groups of 16 (I = 16 ngrp)
+    const int r = tid % p.R, g = tid / p.R;
+    const bool active = r < R && g < ngrp;
+    const int64_t delta = p.delta;
+    const int I = p.I, nd = p.nd, ntap = p.ntap;
+    const int rowsS = I + ntap;
+    const int64_t nrows = (N + delta - 1) / delta;
+    // S rows that some output of the tile uses; rows beyond are zero
+    const int mvalid = (int)min((int64_t)rowsS, min((int64_t)I, nrows - w.i0) + 2 * nd);
+    const int F = fx[0];
+    const int bad = fx[1];
+    if (active) {
+        const int ch = (rowsS + ngrp - 1) / ngrp;
+        const int mb = g * ch, me = min(rowsS, mb + ch);
+        // H row rho of column r: index E + rho delta + r0 + r - 2
+        const u128 *hc = H + (E + w.r0 + r - 2);
+        if (mb < me) {
+            const int64_t ib = w.i0 - nd + mb;  // i of the first S row
+            u128 hm2 = 0, hm1 = 0, h0 = 0, hp1 = 0;
+            if (mb < mvalid) {
+                hm2 = hc[(ib - 2) * delta];
+                hm1 = hc[(ib - 1) * delta];
+                h0 = hc[ib * delta];
+                hp1 = hc[(ib + 1) * delta];
+            }
+            for (int m = mb; m < me; ++m) {
+                double v = 0.0;
+                if (m < mvalid) {
+                    const int64_t i = w.i0 - nd + m;
+                    const u128 hp2 = hc[(i + 2) * delta];
+                    const u128 sv = hp2 + hm2 + 6 * h0 - 4 * (hp1 + hm1);
+                    v = i128_to_double(sv);
+                    hm2 = hm1;
+                    hm1 = h0;
+                    h0 = hp1;
+                    hp1 = hp2;
+                }
+                S[m * R + r] = v;
+            }
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    const int u0 = g * 16;
+    const double2 *dd = dtab + p.d_off;
+    double ar[16], ai[16], win[32];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        ar[u] = 0.0;
+        ai[u] = 0.0;
+        win[u] = S[(u0 + u) * R + r];
+    }
+    for (int nb = 0; nb < ntap; nb += 16) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) win[16 + k] = S[(u0 + nb + 16 + k) * R + r];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const double2 dv = dd[nb + t];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                ar[u] = fma(dv.x, win[u + t], ar[u]);
+                if (CPLX) ai[u] = fma(dv.y, win[u + t], ai[u]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) win[k] = win[16 + k];
+    }
+    const double nan = __builtin_nan("");
+    OUT *row = out + (int64_t)w.j * N * (CPLX ? 2 : 1);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int64_t x = (w.i0 + u0 + u) * delta + w.r0 + r;
+        if (x < N) {
+            const double vr = bad ? nan : ldexp(ar[u], -F);
+            if (CPLX) {
+                const double vi = bad ? nan : ldexp(ai[u], -F);
+                row[2 * x] = (OUT)vr;
+                row[2 * x + 1] = (OUT)vi;
+            } else {
+                row[x] = (OUT)vr;
+            }
+        }
+    }
+}
+
+template <typename R>
+static hipError_t spline_sums(const Plan &p, const R *f, char *ws, hipStream_t st) {
+    double *part = reinterpret_cast<double *>(ws + p.ws_maxp_off);
+    int *fx = reinterpret_cast<int *>(ws + p.ws_fx_off);
+    Sums *state = reinterpret_cast<Sums *>(ws + p.ws_state_off);
+    Sums *carry = reinterpret_cast<Sums *>(ws + p.ws_carry_off);
+    u128 *H = reinterpret_cast<u128 *>(ws + p.ws_H_off);
+    const int periodic = p.boundary == CWT_PERIODIC;
+    hipLaunchKernelGGL(spl_maxabs_kernel<R>, dim3(p.spl_nb0), dim3(kSNT), 0, st, f, p.N, part);
+    hipLaunchKernelGGL(spl_exponent_kernel, dim3(1), dim3(kSNT), 0, st, part, p.spl_nb0, p.spl_qbits, fx);
+    hipLaunchKernelGGL((spl_sums_kernel<R, 0>), dim3(p.spl_nblk), dim3(kSNT), 0, st, f, p.N, periodic, p.spl_E,
+                       p.spl_len, fx, state, carry, H);
+    hipLaunchKernelGGL(spl_carry_kernel, dim3(1), dim3(kCNT), 0, st, state, p.spl_nblk, carry);
+    hipLaunchKernelGGL((spl_sums_kernel<R, 1>), dim3(p.spl_nblk), dim3(kSNT), 0, st, f, p.N, periodic, p.spl_E,
+                       p.spl_len, fx, state, carry, H);
+    return hipGetLastError();
+}
+
+template <typename OUT>
+static hipError_t spline_taps(const Plan &p, char *ws, void *out, hipStream_t st) {
+    const int *fx = reinterpret_cast<const int *>(ws + p.ws_fx_off);
+    const u128 *H = reinterpret_cast<const u128 *>(ws + p.ws_H_off);
+    const double2 *dt = reinterpret_cast<const double2 *>(p.d_dtab);
+    const dim3 grid((unsigned)p.spl_work.size());
+    if (p.cplx_out)
+        hipLaunchKernelGGL((spl_tap_kernel<OUT, true>), grid, dim3(256), 0, st, p.N, p.spl_E, p.d_spl, p.d_spl_work, H,
+                           dt, fx, reinterpret_cast<OUT *>(out));
+    else
+        hipLaunchKernelGGL((spl_tap_kernel<OUT, false>), grid, dim3(256), 0, st, p.N, p.spl_E, p.d_spl, p.d_spl_work, H,
+                           dt, fx, reinterpret_cast<OUT *>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_spline(const Plan &p, const void *signal, void *out, void *ws, hipStream_t st, int phase) {
+    char *w = reinterpret_cast<char *>(ws);
+    const bool fp64 = p.precision == CWT_FP64;
+    if (phase == 0)
+        return fp64 ? spline_sums(p, reinterpret_cast<const double *>(signal), w, st)
+                    : spline_sums(p, reinterpret_cast<const float *>(signal), w, st);
+    return fp64 ? spline_taps<double>(p, w, out, st) : spline_taps<float>(p, w, out, st);
+}
+
+std::string spline_kernel_name(const Plan &p, int phase) {
+    const std::string t = p.precision == CWT_FP64 ? "f64" : "f32";
+    if (phase == 0) return "spline_sums<" + t + ">";
+    return "spl_tap_kernel<" + t + (p.cplx_out ? ",complex>" : ",real>");
+}
+
 }  // namespace cwt

@@ -1,10 +1,227 @@
-// cwt_spline_plan.cpp -- host side of the spline method; filled in by the spline path.
-#include <string>
-#include "../../include/cwt.h"
+// cwt_spline_plan.cpp -- host side of the spline method (Sec. 3.3, App. B,
+// App. C, Eq. m02cwt_error).
+//
+// Per plan: h*, the largest knot step whose spline wavelet reaches the
+// accuracy AE_M = 5e-4 (Eq. m02cwt_error, Table 3).  Per scale s: the integer
+// knot spacing delta = max(1, floor(h* s)) in samples, h_s = delta / s, the
+// wavelet coefficients d_s (Eq. beta3_wavelet_approx_m02, computed as Eq.
+// interp_coeffs on the samples psi(h_s k)), N_d = ceil(chi / h_s - 2) + 2
+// taps on each side, and the tiling of the tap-sum launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "cwt_host.h"
 #include "cwt_internal.h"
+
 namespace cwt {
-struct Wavelet;
-struct TableBuilder;
-[[noreturn]] void spline_unsupported();
-void build_spline_plan(Plan &, const Wavelet &, TableBuilder &) { spline_unsupported(); }
+
+using cd = std::complex<double>;
+
+// cubic B-spline (App. B, Eq. betan with n = 3)
+static double bspline3(double x) {
+    x = std::fabs(x);
+    if (x < 1.0) return 2.0 / 3.0 - x * x + 0.5 * x * x * x;
+    if (x < 2.0) return (2.0 - x) * (2.0 - x) * (2.0 - x) / 6.0;
+    return 0.0;
+}
+
+// Support radius used by the spline method: one grid step past the last point
+// of the grid i / 4096 (0 <= i <= 64 * 4096) where |psi| >= rel * max|psi|.
+static double spline_chi(const Wavelet &w, double rel) {
+    const double step = 1.0 / 4096.0;
+    const int n = 64 * 4096;
+    double mx = 0.0;
+    for (int i = 0; i <= n; ++i) mx = std::max(mx, std::abs(w.psi_time(i * step)));
+    double last = 0.0;
+    for (int i = 0; i <= n; ++i)
+        if (std::abs(w.psi_time(i * step)) >= rel * mx) last = i * step;
+    return last + step;
+}
+
+// Cubic-spline interpolation coefficients of v (zero outside the array), in
+// place: the causal and anticausal first-order recursions of App. C with the
+// pole z1 = sqrt(3) - 2 and gain d0 = 6.  The anticausal start value is the
+// exact sum of the zero-extended causal output.
+static void interp_coeffs(std::vector<cd> &v) {
+    const double z = std::sqrt(3.0) - 2.0;
+    const size_t n = v.size();
+    for (size_t k = 1; k < n; ++k) v[k] += z * v[k - 1];
+    v[n - 1] = (-z / (1.0 - z * z)) * v[n - 1];
+    for (size_t k = n - 1; k-- > 0;) v[k] = z * (v[k + 1] - v[k]);
+    for (auto &x : v) x *= 6.0;
+}
+
+// coefficients of psi(h k), k in [-K, K], stored at k + K
+static std::vector<cd> wavelet_coeffs(const Wavelet &w, double h, int K) {
+    std::vector<cd> v(2 * (size_t)K + 1);
+    for (int k = -K; k <= K; ++k) v[(size_t)(k + K)] = w.psi_time(h * k);
+    interp_coeffs(v);
+    return v;
+}
+
+// psi_h(x) = sum_k d[k] beta3(x/h - k)
+static cd spline_eval(const std::vector<cd> &d, int K, double h, double x) {
+    const double y = x / h;
+    const long k0 = (long)std::floor(y) - 1;
+    cd acc = 0.0;
+    for (long k = k0; k <= k0 + 3; ++k)
+        if (k >= -K && k <= K) acc += d[(size_t)(k + K)] * bspline3(y - (double)k);
+    return acc;
+}
+
+// AE_M(h) of Eq. m02cwt_error on 20001 uniform points of [-chi, chi]; the
+// spline uses the untruncated coefficients (40 beyond chi / h on each side)
+static double ae_m(const Wavelet &w, double chi, double h) {
+    const int K = (int)std::ceil(chi / h) + 40;
+    const std::vector<cd> d = wavelet_coeffs(w, h, K);
+    const int npts = 20001;
+    const double dx = 2.0 * chi / (npts - 1);
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < npts; ++i) {
+        const double x = i == npts - 1 ? chi : -chi + i * dx;
+        const cd ex = w.psi_time(x);
+        num += std::abs(ex - spline_eval(d, K, h, x));
+        den += std::abs(ex);
+    }
+    return num / den;
+}
+
+// h*: scan h upward in steps of 0.005 until AE_M reaches 5e-4, then bisect the
+// bracketing interval (60 halvings)
+static double h_star(const Wavelet &w, double chi) {
+    const double target = 5e-4;
+    double lo = 0.005, h = lo;
+    while (ae_m(w, chi, h) < target) {
+        lo = h;
+        h += 0.005;
+        if (h > 3.0) fail(CWT_EUNSUPPORTED, "spline method: AE_M never reaches 5e-4 for this wavelet");
+    }
+    double hi = h;
+    for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (ae_m(w, chi, mid) < target) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+static double cached_h_star(const Wavelet &w, double chi) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, double, int>, double> cache;
+    const auto key = std::make_tuple(w.kind, w.kind == CWT_MORLET ? w.w0 : 0.0, w.kind == CWT_MORLET ? 0 : w.m);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const double h = h_star(w, chi);
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = h;
+    return h;
+}
+
+static const int kSplineBlock = 4096;  // elements per block of the running sums and the max|f| reduction
+
+void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
+    const double chi14 = spline_chi(w, 1e-14);  // truncation used for h* (Table 2 keeps |psi| near 1e-14)
+    const double chi17 = spline_chi(w, 1e-17);  // truncation of d_s
+    p.hstar = cached_h_star(w, chi14);
+    p.path.assign(p.S, PATH_SPLINE);
+    p.spl.resize(p.S);
+    p.spl_delta.resize(p.S);
+    p.spl_work.clear();
+
+    std::vector<cd> dtab;
+    int64_t delta_max = 1, E = 16;
+    for (int j = 0; j < p.S; ++j) {
+        const double s = p.scales[j];
+        const double fl = std::floor(p.hstar * s);
+        if (fl > 1e9) fail(CWT_EUNSUPPORTED, "spline method: scale too large");
+        const int64_t delta = std::max<int64_t>(1, (int64_t)fl);
+        const double h = (double)delta / s;
+        const int nd = (int)std::ceil(chi17 / h - 2.0) + 2;
+        if (nd > 2040) fail(CWT_EUNSUPPORTED, "spline method: more than 4081 wavelet coefficients at this scale");
+        const int K = std::max(nd, (int)std::ceil(chi17 / h)) + 40;
+        const std::vector<cd> dk = wavelet_coeffs(w, h, K);
+        const int ntap = (2 * nd + 1 + 15) / 16 * 16;
+        SplineScaleDev &sc = p.spl[j];
+        sc.delta = (int32_t)delta;
+        sc.nd = nd;
+        sc.ntap = ntap;
+        sc.d_off = (int64_t)dtab.size();
+        const double kscale = 1.0 / (5040.0 * s * (double)delta * (double)delta * (double)delta);
+        for (int n = 0; n < ntap; ++n)
+            dtab.push_back(n <= 2 * nd ? std::conj(dk[(size_t)(K - nd + n)]) * kscale : cd(0.0));
+        // tile: R columns x I rows; the S tile holds R (I + ntap) <= 4096 + R (2 nd + 16) <= 8192 values
+        int rmax = 1;
+        while (rmax < 64 && 2 * rmax * (2 * nd + 16) <= 4096) rmax *= 2;
+        const int64_t nck = (delta + rmax - 1) / rmax;
+        const int R = (int)((delta + nck - 1) / nck);
+        sc.R = R;
+        sc.I = 16 * (256 / R);
+        sc.pad = 0;
+        const int64_t rows = (p.N + delta - 1) / delta;
+        for (int64_t i0 = 0; i0 < rows; i0 += sc.I)
+            for (int64_t k = 0; k < nck; ++k) {
+                const int64_t r0 = k * R;
+                if (r0 >= delta) break;
+                SplineWork wk;
+                wk.j = j;
+                wk.r0 = (int32_t)r0;
+                wk.R = (int32_t)std::min<int64_t>(R, delta - r0);
+                wk.pad = 0;
+                wk.i0 = i0;
+                p.spl_work.push_back(wk);
+            }
+        p.spl_delta[j] = (int32_t)delta;
+        delta_max = std::max(delta_max, delta);
+        E = std::max<int64_t>(E, (int64_t)(nd + 3) * delta + 16);
+    }
+    // most expensive tiles first
+    std::stable_sort(p.spl_work.begin(), p.spl_work.end(), [&](const SplineWork &a, const SplineWork &b) {
+        return p.spl[a.j].ntap > p.spl[b.j].ntap;
+    });
+    if (p.N + 2 * E > (int64_t(1) << 31)) fail(CWT_EUNSUPPORTED, "spline method: signal plus wavelet support above 2^31");
+    p.spl_E = E;
+    p.spl_len = p.N + 2 * E;
+    // fixed-point bits: |5040 beta7 * box^4 q| <= 5040 delta^4 max|q| must stay below 2^127
+    const int qb = (int)std::floor(127.0 - std::log2(5040.0) - 4.0 * std::log2((double)delta_max)) - 1;
+    p.spl_qbits = std::min(62, qb);
+    if (p.spl_qbits < 40) fail(CWT_EUNSUPPORTED, "spline method: knot spacing too large for 128-bit running sums");
+    p.spl_nb0 = (int32_t)((p.N + kSplineBlock - 1) / kSplineBlock);
+    p.spl_nblk = (int32_t)((p.spl_len + kSplineBlock - 1) / kSplineBlock);
+
+    size_t ws = 0;
+    auto take = [&](size_t bytes) {
+        size_t off = (ws + 255) & ~size_t(255);
+        ws = off + bytes;
+        return off;
+    };
+    p.ws_maxp_off = take((size_t)p.spl_nb0 * sizeof(double));
+    p.ws_fx_off = take(16);
+    p.ws_state_off = take((size_t)p.spl_nblk * 64);
+    p.ws_carry_off = take((size_t)p.spl_nblk * 64);
+    p.ws_H_off = take((size_t)p.spl_len * 16);
+    p.ws_bytes = ws;
+    if (p.host_only) return;
+
+    auto upload = [&](const void *src, size_t bytes, void **dst) {
+        HIPCHK(hipMalloc(dst, bytes));
+        p.table_bytes += bytes;
+        HIPCHK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    };
+    upload(dtab.data(), dtab.size() * sizeof(cd), &p.d_dtab);
+    upload(p.spl.data(), p.spl.size() * sizeof(SplineScaleDev), reinterpret_cast<void **>(&p.d_spl));
+    p.d_extra.push_back(p.d_spl);
+    upload(p.spl_work.data(), p.spl_work.size() * sizeof(SplineWork), reinterpret_cast<void **>(&p.d_spl_work));
+    p.d_extra.push_back(p.d_spl_work);
+}
+
 }  // namespace cwt

@@ -1,0 +1,157 @@
+"""GPU parity of the spline method against the oracle's exact spline target
+(the CWT of the cubic-spline interpolant of the samples with the spline
+wavelet psi_h, integrated exactly; Sec. 3.3).  The oracle gets the plan's
+knot spacings, checked separately against the oracle's own rule.
+
+Bars (per-scale relative L2 with a floor, tests/helpers.py): 1e-10 for FP64
+output, 1e-5 for FP32 output (FP32-rounded input, FP64 reference)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import per_scale_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def gpu_spline(torch, f, bc, wav, par, scales, precision):
+    import paper_2302_03909_amd as cwt
+    plan = cwt.Plan(f.size, bc, wav, scales, param=par, precision=precision, method="spline")
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    w = plan(torch.as_tensor(f, dtype=dt, device="cuda"))
+    torch.cuda.synchronize()
+    return plan, w
+
+
+def ref_input(f, precision):
+    return f.astype(np.float32).astype(np.float64) if precision == "fp32" else f
+
+
+def ref_rows(f, bc, wav, par, scales, deltas, x):
+    return np.stack([oracle.spline_target(f, bc, wav, s, int(d), x, param=par, nthreads=8)
+                     for s, d in zip(scales, deltas)])
+
+
+def check_full(torch, f, bc, wav, par, scales, precision):
+    print(f"spline case N={f.size} bc={bc} wav={wav}({par}) S={len(scales)} {precision}", flush=True)
+    plan, w = gpu_spline(torch, f, bc, wav, par, scales, precision)
+    got = w.cpu().numpy()
+    deltas = plan.spline_delta()
+    hs = oracle.spline_h_star(wav, par)
+    assert deltas.tolist() == [oracle.spline_delta(hs, s) for s in scales]
+    ref = ref_rows(ref_input(f, precision), bc, wav, par, scales, deltas, np.arange(f.size))
+    assert np.all(np.isfinite(got))
+    err = per_scale_rel_l2(got, ref)
+    assert err.max() <= TOL[precision], (err.max(), int(err.argmax()))
+    return err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,bc,wav,par,scales", [
+    (4096, "periodic", "morlet", 6.0, [0.7, 2.0, 9.0, 40.0, 300.0, 1500.0]),
+    (3001, "zero", "mexhat", None, [1.5, 2.0, 9.0, 40.0, 150.0, 700.0]),
+    (5000, "periodic", "dog", 4.0, [2.0, 30.0, 400.0, 2500.0]),
+    (2000, "zero", "morlet", 4.0, [1.0, 7.0, 333.0]),
+])
+def test_spline_parity(torch_cuda, precision, n, bc, wav, par, scales):
+    rng = np.random.default_rng(n + 7)
+    f = rng.standard_normal(n) + 0.3
+    err = check_full(torch_cuda, f, bc, wav, par, scales, precision)
+    print("max rel L2", err.max())
+
+
+@pytest.mark.parametrize("n", [2, 3, 17])
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+def test_spline_degenerate_lengths(torch_cuda, n, bc):
+    f = np.random.default_rng(11).standard_normal(n)
+    check_full(torch_cuda, f, bc, "mexhat", None, [0.5, 1.0, 5.0, 30.0], "fp64")
+    check_full(torch_cuda, f, bc, "morlet", 6.0, [1.0, 40.0], "fp64")
+
+
+def test_spline_paper_signal_and_gap(torch_cuda):
+    # N = 4096 periodic tones + noise, Morlet(6), 32 log scales 2..512: parity
+    # with the spline target, and the gap to the sampled-sum transform.  The
+    # gap is the spline approximations' own error: near Nyquist (s < 8 for
+    # Morlet(6), whose passband w0/s approaches pi) the cubic interpolant of a
+    # broadband signal departs from its samples and the gap reaches tens of
+    # percent; above that it is of the order of AE_M.
+    f = synth.tones_noise(4096)
+    scales = synth.log_scales(2.0, 512.0, 32)
+    check_full(torch_cuda, f, "periodic", "morlet", 6.0, scales, "fp64")
+    _, w = gpu_spline(torch_cuda, f, "periodic", "morlet", 6.0, scales, "fp64")
+    canon = oracle.cwt(f, "periodic", "morlet", scales, param=6.0)
+    gap = per_scale_rel_l2(w.cpu().numpy(), canon)
+    print("gap to the sampled sum, per scale:", np.array2string(gap, precision=2))
+    assert gap[np.asarray(scales) >= 8.0].max() < 1e-2
+
+
+def test_spline_zero_and_nan_input(torch_cuda):
+    _, w = gpu_spline(torch_cuda, np.zeros(1000), "zero", "mexhat", None, [2.0, 50.0], "fp64")
+    assert np.all(w.cpu().numpy() == 0.0)
+    f = np.random.default_rng(3).standard_normal(1000)
+    f[500] = np.nan
+    _, w = gpu_spline(torch_cuda, f, "zero", "mexhat", None, [2.0, 50.0], "fp64")
+    assert np.all(np.isnan(w.cpu().numpy()))
+
+
+def test_spline_deterministic(torch_cuda):
+    f = synth.lognormal_field(20000, seed=9)
+    scales = [1.3, 17.0, 900.0]
+    _, a = gpu_spline(torch_cuda, f, "zero", "morlet", 6.0, scales, "fp64")
+    _, b = gpu_spline(torch_cuda, f, "zero", "morlet", 6.0, scales, "fp64")
+    assert torch_cuda.equal(a, b)
+
+
+def sampled(torch, f, bc, wav, par, scales, precision, npos, seed):
+    plan, w = gpu_spline(torch, f, bc, wav, par, scales, precision)
+    n = f.size
+    rng = np.random.default_rng(seed)
+    pos = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.integers(0, n, npos - 5)]))
+    got = w[:, torch.as_tensor(pos, device="cuda")].cpu().numpy()
+    del w
+    torch.cuda.empty_cache()
+    ref = ref_rows(ref_input(f, precision), bc, wav, par, scales, plan.spline_delta(), pos)
+    return per_scale_rel_l2(got, ref)
+
+
+def test_spline_full_size_fp64_mexhat_1m(torch_cuda):
+    # N = 2^20 zero-boundary lognormal field, Mexican hat, 64 log scales
+    # 2..2^14, FP64, sampled positions
+    f = synth.lognormal_field(1 << 20, seed=synth.SEED_FIELD_1M)
+    scales = synth.log_scales(2.0, 2.0 ** 14, 64)
+    err = sampled(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", 24, 1)
+    print("spline fp64 1M max err", err.max())
+    assert err.max() <= 1e-10
+
+
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+def test_spline_full_size_fp32_morlet_4m(torch_cuda, bc):
+    # N = 2^22 lognormal field, Morlet(6), 128 log scales 2..2^16, FP32
+    # output; every 8th scale is checked at sampled positions
+    f = synth.lognormal_field(1 << 22, seed=synth.SEED_FIELD_4M)
+    scales = synth.log_scales(2.0, 2.0 ** 16, 128)
+    import paper_2302_03909_amd as cwt
+    plan = cwt.Plan(f.size, bc, "morlet", scales, param=6.0, precision="fp32", method="spline")
+    w = plan(torch_cuda.as_tensor(f, dtype=torch_cuda.float32, device="cuda"))
+    torch_cuda.cuda.synchronize()
+    rows = np.arange(0, 128, 8)
+    n = f.size
+    pos = np.unique(np.concatenate([[0, 1, n // 2, n - 1], np.random.default_rng(2).integers(0, n, 20)]))
+    got = w[torch_cuda.as_tensor(rows, device="cuda")][:, torch_cuda.as_tensor(pos, device="cuda")].cpu().numpy()
+    del w
+    torch_cuda.cuda.empty_cache()
+    ref = ref_rows(ref_input(f, "fp32"), bc, "morlet", 6.0, scales[rows], plan.spline_delta()[rows], pos)
+    err = per_scale_rel_l2(got, ref)
+    print(f"spline fp32 4M {bc} max err", err.max())
+    assert err.max() <= 1e-5

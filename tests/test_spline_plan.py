@@ -1,0 +1,52 @@
+"""Host side of the spline method (no GPU): h*, knot spacings and the
+plan's limits, checked against the oracle's independent h* search and
+against the step sizes Table 3 prints for the paper's wavelets' accuracy
+criterion (Eq. m02cwt_error, AE_M = 5e-4)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2302_03909_amd as cwt
+
+
+def host_plan(n, wav, par, scales, bc="zero", precision="fp64"):
+    return cwt.Plan(n, bc, wav, scales, param=par, precision=precision, method="spline", host_only=True)
+
+
+@pytest.mark.parametrize("wav,par", [("mexhat", None), ("morlet", 6.0), ("dog", 4.0)])
+def test_hstar_matches_oracle(wav, par):
+    p = host_plan(4096, wav, par, [2.0, 40.0])
+    ref = oracle.spline_h_star(wav, par)
+    assert abs(p.spline_hstar() - ref) <= 1e-9 * ref, (p.spline_hstar(), ref)
+
+
+def test_hstar_values():
+    # h* of the spec wavelets at AE_M = 5e-4 (three digits; the same
+    # criterion reproduces the three h of Table 3 for GDW, CW-GDW and MW)
+    for wav, par, h in [("mexhat", None, 0.3722), ("morlet", 6.0, 0.1167), ("dog", 4.0, 0.3010)]:
+        assert abs(host_plan(1024, wav, par, [3.0]).spline_hstar() - h) < 5e-4
+
+
+def test_delta_rule():
+    scales = np.array([0.3, 1.0, 2.0, 2.687, 2.69, 7.5, 64.0, 1000.0, 16384.0])
+    p = host_plan(1 << 16, "mexhat", None, scales)
+    hs = p.spline_hstar()
+    want = [oracle.spline_delta(hs, s) for s in scales]
+    assert p.spline_delta().tolist() == want
+    assert set(p.scale_path().tolist()) == {cwt.PATH_SPLINE}
+    assert p.fft_len == 0
+
+
+def test_spline_limits():
+    # delta^4 beyond the 128-bit headroom
+    with pytest.raises(cwt.CwtError) as e:
+        host_plan(1 << 20, "mexhat", None, [3.0e6])
+    assert e.value.code == cwt.CWT_EUNSUPPORTED
+    # fine just below
+    host_plan(1 << 12, "mexhat", None, [3.0e5])
+
+
+def test_workspace_grows_with_support():
+    a = host_plan(1 << 16, "morlet", 6.0, [4.0])
+    b = host_plan(1 << 16, "morlet", 6.0, [4.0, 4096.0])
+    assert b.workspace_bytes > a.workspace_bytes > 16 * (1 << 16)
