@@ -1,14 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the multi-scale 1D CWT on one MI355X.
 
-One step = one full transform (whole-signal FFT where needed, every scale's
-spectral multiply and inverse FFT) of one synthetic signal whose data already
-sit in device memory.  Default workload: N = 2^22 samples of a zero-boundary
-lognormal field, complex Morlet (omega0 = 6), 128 log-spaced scales 2..2^16,
-FP32 form.  Prints one JSON line (see the fields below).
+One step = one full transform of one synthetic signal whose samples already
+sit in device memory (every kernel of the method, all scales).  Workloads:
 
-    python bench.py [--steps K] [--warmup W] [--wavelet morlet|dog2]
-                    [--boundary zero|periodic] [--no-cpu-baseline] [--copy-calibration]
+  --method fft (default): N = 2^22 samples of a zero-boundary lognormal
+      field, complex Morlet (omega0 = 6) or DOG(2), 128 log-spaced scales
+      2..2^16, FP32 form (FP64 forward sums, FP32 output).
+  --method spline: N = 2^20 samples of a zero-boundary lognormal field,
+      Mexican hat (or Morlet(6)), 64 log-spaced scales 2..2^14, FP64.
+
+Prints one JSON line (fields below), with a roofline entry for the kernel
+that takes most of the step and the FP64 oracle timed on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--method fft|spline]
+                    [--wavelet morlet|dog2|mexhat] [--boundary zero|periodic]
+                    [--no-cpu-baseline] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -22,7 +29,8 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+FP64_PEAK_TFS = 78.6       # MI355X FP64 vector, published
 
 
 def kernel_source_hash() -> str:
@@ -53,9 +61,18 @@ def measured_traffic(kernel: str, workload: str):
     return e.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(f, boundary, wavelet, param, scales, seconds=10.0):
-    """The FP64 oracle on a uniform random sample of the workload's outputs
-    (scale, position), so the per-output cost matches the whole workload."""
+def _timed_sample(run, seconds):
+    count = 2000
+    while True:
+        t = run(count)
+        if t >= seconds:
+            return count, t
+        count = int(count * min(8.0, max(1.5, 1.2 * seconds / max(t, 1e-3))))
+
+
+def cpu_baseline_fft(f, boundary, wavelet, param, scales, seconds=10.0):
+    """The FP64 direct-sum oracle on a uniform random sample of the
+    workload's outputs (scale, position)."""
     import numpy as np
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -70,15 +87,36 @@ def cpu_baseline(f, boundary, wavelet, param, scales, seconds=10.0):
         oracle.cwt_points(f64, boundary, wavelet, scales, si, ps, param=param, nthreads=threads)
         return time.perf_counter() - t0
 
-    count = 2000
-    while True:
-        t = run(count)
-        if t >= seconds:
-            break
-        count = int(count * min(8.0, max(1.5, 1.2 * seconds / max(t, 1e-3))))
+    count, t = _timed_sample(run, seconds)
     return {"value": count / t, "unit": "coefficients/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} outputs drawn uniformly over the {s} x {n} outputs of the workload "
                       f"(FP64 direct sum), {t:.1f} s"}
+
+
+def cpu_baseline_spline(f, boundary, wavelet, param, scales, deltas, seconds=10.0):
+    """The oracle's exact spline target (Gauss-Legendre over the merged
+    knots) on random positions of 8 scales spread over the scale range."""
+    import numpy as np
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    n = f.size
+    rng = np.random.default_rng(321)
+    pick = np.linspace(0, len(scales) - 1, 8).round().astype(int)
+    f64 = f.astype(np.float64)
+
+    def run(count):
+        per = max(1, count // len(pick))
+        t0 = time.perf_counter()
+        for j in pick:
+            oracle.spline_target(f64, boundary, wavelet, float(scales[j]), int(deltas[j]),
+                                 rng.integers(0, n, per), param=param, nthreads=threads)
+        return time.perf_counter() - t0
+
+    count, t = _timed_sample(run, seconds)
+    count = max(1, count // len(pick)) * len(pick)
+    return {"value": count / t, "unit": "coefficients/s", "cores": threads, "kind": "oracle",
+            "sample": f"{count} outputs, equal numbers at 8 of the {len(scales)} scales (spread over the "
+                      f"range), random positions of N = {n} (exact spline target), {t:.1f} s"}
 
 
 def main():
@@ -86,7 +124,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--wavelet", default="morlet", choices=["morlet", "dog2"])
+    ap.add_argument("--method", default="fft", choices=["fft", "spline"])
+    ap.add_argument("--wavelet", default=None, choices=["morlet", "dog2", "mexhat"])
     ap.add_argument("--boundary", default="zero", choices=["zero", "periodic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -104,13 +143,21 @@ def main():
     import paper_2302_03909_amd as cwt
     import synth
 
-    n, nscales = 1 << 22, 128
-    scales = synth.log_scales(2.0, 2.0 ** 16, nscales)
-    wav, par = ("morlet", 6.0) if args.wavelet == "morlet" else ("dog", 2.0)
-    f = synth.lognormal_field(n, seed=synth.SEED_FIELD_4M).astype(np.float32)
+    if args.method == "fft":
+        n, nscales, smax, precision = 1 << 22, 128, 2.0 ** 16, "fp32"
+        seed, nname = synth.SEED_FIELD_4M, "2^22"
+        wavelet = args.wavelet or "morlet"
+    else:
+        n, nscales, smax, precision = 1 << 20, 64, 2.0 ** 14, "fp64"
+        seed, nname = synth.SEED_FIELD_1M, "2^20"
+        wavelet = args.wavelet or "mexhat"
+    wav, par = {"morlet": ("morlet", 6.0), "dog2": ("dog", 2.0), "mexhat": ("mexhat", None)}[wavelet]
+    scales = synth.log_scales(2.0, smax, nscales)
+    dt = np.float32 if precision == "fp32" else np.float64
+    f = synth.lognormal_field(n, seed=seed).astype(dt)
 
     dev = torch.device("cuda", 0)
-    plan = cwt.Plan(n, args.boundary, wav, scales, param=par, precision="fp32")
+    plan = cwt.Plan(n, args.boundary, wav, scales, param=par, precision=precision, method=args.method)
     x = torch.as_tensor(f, device=dev)
     out = plan.empty_output(dev)
     ws = plan.empty_workspace(dev)
@@ -133,19 +180,35 @@ def main():
     ms = (t1 - t0) * 1e3 / args.steps
     coeffs = n * nscales
     value = coeffs / (ms * 1e-3)
-    out_bytes = coeffs * (8 if plan.is_complex else 4)
+    out_bytes = coeffs * (4 if precision == "fp32" else 8) * (2 if plan.is_complex else 1)
+
+    wname = f"{wav}({par:g})" if par is not None else wav
+    workload = (f"lognormal field N={nname} {args.boundary} boundary, {wname}, "
+                f"{nscales} log scales 2..2^{int(np.log2(smax))}, "
+                f"{'fp32 form' if precision == 'fp32' else 'fp64'}"
+                + (", spline method" if args.method == "spline" else ""))
 
     # dominant kernel: largest total time over the timed region
     name, (cnt, tot_ms, bpl) = max(kern.items(), key=lambda kv: kv[1][1])
     avg_s = tot_ms / cnt * 1e-3
-    achieved = bpl / avg_s / 1e9
-    workload = (f"lognormal field N=2^22 {args.boundary} boundary, {wav}({par:g}), "
-                f"128 log scales 2..2^16, fp32 form")
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
-            "kernel": name, "avg_launch_ms": round(tot_ms / cnt, 4),
-            "algorithmic_bytes_per_launch": bpl}
-    whole = {"output_bytes": out_bytes, "hbm_frac_of_output_write": round(out_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    if name.startswith("spl_tap"):
+        # FP64 fused multiply-adds of the tap sums: (2 N_d + 1) taps per output,
+        # one real (two for a complex d) FMA each, 2 flops per FMA
+        taps = plan.spline_taps().astype(np.float64)
+        flops = 2.0 * n * taps.sum() * (2.0 if plan.is_complex else 1.0)
+        achieved = flops / avg_s / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFS, 4), "traffic": measured_traffic(name, workload),
+                "kernel": name, "avg_launch_ms": round(tot_ms / cnt, 4),
+                "algorithmic_flops_per_launch": flops, "output_write_gbs": round(bpl / avg_s / 1e9, 1)}
+    else:
+        achieved = bpl / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
+                "kernel": name, "avg_launch_ms": round(tot_ms / cnt, 4),
+                "algorithmic_bytes_per_launch": bpl}
+    whole = {"output_bytes": out_bytes,
+             "hbm_frac_of_output_write": round(out_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "kernels": {k: {"launches": v[0], "ms_per_step": round(v[1] / args.steps, 4),
                              "bytes_per_launch": v[2]} for k, v in kern.items()}}
 
@@ -159,15 +222,18 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(f, args.boundary, wav, par, scales)
+        if args.method == "fft":
+            cpu = cpu_baseline_fft(f, args.boundary, wav, par, scales)
+        else:
+            cpu = cpu_baseline_spline(f, args.boundary, wav, par, scales, plan.spline_delta())
 
     line = {"metric": "CWT coefficients/sec (N x scales) and % HBM peak at N=2^22, 128 scales",
             "value": value, "unit": "coefficients/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": workload, "n": n, "scales": nscales, "scale_range": [2, 65536],
-                       "boundary": args.boundary, "wavelet": f"{wav}{par:g}", "precision": "fp32",
-                       "fft_len": plan.fft_len},
+            "vs_baseline": None, "dtype": "f32" if precision == "fp32" else "f64", "data": "synthetic",
+            "config": {"workload": workload, "method": args.method, "n": n, "scales": nscales,
+                       "scale_range": [2, int(smax)], "boundary": args.boundary, "wavelet": wname,
+                       "precision": precision},
             "roofline": roof, "whole_step": whole, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 

@@ -133,7 +133,7 @@ typedef struct {
  * not of the supported form, or (spline method) a knot spacing delta_s
  * above about 2^18.4 (the 128-bit running sums then keep fewer than 40
  * fixed-point bits), more
- * than 4081 wavelet coefficients at one scale, or N + 2 (N_d + 3) delta_s
+ * than 3601 wavelet coefficients at one scale, or N + 2 (N_d + 3) delta_s
  * above 2^31;
  * CWT_ENOMEM / CWT_EDEVICE on allocation or HIP failures.
  * On failure *out is set to NULL.
@@ -193,6 +193,9 @@ int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals,
  *   cwt_plan_spline_delta: fills delta[j] (S entries) with the integer knot
  *                          spacing delta_j of the spline method (0 for plans
  *                          of the FFT method).
+ *   cwt_plan_spline_taps:  fills taps[j] with 2 N_d + 1, the number of
+ *                          wavelet coefficients d_s of scale j (0 for the
+ *                          FFT method).
  *   cwt_plan_spline_hstar: h* of the plan's wavelet (0 for the FFT method).
  *   cwt_plan_scale_path:   fills path[j] with how scale j is computed:
  *                          0 = segmented FFT (overlap-save), 1 = band-limited
@@ -200,6 +203,7 @@ int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals,
  */
 int64_t cwt_plan_fft_len(cwt_plan_t plan);
 int cwt_plan_spline_delta(cwt_plan_t plan, int32_t *delta);
+int cwt_plan_spline_taps(cwt_plan_t plan, int32_t *taps);
 double cwt_plan_spline_hstar(cwt_plan_t plan);
 int cwt_plan_scale_path(cwt_plan_t plan, int32_t *path);
 

@@ -46,7 +46,7 @@ class _Opts(ctypes.Structure):
 
 EXPORTS = ["cwt_plan", "cwt_destroy", "cwt_out_is_complex", "cwt_out_elems", "cwt_out_elem_bytes",
            "cwt_workspace_bytes", "cwt_footprint_bytes", "cwt_exec", "cwt_batch_workspace_bytes",
-           "cwt_exec_batch", "cwt_plan_fft_len", "cwt_plan_spline_delta", "cwt_plan_spline_hstar",
+           "cwt_exec_batch", "cwt_plan_fft_len", "cwt_plan_spline_delta", "cwt_plan_spline_taps", "cwt_plan_spline_hstar",
            "cwt_plan_scale_path", "cwt_plan_timing_enable", "cwt_plan_timing_read", "cwt_last_error"]
 
 _lib = None
@@ -81,6 +81,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cwt_plan_fft_len.argtypes = [vp]
     lib.cwt_plan_fft_len.restype = ctypes.c_int64
     lib.cwt_plan_spline_delta.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.cwt_plan_spline_taps.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.cwt_plan_spline_hstar.argtypes = [vp]
     lib.cwt_plan_spline_hstar.restype = ctypes.c_double
     lib.cwt_plan_scale_path.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -174,6 +175,11 @@ class Plan:
     def spline_delta(self) -> np.ndarray:
         out = np.zeros(self.num_scales, dtype=np.int32)
         _check(load().cwt_plan_spline_delta(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def spline_taps(self) -> np.ndarray:
+        out = np.zeros(self.num_scales, dtype=np.int32)
+        _check(load().cwt_plan_spline_taps(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return out
 
     def spline_hstar(self) -> float:

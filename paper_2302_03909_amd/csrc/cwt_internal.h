@@ -100,7 +100,7 @@ struct ColumnLaunch {
 
 // Spline method (Sec. 3.3 with integer knot spacing, see cwt_spline.hip).
 // Per scale: knot spacing delta, wavelet coefficients d'[n] = conj(d[n - nd]) /
-// (5040 s delta^3), n < ntap (2 nd + 1 taps, zero-padded to a multiple of 16),
+// (5040 s delta^3), n < ntap (2 nd + 1 taps, zero-padded to a multiple of 8),
 // and the tile shape: R columns (consecutive positions) x I rows (stride delta).
 struct SplineScaleDev {
     int32_t delta, nd, ntap, R, I, pad;
@@ -153,6 +153,7 @@ struct Plan {
     int32_t spl_qbits = 0;  // bits of the fixed-point coefficients
     int32_t spl_nb0 = 0;    // blocks of the max|f| reduction
     int32_t spl_nblk = 0;   // blocks of the running sums
+    int64_t spl_lds_bytes = 0;  // LDS of the tap-sum launch (largest tile plus its taps)
     SplineScaleDev *d_spl = nullptr;
     SplineWork *d_spl_work = nullptr;
     size_t ws_maxp_off = 0, ws_fx_off = 0, ws_state_off = 0, ws_carry_off = 0, ws_H_off = 0;

@@ -1032,6 +1032,13 @@ int cwt_plan_spline_delta(cwt_plan_t plan, int32_t *delta) {
     return CWT_OK;
 }
 
+int cwt_plan_spline_taps(cwt_plan_t plan, int32_t *taps) {
+    if (!plan || !taps) return CWT_EINVAL;
+    const Plan &p = *plan->p;
+    for (int j = 0; j < p.S; ++j) taps[j] = p.method == CWT_METHOD_SPLINE ? 2 * p.spl[j].nd + 1 : 0;
+    return CWT_OK;
+}
+
 double cwt_plan_spline_hstar(cwt_plan_t plan) { return plan ? plan->p->hstar : 0.0; }
 
 int cwt_plan_scale_path(cwt_plan_t plan, int32_t *path) {

@@ -23,7 +23,7 @@
 // segmentation of the sums is needed.  The sums are shared by every scale.
 //
 // Kernels (one exec):
-//   spl_maxabs   partial max |f| per block of 4096 samples
+//   spl_maxabs   partial max |f| per block of 1024 samples
 //   spl_exponent F = qbits - e, 3 max|f| = m 2^e, 0.5 <= m < 1  (|c| <= 3 max|f|)
 //   spl_sums<0>  per block: c (61-tap FIR, Eq. interp_coeffs), q, q7, local
 //                running-sum state
@@ -42,7 +42,7 @@ namespace cwt {
 typedef unsigned __int128 u128;
 typedef __int128 i128;
 
-constexpr int kSB = 4096;       // positions per block
+constexpr int kSB = 1024;       // positions per block
 constexpr int kSNT = 256;       // threads per block
 constexpr int kSPT = kSB / kSNT;  // positions per thread
 constexpr int kFIR = 30;        // prefilter half length: (2 - sqrt 3)^31 < 2e-18
@@ -53,9 +53,24 @@ struct Sums {
     u128 y1, y2, y3, y4;
 };
 
-// state after run A followed by run B of length t (B's sums started at zero)
-__device__ __forceinline__ Sums sums_then(const Sums &a, const Sums &b, u128 t) {
-    const u128 c2 = t * (t + 1) / 2, c3 = t * (t + 1) * (t + 2) / 6;
+// C(t + 1, 2) and C(t + 2, 3) for t < 2^32, dividing the factors by 2 and 3
+// before the 128-bit products (no 128-bit division)
+__device__ __forceinline__ void binoms(uint64_t t, u128 &c2, u128 &c3) {
+    uint64_t a = t, b = t + 1, c = t + 2;
+    if ((t & 1) == 0) a >>= 1;  // exactly one of t, t + 1 is even
+    else b >>= 1;
+    c2 = (u128)a * (u128)b;
+    if (a % 3 == 0) a /= 3;  // one of t, t + 1, t + 2 is a multiple of 3 (halving keeps that)
+    else if (b % 3 == 0) b /= 3;
+    else c /= 3;
+    c3 = (u128)a * (u128)b * (u128)c;
+}
+
+// state after run A followed by run B of length t < 2^32 (B's sums started at zero)
+__device__ __forceinline__ Sums sums_then(const Sums &a, const Sums &b, uint64_t tt) {
+    u128 c2, c3;
+    binoms(tt, c2, c3);
+    const u128 t = tt;
     Sums r;
     r.y1 = a.y1 + b.y1;
     r.y2 = a.y2 + t * a.y1 + b.y2;
@@ -195,7 +210,7 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
         const bool has = tid >= d;
         if (has) left = scan[tid - d];
         __syncthreads();
-        if (has) inc = sums_then(left, inc, (u128)(d * kSPT));
+        if (has) inc = sums_then(left, inc, (uint64_t)(d * kSPT));
         scan[tid] = inc;
         __syncthreads();
     }
@@ -205,7 +220,7 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
     }
     // absolute state before this thread's first position
     Sums st = carry[blockIdx.x];
-    if (tid > 0) st = sums_then(st, scan[tid - 1], (u128)(tid * kSPT));
+    if (tid > 0) st = sums_then(st, scan[tid - 1], (uint64_t)(tid * kSPT));
 #pragma unroll
     for (int e = 0; e < kSPT; ++e) {
         st.y1 += (u128)q7v[e];
@@ -229,7 +244,7 @@ __global__ __launch_bounds__(kCNT) void spl_carry_kernel(const Sums *__restrict_
     Sums acc = {0, 0, 0, 0};
     int64_t len = 0;
     for (int b = b0; b < b1; ++b) {
-        acc = sums_then(acc, state[b], (u128)kSB);
+        acc = sums_then(acc, state[b], (uint64_t)kSB);
         len += kSB;
     }
     sc[tid] = acc;
@@ -245,7 +260,7 @@ __global__ __launch_bounds__(kCNT) void spl_carry_kernel(const Sums *__restrict_
         }
         __syncthreads();
         if (has) {
-            acc = sums_then(left, acc, (u128)len);
+            acc = sums_then(left, acc, (uint64_t)len);
             len += llen;
         }
         sc[tid] = acc;
@@ -256,19 +271,25 @@ __global__ __launch_bounds__(kCNT) void spl_carry_kernel(const Sums *__restrict_
     if (tid > 0) st = sc[tid - 1];
     for (int b = b0; b < b1; ++b) {
         carry[b] = st;
-        st = sums_then(st, state[b], (u128)kSB);
+        st = sums_then(st, state[b], (uint64_t)kSB);
     }
 }
 
 // Tap sums.  Positions x = i delta + r0 + r (row i, column r < R); the tile
-// holds rows [i0, i0 + I).  S rows m <-> i = i0 - nd + m, m < I + ntap.
-constexpr int kSTile = 8192;
+// holds rows [i0, i0 + I).  S rows m <-> i = i0 - nd + m, m < I + ntap, kept
+// in LDS at R (m + m/16) + r: one spare row per 16 makes the strides between
+// the 16-row groups of neighbouring threads odd (no bank conflicts).
+constexpr int kSTile = 8192;  // S values per tile (rows with spares included), 64 KiB
+__device__ __forceinline__ int stile_idx(int m, int R, int r) { return R * (m + (m >> 4)) + r; }
+
+// LDS: the S tile (stile doubles), then the tile's taps d' (ntap double2).
+// The launch passes the largest such size over the plan's scales.
 template <typename OUT, bool CPLX>
 __global__ __launch_bounds__(256) void spl_tap_kernel(int64_t N, int64_t E, const SplineScaleDev *__restrict__ scl,
                                                       const SplineWork *__restrict__ work,
                                                       const u128 *__restrict__ H, const double2 *__restrict__ dtab,
                                                       const int *__restrict__ fx, OUT *__restrict__ out) {
-    __shared__ double S[kSTile];
+    extern __shared__ double lds[];
     const SplineWork w = work[blockIdx.x];
     const SplineScaleDev p = scl[w.j];
     const int tid = threadIdx.x;
@@ -279,66 +300,109 @@ __global__ __launch_bounds__(256) void spl_tap_kernel(int64_t N, int64_t E, cons
     const int64_t delta = p.delta;
     const int I = p.I, nd = p.nd, ntap = p.ntap;
     const int rowsS = I + ntap;
+    double *S = lds;
+    double2 *dl = reinterpret_cast<double2 *>(lds + R * (rowsS + rowsS / 16 + 1));
+    for (int k = tid; k < ntap; k += 256) dl[k] = dtab[p.d_off + k];
     const int64_t nrows = (N + delta - 1) / delta;
-    // S rows that some output of the tile uses; rows beyond are zero
+    // S rows that some output of the tile uses with a nonzero tap; the H
+    // rows of later S rows are clamped (their finite values meet zero taps or
+    // outputs beyond N only)
     const int mvalid = (int)min((int64_t)rowsS, min((int64_t)I, nrows - w.i0) + 2 * nd);
+    const int64_t rho_max = w.i0 - nd + mvalid + 1;
     const int F = fx[0];
     const int bad = fx[1];
     if (active) {
-        const int ch = (rowsS + ngrp - 1) / ngrp;
+        // rows in batches of 8: S rows m0..m0+7 need H rows i - 2 .. i + 2,
+        // i.e. the 12 rows starting at i0 - nd + m0 - 2, loaded together
+        const int ch = 8 * ((rowsS + 8 * ngrp - 1) / (8 * ngrp));
         const int mb = g * ch, me = min(rowsS, mb + ch);
-        // H row rho of column r: index E + rho delta + r0 + r - 2
-        const u128 *hc = H + (E + w.r0 + r - 2);
-        if (mb < me) {
-            const int64_t ib = w.i0 - nd + mb;  // i of the first S row
-            u128 hm2 = 0, hm1 = 0, h0 = 0, hp1 = 0;
-            if (mb < mvalid) {
-                hm2 = hc[(ib - 2) * delta];
-                hm1 = hc[(ib - 1) * delta];
-                h0 = hc[ib * delta];
-                hp1 = hc[(ib + 1) * delta];
+        const u128 *hc = H + (E + w.r0 + r - 2);  // H row rho of this column: hc[rho delta]
+        for (int m0 = mb; m0 < me; m0 += 8) {
+            u128 h[12];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const int64_t rho = min(w.i0 - nd + m0 - 2 + q, rho_max);
+                h[q] = hc[rho * delta];
             }
-            for (int m = mb; m < me; ++m) {
-                double v = 0.0;
-                if (m < mvalid) {
-                    const int64_t i = w.i0 - nd + m;
-                    const u128 hp2 = hc[(i + 2) * delta];
-                    const u128 sv = hp2 + hm2 + 6 * h0 - 4 * (hp1 + hm1);
-                    v = i128_to_double(sv);
-                    hm2 = hm1;
-                    hm1 = h0;
-                    h0 = hp1;
-                    hp1 = hp2;
-                }
-                S[m * R + r] = v;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const u128 sv = h[k] + h[k + 4] + 6 * h[k + 2] - 4 * (h[k + 1] + h[k + 3]);
+                if (m0 + k < me) S[stile_idx(m0 + k, R, r)] = i128_to_double(sv);
             }
         }
     }
     __syncthreads();
     if (!active) return;
     const int u0 = g * 16;
-    const double2 *dd = dtab + p.d_off;
-    double ar[16], ai[16], win[32];
+    // rows u0 + m for m in [16 q, 16 q + 16) start at stile_idx(u0 + 16 q) and
+    // are R apart: a block of 8 rows starting at a multiple of 8 has constant
+    // offsets
+    const double *Sc = S + stile_idx(u0, R, r);
+    auto rowp = [&](int m) { return Sc + R * (m + (m >> 4)); };  // m relative to u0, u0 % 16 == 0
+    double ar[16], ai[16], win[24], nxt[8];
+    double2 dc[8], dn[8];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         ar[u] = 0.0;
         ai[u] = 0.0;
-        win[u] = S[(u0 + u) * R + r];
     }
-    for (int nb = 0; nb < ntap; nb += 16) {
+    {
+        const double *p0 = rowp(0), *p1 = rowp(16);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) win[16 + k] = S[(u0 + nb + 16 + k) * R + r];
+        for (int k = 0; k < 16; ++k) win[k] = p0[k * R];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const double2 dv = dd[nb + t];
+        for (int k = 0; k < 8; ++k) win[16 + k] = p1[k * R];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) dc[t] = dl[t];
+    }
+    // taps in blocks of 8 (ntap is a multiple of 8); win holds S rows
+    // u0 + nb .. u0 + nb + 23; the next block's rows and taps are loaded
+    // before this block's multiply-adds
+    // (complex taps: no prefetch, which would exceed the register budget)
+    for (int nb = 0; nb < ntap; nb += 8) {
+        const bool more = nb + 8 < ntap;
+        if (CPLX) {
+            if (more) {
+                const double *pn = rowp(nb + 24);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) nxt[k] = pn[k * R];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const double2 dv = dl[nb + t];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    ar[u] = fma(dv.x, win[u + t], ar[u]);
+                    ai[u] = fma(dv.y, win[u + t], ai[u]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) win[k] = win[8 + k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) win[16 + k] = nxt[k];
+            continue;
+        }
+        if (more) {
+            const double *pn = rowp(nb + 24);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) nxt[k] = pn[k * R];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) dn[t] = dl[nb + 8 + t];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
-                ar[u] = fma(dv.x, win[u + t], ar[u]);
-                if (CPLX) ai[u] = fma(dv.y, win[u + t], ai[u]);
+                ar[u] = fma(dc[t].x, win[u + t], ar[u]);
+                if (CPLX) ai[u] = fma(dc[t].y, win[u + t], ai[u]);
             }
         }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) win[k] = win[16 + k];
+        for (int k = 0; k < 16; ++k) win[k] = win[8 + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) win[16 + k] = nxt[k];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) dc[t] = dn[t];
     }
     const double nan = __builtin_nan("");
     OUT *row = out + (int64_t)w.j * N * (CPLX ? 2 : 1);
@@ -382,12 +446,13 @@ static hipError_t spline_taps(const Plan &p, char *ws, void *out, hipStream_t st
     const u128 *H = reinterpret_cast<const u128 *>(ws + p.ws_H_off);
     const double2 *dt = reinterpret_cast<const double2 *>(p.d_dtab);
     const dim3 grid((unsigned)p.spl_work.size());
+    const size_t lds = (size_t)p.spl_lds_bytes;
     if (p.cplx_out)
-        hipLaunchKernelGGL((spl_tap_kernel<OUT, true>), grid, dim3(256), 0, st, p.N, p.spl_E, p.d_spl, p.d_spl_work, H,
-                           dt, fx, reinterpret_cast<OUT *>(out));
+        hipLaunchKernelGGL((spl_tap_kernel<OUT, true>), grid, dim3(256), lds, st, p.N, p.spl_E, p.d_spl, p.d_spl_work,
+                           H, dt, fx, reinterpret_cast<OUT *>(out));
     else
-        hipLaunchKernelGGL((spl_tap_kernel<OUT, false>), grid, dim3(256), 0, st, p.N, p.spl_E, p.d_spl, p.d_spl_work, H,
-                           dt, fx, reinterpret_cast<OUT *>(out));
+        hipLaunchKernelGGL((spl_tap_kernel<OUT, false>), grid, dim3(256), lds, st, p.N, p.spl_E, p.d_spl, p.d_spl_work,
+                           H, dt, fx, reinterpret_cast<OUT *>(out));
     return hipGetLastError();
 }
 

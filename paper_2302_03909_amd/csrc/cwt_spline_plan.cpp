@@ -127,7 +127,7 @@ static double cached_h_star(const Wavelet &w, double chi) {
     return h;
 }
 
-static const int kSplineBlock = 4096;  // elements per block of the running sums and the max|f| reduction
+static const int kSplineBlock = 1024;  // elements per block of the running sums and the max|f| reduction
 
 void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
     const double chi14 = spline_chi(w, 1e-14);  // truncation used for h* (Table 2 keeps |psi| near 1e-14)
@@ -137,6 +137,7 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
     p.spl.resize(p.S);
     p.spl_delta.resize(p.S);
     p.spl_work.clear();
+    p.spl_lds_bytes = 0;
 
     std::vector<cd> dtab;
     int64_t delta_max = 1, E = 16;
@@ -147,10 +148,10 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
         const int64_t delta = std::max<int64_t>(1, (int64_t)fl);
         const double h = (double)delta / s;
         const int nd = (int)std::ceil(chi17 / h - 2.0) + 2;
-        if (nd > 2040) fail(CWT_EUNSUPPORTED, "spline method: more than 4081 wavelet coefficients at this scale");
+        if (nd > 1800) fail(CWT_EUNSUPPORTED, "spline method: more than 3601 wavelet coefficients at this scale");
         const int K = std::max(nd, (int)std::ceil(chi17 / h)) + 40;
         const std::vector<cd> dk = wavelet_coeffs(w, h, K);
-        const int ntap = (2 * nd + 1 + 15) / 16 * 16;
+        const int ntap = (2 * nd + 1 + 7) / 8 * 8;
         SplineScaleDev &sc = p.spl[j];
         sc.delta = (int32_t)delta;
         sc.nd = nd;
@@ -159,14 +160,25 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
         const double kscale = 1.0 / (5040.0 * s * (double)delta * (double)delta * (double)delta);
         for (int n = 0; n < ntap; ++n)
             dtab.push_back(n <= 2 * nd ? std::conj(dk[(size_t)(K - nd + n)]) * kscale : cd(0.0));
-        // tile: R columns x I rows; the S tile holds R (I + ntap) <= 4096 + R (2 nd + 16) <= 8192 values
-        int rmax = 1;
-        while (rmax < 64 && 2 * rmax * (2 * nd + 16) <= 4096) rmax *= 2;
+        // tile: R <= 16 columns x I = 16 floor(256 / R) rows; the S tile holds
+        // R (I + ntap) values plus one spare row per 16, and the taps follow it
+        auto tile_fits = [&](int r) {
+            const int rows_s = 16 * (256 / r) + ntap;
+            return r * (rows_s + rows_s / 16 + 1) + 2 * ntap <= 8192;  // 64 KiB of LDS
+        };
+        int rmax = 16;
+        while (rmax > 1 && !tile_fits(rmax)) rmax /= 2;
+        if (!tile_fits(rmax)) fail(CWT_EUNSUPPORTED, "spline method: wavelet support too long for the tap tile");
         const int64_t nck = (delta + rmax - 1) / rmax;
         const int R = (int)((delta + nck - 1) / nck);
         sc.R = R;
         sc.I = 16 * (256 / R);
         sc.pad = 0;
+        {
+            const int64_t rows_s = sc.I + ntap;
+            const int64_t lds = 8 * (int64_t)R * (rows_s + rows_s / 16 + 1) + 16 * (int64_t)ntap;
+            p.spl_lds_bytes = std::max(p.spl_lds_bytes, lds);
+        }
         const int64_t rows = (p.N + delta - 1) / delta;
         for (int64_t i0 = 0; i0 < rows; i0 += sc.I)
             for (int64_t k = 0; k < nck; ++k) {
