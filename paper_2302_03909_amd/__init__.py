@@ -252,6 +252,8 @@ def exec_batch(plans, signals, outs=None, workspace=None, stream=None):
     """Transform many signals (each with its own plan) in one enqueue."""
     import torch
     n = len(plans)
+    if n == 0:
+        return []
     if outs is None:
         outs = [p.empty_output(s.device) for p, s in zip(plans, signals)]
     if workspace is None:

@@ -147,25 +147,33 @@ __global__ __launch_bounds__(NT) void local_kernel(const R *__restrict__ f, int6
                                                    int64_t Tg, int64_t V, int64_t nseg, int nscale,
                                                    const int32_t *__restrict__ scale_ids,
                                                    const R *__restrict__ ktab, int cph,
-                                                   const cplx_t<R> *__restrict__ tw, R *__restrict__ out) {
+                                                   const cplx_t<R> *__restrict__ tw,
+                                                   const double2 *__restrict__ tw64, R *__restrict__ out) {
     using C = cplx_t<R>;
     constexpr int LD = lds_len(L);
     constexpr int E = L / NT;
     static_assert(L % NT == 0, "L must be a multiple of NT");
-    __shared__ C buf[LD];
+    // segment forward transform in FP64 (the FP32 inverse buffer aliases it):
+    // an FP32 forward would leave rounding noise of order eps |f| in the weak
+    // high-frequency bands of red spectra
+    __shared__ double2 bufF[LD];
+    C *buf = reinterpret_cast<C *>(bufF);
     const int tid = threadIdx.x;
     const int64_t seg = (int64_t)blockIdx.x * (PAIR ? 2 : 1);
     const int64_t x0 = seg * V - Tg;
     for (int u = tid; u < L; u += NT) {
-        R a = sig_at(f, N, periodic, x0 + u);
-        R b = PAIR ? sig_at(f, N, periodic, x0 + V + u) : (R)0;
-        buf[lidx(u)] = mk<C>(a, b);
+        double a = (double)sig_at(f, N, periodic, x0 + u);
+        double b = PAIR ? (double)sig_at(f, N, periodic, x0 + V + u) : 0.0;
+        bufF[lidx(u)] = make_double2(a, b);
     }
     __syncthreads();
-    block_fft<C, L, 1, NT, LD, -1>(buf, tw);
+    block_fft<double2, L, 1, NT, LD, -1>(bufF, tw64);
     C X[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) X[i] = buf[lidx(tid + i * NT)];
+    for (int i = 0; i < E; ++i) {
+        const double2 v = bufF[lidx(tid + i * NT)];
+        X[i] = mk<C>((R)v.x, (R)v.y);
+    }
     __syncthreads();
     const int64_t b0 = seg * V;
     const bool second = PAIR && (seg + 1 < nseg);
@@ -262,7 +270,8 @@ __global__ __launch_bounds__(NT) void column_kernel(const cplx_t<R> *__restrict_
 // size tables and launchers
 
 bool local_size_ok(int L, int precision) {
-    int lmax = precision == 0 ? 4096 : 8192;
+    (void)precision;
+    int lmax = 4096;
     return L >= 256 && L <= lmax && (L & (L - 1)) == 0;
 }
 bool column_size_ok(int P, int precision) {
@@ -373,21 +382,22 @@ static hipError_t local_launch_L(const Plan &p, const LocalGroup &g, const R *f,
     using C = cplx_t<R>;
     const R *ktab = static_cast<const R *>(p.d_tab) + g.tab_off;
     const C *tw = tw_ptr<C>(p, L, false);
+    const double2 *tw64 = sizeof(R) == 8 ? reinterpret_cast<const double2 *>(tw) : tw_ptr<double2>(p, L, true);
     int periodic = p.boundary == 0 ? 1 : 0;
     int64_t grid = p.pair_real ? (g.nseg + 1) / 2 : g.nseg;
     if (grid <= 0) return hipSuccess;
     if (p.cplx_out)
         hipLaunchKernelGGL((local_kernel<R, L, NT, false, true>), dim3((unsigned)grid), dim3(NT), 0, st, f,
                            p.N, periodic, g.Tg, g.V, g.nseg, (int)g.scales.size(), g.d_scales, ktab, p.cph, tw,
-                           out);
+                           tw64, out);
     else if (p.pair_real)
         hipLaunchKernelGGL((local_kernel<R, L, NT, true, false>), dim3((unsigned)grid), dim3(NT), 0, st, f,
                            p.N, periodic, g.Tg, g.V, g.nseg, (int)g.scales.size(), g.d_scales, ktab, p.cph, tw,
-                           out);
+                           tw64, out);
     else
         hipLaunchKernelGGL((local_kernel<R, L, NT, false, false>), dim3((unsigned)grid), dim3(NT), 0, st, f,
                            p.N, periodic, g.Tg, g.V, g.nseg, (int)g.scales.size(), g.d_scales, ktab, p.cph, tw,
-                           out);
+                           tw64, out);
     return hipGetLastError();
 }
 
@@ -422,7 +432,6 @@ hipError_t launch_local(const Plan &p, const LocalGroup &g, const void *signal, 
         case 1024: return local_launch_L<float, 1024>(p, g, f, o, st);
         case 2048: return local_launch_L<float, 2048>(p, g, f, o, st);
         case 4096: return local_launch_L<float, 4096>(p, g, f, o, st);
-        case 8192: return local_launch_L<float, 8192>(p, g, f, o, st);
         default: return hipErrorInvalidValue;
     }
 }

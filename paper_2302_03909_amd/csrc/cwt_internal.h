@@ -53,9 +53,12 @@ struct SegGroup {
     int64_t tab_off = 0;          // LOCAL: offset (elements) of the L-point tables
     int32_t *d_scales = nullptr;
     int64_t twl_off = -1;  // LOCAL: per-pass LDS twiddle table of size L, bytes
+    int64_t twl64_off = -1;  // LOCAL: the same table in FP64, bytes
     int64_t gtw_off = -1;  // BAND: w_L^{m g}, g < 16, m in band, bytes
     size_t ws_xp_off = 0, ws_x_off = 0;
     int32_t unit0 = 0, nunits = 0;  // BAND: range in Plan::units
+    int32_t key = -1;               // LOCAL: index of its KeyDesc
+    int64_t blocks = 0;             // LOCAL: workgroups of its launch
 };
 
 // device copy of a BAND group's parameters
@@ -90,6 +93,54 @@ struct SegLaunch {
     SegGroupDev *d_groups = nullptr;
     SegWork *d_fwd = nullptr, *d_red = nullptr, *d_inv = nullptr;
     double out_rows = 0.0;  // output rows written by the launch (for timing)
+    int32_t key[3] = {-1, -1, -1};  // KeyDesc of the forward, reduce and inverse launches
+};
+
+// Launch key of the segmented FFT method, static and device resident (built
+// with the plan): everything a workgroup needs besides the caller's buffers.
+//   LOCAL group: one key (local2 kernel), work items = segment blocks.
+//   SegLaunch:   three keys (forward, reduce, inverse), work items = `work`.
+struct KeyDesc {
+    int64_t N;
+    int32_t periodic, cph;
+    const SegGroupDev *groups;
+    const SegUnit *units;
+    const SegWork *work;
+    const void *ktab;      // spectrum samples, plan precision (LOCAL: this group's L-point tables)
+    const char *twbase;    // the plan's twiddle allocation
+    const void *twl;       // per-pass LDS twiddle table of the key's transform size
+    const void *twl64;     // LOCAL: the same table in FP64 (segment forward transform)
+    const double2 *whi, *wlo;  // FP64 w_{2^23} = hi[x >> 11] lo[x & 2047]
+    int64_t Tg, V, nseg;   // LOCAL group
+    int32_t nscale, pad;
+    const int32_t *scale_ids;
+};
+
+// caller buffers of one transform
+struct BatchInst {
+    const void *f;
+    void *out;
+    char *ws;
+};
+
+// blocks [block0, next range's block0) of a merged launch run key `key` on
+// instance `inst`, local block = blockIdx.x - block0
+struct BatchRange {
+    int64_t block0;
+    const KeyDesc *key;
+    int32_t inst, pad;
+};
+
+// kernel argument of every segmented kernel.  nranges == 0: one transform,
+// key and buffers by value (k0, i0); else block b belongs to
+// ranges[blockmap[b]].
+struct BatchArgs {
+    const BatchRange *ranges;
+    const int32_t *blockmap;
+    const BatchInst *insts;
+    int32_t nranges, pad;
+    KeyDesc k0;
+    BatchInst i0;
 };
 
 struct ColumnLaunch {
@@ -139,6 +190,8 @@ struct Plan {
     std::vector<SegLaunch> seg_launches;
     std::vector<SegUnit> units;
     SegUnit *d_units = nullptr;
+    std::vector<KeyDesc> keys;  // host copy (device pointers inside)
+    KeyDesc *d_keys = nullptr;
     int32_t fft_mode = 0;  // 0 segmented, 1 whole signal
     int64_t w23_hi_off = -1, w23_lo_off = -1;  // FP64 w_{2^23} tables, bytes
     bool pair_real = false;
@@ -184,12 +237,20 @@ struct Plan {
     size_t table_bytes = 0;
 };
 
-hipError_t launch_local2(const Plan &p, const SegGroup &g, const void *signal, void *out, hipStream_t st);
-// phase 0: band spectra of the segments (forward), 1: their reduction, 2: inverse
-hipError_t launch_seg(const Plan &p, const SegLaunch &l, const void *signal, void *ws, void *out, hipStream_t st,
-                      int phase);
-std::string local2_kernel_name(const Plan &p, const SegGroup &g);
-std::string seg_kernel_name(const Plan &p, const SegLaunch &l, int phase);
+// Segmented FFT kernels.  A launch is identified by its instantiation:
+//   kind 0: local2 (size = L), 1: forward (size = P), 2: reduce, 3: inverse (size = P)
+// and runs `blocks` workgroups described by `a`.
+struct SegKernelId {
+    int32_t kind, size, precision, cplx;  // cplx: complex output (else real pairs)
+    bool operator<(const SegKernelId &o) const {
+        if (kind != o.kind) return kind < o.kind;
+        if (size != o.size) return size < o.size;
+        if (precision != o.precision) return precision < o.precision;
+        return cplx < o.cplx;
+    }
+};
+hipError_t launch_seg_kernel(const SegKernelId &id, const BatchArgs &a, int64_t blocks, hipStream_t st);
+std::string seg_kernel_id_name(const SegKernelId &id);
 bool local2_size_ok(int L, int precision);
 bool seg_size_ok(int P, int precision);
 int local2_segs_per_block(int L, bool pair);

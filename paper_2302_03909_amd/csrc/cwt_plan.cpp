@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <map>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -207,7 +208,7 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &tb);  // cwt_spl
 static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
     const bool fp64 = p.precision == CWT_FP64;
     // largest segment transform that keeps its spectrum in registers without spills
-    const int lmax = fp64 ? 4096 : 8192;
+    const int lmax = 4096;  // FP64 segment forward in LDS
     const int pmax = fp64 ? 1024 : 2048;
     p.path.assign(p.S, PATH_LOCAL);
     // local if the halo fits a quarter of the largest segment transform
@@ -408,7 +409,10 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
     TableBuilder tb;
     for (auto &g : p.groups) {
         if (fp64) push_twiddles<double>(tb, g.L, p.tw_off);
-        else push_twiddles<float>(tb, g.L, p.tw_off);
+        else {
+            push_twiddles<float>(tb, g.L, p.tw_off);
+            push_twiddles<double>(tb, g.L, p.tw64_off);  // FP64 segment forward transforms
+        }
     }
     for (auto &c : p.columns) {
         if (fp64) push_twiddles<double>(tb, c.P, p.tw_off);
@@ -461,7 +465,7 @@ static int64_t align_halo(int64_t t) { return (t + 15) & ~int64_t(15); }
 
 static void build_seg_plan(Plan &p, const Wavelet &w) {
     const bool fp64 = p.precision == CWT_FP64;
-    const int lmax_local = fp64 ? 4096 : 8192;
+    const int lmax_local = 4096;
     const int pmax = 512;
     const int lg_max = 23;
     double ulo, uhi;
@@ -526,6 +530,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
                 tab.push_back(psi_aliased(w, p.scales[j], 2.0 * M_PI * ms / g.L, umax) / g.L);
             }
         g.twl_off = fp64 ? push_pass_twiddles<double>(tb, g.L) : push_pass_twiddles<float>(tb, g.L);
+        g.twl64_off = fp64 ? g.twl_off : push_pass_twiddles<double>(tb, g.L);
         p.segs.push_back(std::move(g));
     }
 
@@ -686,6 +691,48 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         upload(l.red.data(), l.red.size() * sizeof(SegWork), reinterpret_cast<void **>(&l.d_red));
         upload(l.inv.data(), l.inv.size() * sizeof(SegWork), reinterpret_cast<void **>(&l.d_inv));
     }
+
+    // launch keys
+    const char *tw = static_cast<const char *>(p.d_tw_all);
+    const char *dtab = static_cast<const char *>(p.d_tab);
+    KeyDesc base{};
+    base.N = p.N;
+    base.periodic = p.boundary == CWT_PERIODIC ? 1 : 0;
+    base.cph = p.cph;
+    base.units = p.d_units;
+    base.ktab = dtab;
+    base.twbase = tw;
+    base.whi = reinterpret_cast<const double2 *>(tw + p.w23_hi_off);
+    base.wlo = reinterpret_cast<const double2 *>(tw + p.w23_lo_off);
+    p.keys.clear();
+    for (auto &g : p.segs) {
+        if (g.kind != SegGroup::LOCAL) continue;
+        KeyDesc k = base;
+        k.ktab = dtab + (size_t)g.tab_off * (fp64 ? 8 : 4);
+        k.twl = tw + g.twl_off;
+        k.twl64 = tw + g.twl64_off;
+        k.Tg = g.Tg;
+        k.V = g.V;
+        k.nseg = g.nseg;
+        k.nscale = (int32_t)g.scales.size();
+        k.scale_ids = g.d_scales;
+        const int64_t per = local2_segs_per_block(g.L, p.pair_real);
+        g.blocks = (g.nseg + per - 1) / per;
+        g.key = (int32_t)p.keys.size();
+        p.keys.push_back(k);
+    }
+    for (auto &l : p.seg_launches) {
+        KeyDesc k = base;
+        k.groups = l.d_groups;
+        k.twl = tw + l.twl_off;
+        const SegWork *lists[3] = {l.d_fwd, l.d_red, l.d_inv};
+        for (int ph = 0; ph < 3; ++ph) {
+            k.work = lists[ph];
+            l.key[ph] = (int32_t)p.keys.size();
+            p.keys.push_back(k);
+        }
+    }
+    upload(p.keys.data(), p.keys.size() * sizeof(KeyDesc), reinterpret_cast<void **>(&p.d_keys));
 }
 
 static void free_plan(Plan *p) {
@@ -700,6 +747,7 @@ static void free_plan(Plan *p) {
     for (auto &g : p->segs)
         if (g.d_scales) (void)hipFree(g.d_scales);
     if (p->d_units) (void)hipFree(p->d_units);
+    if (p->d_keys) (void)hipFree(p->d_keys);
     for (auto &l : p->seg_launches) {
         if (l.d_groups) (void)hipFree(l.d_groups);
         if (l.d_fwd) (void)hipFree(l.d_fwd);
@@ -791,6 +839,28 @@ static hipEvent_t pool_event(Plan &p) {
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
     return e;
+}
+
+// The segmented launches of a plan in execution order (local groups, then per
+// band size: forward, reduce, inverse), with their kernel instantiation,
+// launch key, workgroup count and algorithmic bytes.
+template <typename F>
+static void for_each_seg_launch(const Plan &p, F &&fn) {
+    const double nn = (double)p.N;
+    const double sb = p.precision == CWT_FP64 ? 8.0 : 4.0;
+    const double eb = (p.precision == CWT_FP64 ? 8.0 : 4.0) * (p.cplx_out ? 2.0 : 1.0);
+    const int32_t cplx = p.cplx_out ? 1 : 0;
+    for (auto &g : p.segs)
+        if (g.kind == SegGroup::LOCAL)
+            fn(SegKernelId{0, g.L, p.precision, cplx}, g.key, g.blocks, nn * sb + nn * (double)g.scales.size() * eb);
+    for (auto &l : p.seg_launches) {
+        double xbytes = 0.0;
+        for (auto &gd : l.gdev) xbytes += (double)gd.nseg * gd.B * 16.0;
+        fn(SegKernelId{1, l.P, p.precision, cplx}, l.key[0], (int64_t)l.fwd.size(),
+           nn * sb * (double)l.gdev.size() + xbytes);
+        fn(SegKernelId{2, l.P, p.precision, cplx}, l.key[1], (int64_t)l.red.size(), 2.0 * xbytes);
+        fn(SegKernelId{3, l.P, p.precision, cplx}, l.key[2], (int64_t)l.inv.size(), nn * l.out_rows * eb + xbytes);
+    }
 }
 
 // Runs `launch` and, when timing is on, brackets it with events on `st`.
@@ -917,19 +987,16 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, vo
             return CWT_OK;
         }
         const double fb = p.precision == CWT_FP64 ? 16.0 : 8.0;
-        for (auto &g : p.segs)
-            if (g.kind == cwt::SegGroup::LOCAL)
-                cwt::timed(p, st, cwt::local2_kernel_name(p, g), nn * sb + nn * (double)g.scales.size() * eb,
-                           "local launch", [&] { return cwt::launch_local2(p, g, signal, out, st); });
-        for (auto &l : p.seg_launches) {
-            double xbytes = 0.0;
-            for (auto &gd : l.gdev) xbytes += (double)gd.nseg * gd.B * 16.0;
-            cwt::timed(p, st, cwt::seg_kernel_name(p, l, 0), nn * sb * (double)l.gdev.size() + xbytes,
-                       "segment spectra launch", [&] { return cwt::launch_seg(p, l, signal, workspace, out, st, 0); });
-            cwt::timed(p, st, cwt::seg_kernel_name(p, l, 1), 2.0 * xbytes, "segment reduce launch",
-                       [&] { return cwt::launch_seg(p, l, signal, workspace, out, st, 1); });
-            cwt::timed(p, st, cwt::seg_kernel_name(p, l, 2), nn * l.out_rows * eb + xbytes, "segment inverse launch",
-                       [&] { return cwt::launch_seg(p, l, signal, workspace, out, st, 2); });
+        if (!p.segs.empty()) {
+            static const char *what[4] = {"local launch", "segment spectra launch", "segment reduce launch",
+                                          "segment inverse launch"};
+            cwt::BatchArgs a{};
+            a.i0 = {signal, out, static_cast<char *>(workspace)};
+            cwt::for_each_seg_launch(p, [&](const cwt::SegKernelId &id, int32_t key, int64_t blocks, double bytes) {
+                a.k0 = p.keys[key];
+                cwt::timed(p, st, cwt::seg_kernel_id_name(id), bytes, what[id.kind],
+                           [&] { return cwt::launch_seg_kernel(id, a, blocks, st); });
+            });
         }
         if (p.M > 0)
             cwt::timed(p, st, "forward", nn * sb + (double)p.M * fb, "forward launch",
@@ -1001,12 +1068,83 @@ int cwt_plan_timing_read(cwt_plan_t plan, int32_t max_kernels, char *names, int6
     });
 }
 
+namespace cwt {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Layout of a batch workspace: the plans' own workspaces one after the
+// other, then the launch tables of the merged segmented launches.
+struct BatchLayout {
+    std::vector<size_t> ws_off;  // per instance
+    size_t tables_off = 0, bytes = 0;
+    // merged launches in execution order
+    struct Merged {
+        SegKernelId id;
+        std::vector<BatchRange> ranges;
+        std::vector<int32_t> blockmap;
+        int64_t blocks = 0;
+        double bytes = 0.0;
+        size_t ranges_off = 0, map_off = 0;  // within the tables
+    };
+    std::vector<Merged> merged;
+    size_t insts_off = 0, tables_bytes = 0;
+};
+
+static bool seg_plan(const Plan &p) { return p.method == CWT_METHOD_FFT && p.fft_mode == CWT_FFT_SEGMENTED; }
+
+static BatchLayout batch_layout(const cwt_plan_t *plans, int32_t n) {
+    BatchLayout bl;
+    size_t off = 0;
+    bl.ws_off.resize(n);
+    std::map<SegKernelId, size_t> index;
+    for (int32_t i = 0; i < n; ++i) {
+        const Plan &p = *plans[i]->p;
+        bl.ws_off[i] = off;
+        off = align256(off + p.ws_bytes);
+        if (!seg_plan(p)) continue;
+        for_each_seg_launch(p, [&](const SegKernelId &id, int32_t key, int64_t blocks, double bytes) {
+            if (blocks <= 0) return;
+            auto it = index.find(id);
+            if (it == index.end()) {
+                it = index.emplace(id, bl.merged.size()).first;
+                bl.merged.emplace_back();
+                bl.merged.back().id = id;
+            }
+            auto &m = bl.merged[it->second];
+            m.ranges.push_back({m.blocks, p.d_keys + key, i, 0});
+            m.blocks += blocks;
+            m.bytes += bytes;
+        });
+    }
+    // execution order: all local launches, then forward, reduce, inverse
+    std::sort(bl.merged.begin(), bl.merged.end(),
+              [](const BatchLayout::Merged &x, const BatchLayout::Merged &y) { return x.id < y.id; });
+    bl.tables_off = off;
+    size_t t = 0;
+    bl.insts_off = t;
+    t = align256(t + (size_t)n * sizeof(BatchInst));
+    for (auto &m : bl.merged) {
+        m.ranges_off = t;
+        t = align256(t + m.ranges.size() * sizeof(BatchRange));
+        m.map_off = t;
+        t = align256(t + (size_t)m.blocks * sizeof(int32_t));
+    }
+    bl.tables_bytes = t;
+    bl.bytes = off + t;
+    return bl;
+}
+
+}  // namespace cwt
+
 size_t cwt_batch_workspace_bytes(const cwt_plan_t *plans, int32_t n) {
     if (!plans || n <= 0) return 0;
-    size_t mx = 0;
     for (int32_t i = 0; i < n; ++i)
-        if (plans[i]) mx = std::max(mx, plans[i]->p->ws_bytes);
-    return mx;
+        if (!plans[i]) return 0;
+    try {
+        return cwt::batch_layout(plans, n).bytes;
+    } catch (...) {
+        return 0;
+    }
 }
 
 int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals, void *const *outs, int32_t n,
@@ -1016,7 +1154,49 @@ int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals, void *co
         if (n == 0) return CWT_OK;
         if (!plans || !signals || !outs) cwt::fail(CWT_EINVAL, "NULL array");
         for (int32_t i = 0; i < n; ++i) {
-            int rc = cwt_exec(plans[i], signals[i], outs[i], workspace, stream);
+            if (!plans[i]) cwt::fail(CWT_EINVAL, "plan is NULL");
+            const Plan &p = *plans[i]->p;
+            if (p.host_only) cwt::fail(CWT_EINVAL, "plan was built host-only");
+            if (!signals[i] || !outs[i]) cwt::fail(CWT_EINVAL, "signal/out is NULL");
+            const size_t ealign = p.precision == CWT_FP64 ? 8 : 4;
+            if ((uintptr_t)signals[i] % ealign || (uintptr_t)outs[i] % ealign)
+                cwt::fail(CWT_EINVAL, "signal/out not aligned to the element size");
+        }
+        if (!workspace) cwt::fail(CWT_EINVAL, "workspace is NULL");
+        if ((uintptr_t)workspace % 256) cwt::fail(CWT_EINVAL, "workspace not 256-byte aligned");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        cwt::BatchLayout bl = cwt::batch_layout(plans, n);
+        char *ws = static_cast<char *>(workspace);
+        char *tables = ws + bl.tables_off;
+        if (!bl.merged.empty()) {
+            // launch tables, copied in one transfer (the host buffer may be
+            // released once the call returns: pageable copies are staged)
+            std::vector<char> host(bl.tables_bytes, 0);
+            auto *insts = reinterpret_cast<cwt::BatchInst *>(host.data() + bl.insts_off);
+            for (int32_t i = 0; i < n; ++i) insts[i] = {signals[i], outs[i], ws + bl.ws_off[i]};
+            for (auto &m : bl.merged) {
+                std::memcpy(host.data() + m.ranges_off, m.ranges.data(), m.ranges.size() * sizeof(cwt::BatchRange));
+                auto *map = reinterpret_cast<int32_t *>(host.data() + m.map_off);
+                for (size_t r = 0; r < m.ranges.size(); ++r) {
+                    const int64_t end = r + 1 < m.ranges.size() ? m.ranges[r + 1].block0 : m.blocks;
+                    for (int64_t b = m.ranges[r].block0; b < end; ++b) map[b] = (int32_t)r;
+                }
+            }
+            HIPCHK(hipMemcpyAsync(tables, host.data(), host.size(), hipMemcpyHostToDevice, st));
+            Plan &tp = *plans[0]->p;  // timing records go to the first plan
+            for (auto &m : bl.merged) {
+                cwt::BatchArgs a{};
+                a.ranges = reinterpret_cast<const cwt::BatchRange *>(tables + m.ranges_off);
+                a.blockmap = reinterpret_cast<const int32_t *>(tables + m.map_off);
+                a.insts = reinterpret_cast<const cwt::BatchInst *>(tables + bl.insts_off);
+                a.nranges = (int32_t)m.ranges.size();
+                cwt::timed(tp, st, cwt::seg_kernel_id_name(m.id), m.bytes, "batched segment launch",
+                           [&] { return cwt::launch_seg_kernel(m.id, a, m.blocks, st); });
+            }
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            if (cwt::seg_plan(*plans[i]->p)) continue;
+            int rc = cwt_exec(plans[i], signals[i], outs[i], ws + bl.ws_off[i], stream);
             if (rc != CWT_OK) return rc;
         }
         return CWT_OK;

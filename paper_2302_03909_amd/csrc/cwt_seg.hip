@@ -79,17 +79,72 @@ __device__ __forceinline__ double bload(const double *, __amdgpu_buffer_rsrc_t r
 template <typename C> __device__ __forceinline__ C to_c(double2 v) { return mk<C>((decltype(C::x))v.x, (decltype(C::x))v.y); }
 template <typename C> __device__ __forceinline__ double2 to_d(C v) { return make_double2((double)v.x, (double)v.y); }
 
+// Read-only data that every lane of a workgroup reads at the same address:
+// loaded through the constant address space, i.e. with scalar loads into
+// scalar registers (the tables are never written while a launch runs).
+template <typename T> __device__ __forceinline__ T cload(const T *p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) T *)p;
+#else
+    return *p;  // host pass of the kernel templates; never executed
+#endif
+}
+
+// Values that are the same in every lane, marked as such so that they stay in
+// scalar registers (buffer descriptors built from them must be scalar).
+__device__ __forceinline__ int64_t uni(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T> __device__ __forceinline__ T *uni(T *p) { return (T *)uni((int64_t)p); }
+template <typename T> __device__ __forceinline__ const T *uni(const T *p) { return (const T *)uni((int64_t)p); }
+
+// The launch key, caller buffers and local block index of this workgroup.
+struct Resolved {
+    KeyDesc kd;
+    BatchInst bi;
+    int64_t local;
+};
+__device__ __forceinline__ Resolved resolve(const BatchArgs &a) {
+    Resolved rv;
+    if (a.nranges == 0) {
+        rv = {a.k0, a.i0, (int64_t)blockIdx.x};
+    } else {
+        const BatchRange r = cload(a.ranges + cload(a.blockmap + blockIdx.x));
+        rv = {cload(r.key), cload(a.insts + r.inst), (int64_t)blockIdx.x - r.block0};
+    }
+    rv.bi.f = uni(rv.bi.f);
+    rv.bi.out = uni(rv.bi.out);
+    rv.bi.ws = uni(rv.bi.ws);
+    rv.local = uni(rv.local);
+    KeyDesc &k = rv.kd;
+    k.N = uni(k.N);
+    k.Tg = uni(k.Tg);
+    k.V = uni(k.V);
+    k.nseg = uni(k.nseg);
+    k.groups = uni(k.groups);
+    k.units = uni(k.units);
+    k.work = uni(k.work);
+    k.ktab = uni(k.ktab);
+    k.twbase = uni(k.twbase);
+    k.twl = uni(k.twl);
+    k.twl64 = uni(k.twl64);
+    k.whi = uni(k.whi);
+    k.wlo = uni(k.wlo);
+    k.scale_ids = uni(k.scale_ids);
+    k.periodic = __builtin_amdgcn_readfirstlane(k.periodic);
+    k.cph = __builtin_amdgcn_readfirstlane(k.cph);
+    k.nscale = __builtin_amdgcn_readfirstlane(k.nscale);
+    return rv;
+}
+
 // ---------------------------------------------------------------------------
 // pruned forward transform of the segments, partial sums per column chunk.
 // Work item (g, seg, chunk): columns q in [chunk * iters * 16, +iters * 16).
 
 template <typename R, int P, int NT>
-__global__ __launch_bounds__(NT) void seg_forward_kernel(const R *__restrict__ f, int64_t N, int periodic,
-                                                         const SegGroupDev *__restrict__ groups,
-                                                         const SegWork *__restrict__ work,
-                                                         const cplx_t<R> *__restrict__ twl_g,
-                                                         const double2 *__restrict__ whi,
-                                                         const double2 *__restrict__ wlo, char *__restrict__ ws) {
+__global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
     using C = cplx_t<R>;
     constexpr int G = 16;
     constexpr int LD = lds_len(P);
@@ -97,9 +152,16 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const R *__restrict__ f
     static_assert(NT >= P && (G * P) % NT == 0, "launch shape");
     __shared__ C buf[G * LD];
     __shared__ C twl[twl_len(P)];
-    load_twl<C, P, NT>(twl, twl_g);
-    const SegWork w = work[blockIdx.x];
-    const SegGroupDev gd = groups[w.g];
+    const Resolved rv = resolve(a);
+    const KeyDesc *kd = &rv.kd;
+    const R *__restrict__ f = static_cast<const R *>(rv.bi.f);
+    char *__restrict__ ws = rv.bi.ws;
+    const int64_t N = kd->N;
+    const int periodic = kd->periodic;
+    const double2 *__restrict__ whi = kd->whi, *__restrict__ wlo = kd->wlo;
+    load_twl<C, P, NT>(twl, static_cast<const C *>(kd->twl));
+    const SegWork w = cload(kd->work + rv.local);
+    const SegGroupDev gd = cload(kd->groups + w.g);
     const int64_t L = int64_t(1) << gd.lgL, Q = L >> log2_exact(P);
     const int sh = 23 - gd.lgL;
     const int64_t x0 = (int64_t)w.seg * gd.V - gd.Tg;
@@ -165,11 +227,12 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const R *__restrict__ f
 
 // X[seg][k] = sum over the column chunks of the partial sums, 16 bins per
 // workgroup, 16 lanes per bin, fixed summation order
-__global__ __launch_bounds__(256) void seg_reduce_kernel(const SegGroupDev *__restrict__ groups,
-                                                         const SegWork *__restrict__ work, char *__restrict__ ws) {
+__global__ __launch_bounds__(256) void seg_reduce_kernel(const BatchArgs args) {
     __shared__ double2 part[256];
-    const SegWork w = work[blockIdx.x];
-    const SegGroupDev gd = groups[w.g];
+    const Resolved rv = resolve(args);
+    char *__restrict__ ws = rv.bi.ws;
+    const SegWork w = cload(rv.kd.work + rv.local);
+    const SegGroupDev gd = cload(rv.kd.groups + w.g);
     const int kb = threadIdx.x / 16, lane = threadIdx.x % 16;
     const int k = w.idx * 16 + kb;
     const double2 *Xp = reinterpret_cast<const double2 *>(ws + gd.xp_off);
@@ -200,14 +263,8 @@ constexpr int seg_kls_elems(int rbytes, int P) {
 // segment for every output unit of the group
 
 template <typename R, int P, int NT, bool PAIR, bool CPLX>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void seg_inverse_kernel(int64_t N, const SegGroupDev *__restrict__ groups,
-                                                         const SegUnit *__restrict__ units,
-                                                         const SegWork *__restrict__ work,
-                                                         const char *__restrict__ ws, const R *__restrict__ ktab,
-                                                         int cph, const char *__restrict__ twbase,
-                                                         const cplx_t<R> *__restrict__ twl_g,
-                                                         const double2 *__restrict__ whi,
-                                                         const double2 *__restrict__ wlo, R *__restrict__ out) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void seg_inverse_kernel(
+    const BatchArgs a) {
     using C = cplx_t<R>;
     constexpr int G = 16;
     constexpr int LD = lds_len(P);
@@ -219,9 +276,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     __shared__ C twl[twl_len(P)];
     __shared__ SegUnit us[MAXU];
     __shared__ R kls[KLS];  // spectrum samples of the group's units (and pair partners)
-    load_twl<C, P, NT>(twl, twl_g);
-    const SegWork w = work[blockIdx.x];
-    const SegGroupDev gd = groups[w.g];
+    const Resolved rv = resolve(a);
+    const KeyDesc *kd = &rv.kd;
+    const char *__restrict__ ws = rv.bi.ws;
+    R *__restrict__ out = static_cast<R *>(rv.bi.out);
+    const int64_t N = kd->N;
+    const int cph = kd->cph;
+    const R *__restrict__ ktab = static_cast<const R *>(kd->ktab);
+    const char *__restrict__ twbase = kd->twbase;
+    const SegUnit *__restrict__ units = kd->units;
+    const double2 *__restrict__ whi = kd->whi, *__restrict__ wlo = kd->wlo;
+    load_twl<C, P, NT>(twl, static_cast<const C *>(kd->twl));
+    const SegWork w = cload(kd->work + rv.local);
+    const SegGroupDev gd = cload(kd->groups + w.g);
     const int nunits = gd.nunits < MAXU ? gd.nunits : MAXU;
     for (int u = threadIdx.x; u < nunits; u += NT) us[u] = units[gd.unit0 + u];
     const int64_t L = int64_t(1) << gd.lgL, Q = L >> log2_exact(P);
@@ -315,32 +382,46 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
 // fused full-spectrum segments (small scales)
 
 template <typename R, int L, int NCOL, int NT, bool PAIR, bool CPLX>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2))) void local2_kernel(const R *__restrict__ f, int64_t N, int periodic, int64_t Tg,
-                                                    int64_t V, int64_t nseg, int nscale,
-                                                    const int32_t *__restrict__ scale_ids,
-                                                    const R *__restrict__ ktab, int cph,
-                                                    const cplx_t<R> *__restrict__ twl_g, R *__restrict__ out) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void local2_kernel(
+    const BatchArgs a) {
     using C = cplx_t<R>;
     constexpr int LD = lds_len(L);
     constexpr int E = NCOL * L / NT;
     static_assert((NCOL * L) % NT == 0, "whole elements per thread");
-    __shared__ C buf[NCOL * LD];
+    // The segment transform is taken in FP64 whatever the plan precision:
+    // an FP32 forward spreads rounding noise of order eps |f| over every bin,
+    // which for red spectra swamps the weak high-frequency bands the small
+    // scales read.  The FP32 inverse buffer aliases the FP64 one.
+    __shared__ double2 bufF[NCOL * LD];
+    C *buf = reinterpret_cast<C *>(bufF);
     __shared__ C twl[twl_len(L)];
-    load_twl<C, L, NT>(twl, twl_g);
+    const Resolved rv = resolve(a);
+    const KeyDesc *kd = &rv.kd;
+    const R *__restrict__ f = static_cast<const R *>(rv.bi.f);
+    R *__restrict__ out = static_cast<R *>(rv.bi.out);
+    const int64_t N = kd->N, Tg = kd->Tg, V = kd->V, nseg = kd->nseg;
+    const int periodic = kd->periodic, nscale = kd->nscale, cph = kd->cph;
+    const int32_t *__restrict__ scale_ids = kd->scale_ids;
+    const R *__restrict__ ktab = static_cast<const R *>(kd->ktab);
+    load_twl<C, L, NT>(twl, static_cast<const C *>(kd->twl));
+    // FP64 forward twiddles: the LDS table for FP64 plans, else the plan's
+    // FP64 table in global memory
+    const double2 *twF = sizeof(R) == 8 ? reinterpret_cast<const double2 *>(twl)
+                                        : static_cast<const double2 *>(kd->twl64);
     const int tid = threadIdx.x;
     constexpr int SEGS = PAIR ? 2 : 1;
-    const int64_t seg0 = (int64_t)blockIdx.x * NCOL * SEGS;
+    const int64_t seg0 = rv.local * NCOL * SEGS;
     for (int idx = tid; idx < NCOL * L; idx += NT) {
         int c = idx / L, u = idx % L;
         int64_t s = seg0 + (int64_t)c * SEGS;
-        R a = sig_seg(f, N, periodic, s * V - Tg + u);
-        R b = PAIR ? sig_seg(f, N, periodic, (s + 1) * V - Tg + u) : (R)0;
-        buf[c * LD + lidx(u)] = mk<C>(a, b);
+        double a = (double)sig_seg(f, N, periodic, s * V - Tg + u);
+        double b = PAIR ? (double)sig_seg(f, N, periodic, (s + 1) * V - Tg + u) : 0.0;
+        bufF[c * LD + lidx(u)] = make_double2(a, b);
     }
     __syncthreads();
     {
-        auto emit = [&](int c, int p, C v) { buf[c * LD + lidx(p)] = v; };
-        cols_fft<C, L, NCOL, NT, LD, -1, true>(buf, twl, emit);
+        auto emit = [&](int c, int p, double2 v) { bufF[c * LD + lidx(p)] = v; };
+        cols_fft<double2, L, NCOL, NT, LD, -1, true, decltype(emit), sizeof(R) == 4>(bufF, twF, emit);
     }
     __syncthreads();
     // spectra in registers in the pass-0 layout of the inverse transforms:
@@ -350,7 +431,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const int cc = tid / NB, ii = tid % NB;
     C Xr[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) Xr[r] = mul_i_pow(buf[cc * LD + lidx(ii + r * NB)], cph);  // phase i^cph folded in
+    for (int r = 0; r < 16; ++r)  // phase i^cph folded in
+        Xr[r] = to_c<C>(mul_i_pow(bufF[cc * LD + lidx(ii + r * NB)], cph));
     R kv[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) kv[r] = ktab[ii + r * NB];
@@ -369,7 +451,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
         cols_pass0_regs<C, L, NCOL, NT, LD, +1>(buf, v);
         constexpr uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
         const __amdgpu_buffer_rsrc_t rr =
-            make_rsrc(out + (int64_t)scale_ids[j] * N * (CPLX ? 2 : 1), (uint32_t)(N * eb));
+            make_rsrc(out + (int64_t)cload(scale_ids + j) * N * (CPLX ? 2 : 1), (uint32_t)(N * eb));
         auto emit = [&](int c, int p, C val) {
             const bool inside = p >= Tg && p < Tg + V;
             const int64_t sgi = seg0 + (int64_t)c * SEGS;
@@ -393,55 +475,35 @@ static constexpr int local2_ncol(int L) { return L >= 1024 ? 1 : 1024 / L; }
 static constexpr int local2_nt(int L) { return local2_ncol(L) * L / 16 < 64 ? 64 : local2_ncol(L) * L / 16; }
 
 bool local2_size_ok(int L, int precision) {
-    int lmax = precision == 0 ? 4096 : 8192;
+    (void)precision;
+    int lmax = 4096;
     return L >= 64 && L <= lmax && (L & (L - 1)) == 0;
 }
 int local2_segs_per_block(int L, bool pair) { return local2_ncol(L) * (pair ? 2 : 1); }
 
 template <typename R, int L>
-static hipError_t local2_launch_L(const Plan &p, const SegGroup &g, const R *f, R *out, hipStream_t st) {
+static hipError_t local2_launch_L(const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
     constexpr int NCOL = local2_ncol(L);
     constexpr int NT = local2_nt(L);
-    using C = cplx_t<R>;
-    const R *ktab = static_cast<const R *>(p.d_tab) + g.tab_off;
-    const C *twl = tw_at<C>(p, g.twl_off);
-    int periodic = p.boundary == 0 ? 1 : 0;
-    int64_t per = (int64_t)NCOL * (p.pair_real ? 2 : 1);
-    int64_t grid = (g.nseg + per - 1) / per;
-    if (grid <= 0) return hipSuccess;
-    if (p.cplx_out)
-        hipLaunchKernelGGL((local2_kernel<R, L, NCOL, NT, false, true>), dim3((unsigned)grid), dim3(NT), 0, st, f, p.N,
-                           periodic, g.Tg, g.V, g.nseg, (int)g.scales.size(), g.d_scales, ktab, p.cph, twl, out);
-    else if (p.pair_real)
-        hipLaunchKernelGGL((local2_kernel<R, L, NCOL, NT, true, false>), dim3((unsigned)grid), dim3(NT), 0, st, f, p.N,
-                           periodic, g.Tg, g.V, g.nseg, (int)g.scales.size(), g.d_scales, ktab, p.cph, twl, out);
+    if (cplx)
+        hipLaunchKernelGGL((local2_kernel<R, L, NCOL, NT, false, true>), dim3((unsigned)blocks), dim3(NT), 0, st, a);
     else
-        hipLaunchKernelGGL((local2_kernel<R, L, NCOL, NT, false, false>), dim3((unsigned)grid), dim3(NT), 0, st, f, p.N,
-                           periodic, g.Tg, g.V, g.nseg, (int)g.scales.size(), g.d_scales, ktab, p.cph, twl, out);
+        hipLaunchKernelGGL((local2_kernel<R, L, NCOL, NT, true, false>), dim3((unsigned)blocks), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
 template <typename R>
-static hipError_t local2_typed(const Plan &p, const SegGroup &g, const R *f, R *o, hipStream_t st) {
-    switch (g.L) {
-        case 64: return local2_launch_L<R, 64>(p, g, f, o, st);
-        case 128: return local2_launch_L<R, 128>(p, g, f, o, st);
-        case 256: return local2_launch_L<R, 256>(p, g, f, o, st);
-        case 512: return local2_launch_L<R, 512>(p, g, f, o, st);
-        case 1024: return local2_launch_L<R, 1024>(p, g, f, o, st);
-        case 2048: return local2_launch_L<R, 2048>(p, g, f, o, st);
-        case 4096: return local2_launch_L<R, 4096>(p, g, f, o, st);
-        case 8192:
-            if constexpr (sizeof(R) == 4) return local2_launch_L<R, 8192>(p, g, f, o, st);
-            return hipErrorInvalidValue;
+static hipError_t local2_typed(int L, const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
+    switch (L) {
+        case 64: return local2_launch_L<R, 64>(a, blocks, cplx, st);
+        case 128: return local2_launch_L<R, 128>(a, blocks, cplx, st);
+        case 256: return local2_launch_L<R, 256>(a, blocks, cplx, st);
+        case 512: return local2_launch_L<R, 512>(a, blocks, cplx, st);
+        case 1024: return local2_launch_L<R, 1024>(a, blocks, cplx, st);
+        case 2048: return local2_launch_L<R, 2048>(a, blocks, cplx, st);
+        case 4096: return local2_launch_L<R, 4096>(a, blocks, cplx, st);
         default: return hipErrorInvalidValue;
     }
-}
-
-hipError_t launch_local2(const Plan &p, const SegGroup &g, const void *signal, void *out, hipStream_t st) {
-    if (p.precision == 0)
-        return local2_typed(p, g, static_cast<const double *>(signal), static_cast<double *>(out), st);
-    return local2_typed(p, g, static_cast<const float *>(signal), static_cast<float *>(out), st);
 }
 
 bool seg_size_ok(int P, int precision) {
@@ -451,65 +513,50 @@ bool seg_size_ok(int P, int precision) {
 }
 
 template <typename R, int P>
-static hipError_t seg_launch_P(const Plan &p, const SegLaunch &l, const R *f, void *ws, R *out, hipStream_t st,
-                               int phase) {
+static hipError_t seg_launch_P(int kind, const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
     constexpr int NT = P;  // 16 columns x P / 16 elements per thread
-    using C = cplx_t<R>;
-    char *w = static_cast<char *>(ws);
-    const C *twl = tw_at<C>(p, l.twl_off);
-    const double2 *whi = tw_at<double2>(p, p.w23_hi_off), *wlo = tw_at<double2>(p, p.w23_lo_off);
-    int periodic = p.boundary == 0 ? 1 : 0;
-    if (phase == 0) {
-        if (l.fwd.empty()) return hipSuccess;
-        hipLaunchKernelGGL((seg_forward_kernel<R, P, NT>), dim3((unsigned)l.fwd.size()), dim3(NT), 0, st, f, p.N,
-                           periodic, l.d_groups, l.d_fwd, twl, whi, wlo, w);
-        return hipGetLastError();
-    }
-    if (phase == 1) {
-        if (l.red.empty()) return hipSuccess;
-        hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)l.red.size()), dim3(256), 0, st, l.d_groups, l.d_red, w);
-        return hipGetLastError();
-    }
-    if (l.inv.empty()) return hipSuccess;
-    const R *ktab = static_cast<const R *>(p.d_tab);
-    const char *twbase = static_cast<const char *>(p.d_tw_all);
-    if (p.cplx_out)
-        hipLaunchKernelGGL((seg_inverse_kernel<R, P, NT, false, true>), dim3((unsigned)l.inv.size()), dim3(NT), 0, st,
-                           p.N, l.d_groups, p.d_units, l.d_inv, w, ktab, p.cph, twbase, twl, whi, wlo, out);
+    if (kind == 1)
+        hipLaunchKernelGGL((seg_forward_kernel<R, P, NT>), dim3((unsigned)blocks), dim3(NT), 0, st, a);
+    else if (kind == 2)
+        hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    else if (cplx)
+        hipLaunchKernelGGL((seg_inverse_kernel<R, P, NT, false, true>), dim3((unsigned)blocks), dim3(NT), 0, st, a);
     else
-        hipLaunchKernelGGL((seg_inverse_kernel<R, P, NT, true, false>), dim3((unsigned)l.inv.size()), dim3(NT), 0, st,
-                           p.N, l.d_groups, p.d_units, l.d_inv, w, ktab, p.cph, twbase, twl, whi, wlo, out);
+        hipLaunchKernelGGL((seg_inverse_kernel<R, P, NT, true, false>), dim3((unsigned)blocks), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
 template <typename R>
-static hipError_t seg_typed(const Plan &p, const SegLaunch &l, const R *f, void *ws, R *o, hipStream_t st, int phase) {
-    switch (l.P) {
-        case 64: return seg_launch_P<R, 64>(p, l, f, ws, o, st, phase);
-        case 128: return seg_launch_P<R, 128>(p, l, f, ws, o, st, phase);
-        case 256: return seg_launch_P<R, 256>(p, l, f, ws, o, st, phase);
-        case 512: return seg_launch_P<R, 512>(p, l, f, ws, o, st, phase);
+static hipError_t seg_typed(int kind, int P, const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
+    switch (P) {
+        case 64: return seg_launch_P<R, 64>(kind, a, blocks, cplx, st);
+        case 128: return seg_launch_P<R, 128>(kind, a, blocks, cplx, st);
+        case 256: return seg_launch_P<R, 256>(kind, a, blocks, cplx, st);
+        case 512: return seg_launch_P<R, 512>(kind, a, blocks, cplx, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_seg(const Plan &p, const SegLaunch &l, const void *signal, void *ws, void *out, hipStream_t st,
-                      int phase) {
-    if (p.precision == 0)
-        return seg_typed(p, l, static_cast<const double *>(signal), ws, static_cast<double *>(out), st, phase);
-    return seg_typed(p, l, static_cast<const float *>(signal), ws, static_cast<float *>(out), st, phase);
+hipError_t launch_seg_kernel(const SegKernelId &id, const BatchArgs &a, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const bool fp64 = id.precision == 0, cplx = id.cplx != 0;
+    if (id.kind == 0)
+        return fp64 ? local2_typed<double>(id.size, a, blocks, cplx, st) : local2_typed<float>(id.size, a, blocks, cplx, st);
+    if (id.kind == 2) return seg_launch_P<float, 64>(2, a, blocks, cplx, st);  // precision-free
+    return fp64 ? seg_typed<double>(id.kind, id.size, a, blocks, cplx, st)
+                : seg_typed<float>(id.kind, id.size, a, blocks, cplx, st);
 }
 
-std::string local2_kernel_name(const Plan &p, const SegGroup &g) {
-    std::string t = p.precision == 0 ? "f64," : "f32,";
-    return "local2_kernel<" + t + std::to_string(g.L) + (p.cplx_out ? ",complex>" : ",real-pair>");
-}
-
-std::string seg_kernel_name(const Plan &p, const SegLaunch &l, int phase) {
-    std::string t = p.precision == 0 ? "f64," : "f32,";
-    if (phase == 0) return "seg_forward_kernel<" + t + std::to_string(l.P) + ">";
-    if (phase == 1) return "seg_reduce_kernel<" + t + std::to_string(l.P) + ">";
-    return "seg_inverse_kernel<" + t + std::to_string(l.P) + (p.cplx_out ? ",complex>" : ",real-pair>");
+std::string seg_kernel_id_name(const SegKernelId &id) {
+    const std::string t = id.precision == 0 ? "f64," : "f32,";
+    const std::string c = id.cplx ? ",complex>" : ",real-pair>";
+    switch (id.kind) {
+        case 0: return "local2_kernel<" + t + std::to_string(id.size) + c;
+        case 1: return "seg_forward_kernel<" + t + std::to_string(id.size) + ">";
+        case 2: return "seg_reduce_kernel<" + t + std::to_string(id.size) + ">";
+        default: return "seg_inverse_kernel<" + t + std::to_string(id.size) + c;
+    }
 }
 
 }  // namespace cwt

@@ -24,7 +24,23 @@ constexpr int twl_len(int P) { return twl_off(P, num_passes(P)) > 0 ? twl_off(P,
 
 // middle pass: LDS -> LDS, column-major thread mapping (consecutive threads
 // take consecutive butterflies of one column)
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS>
+// Twiddles of a butterfly: e^{+2 pi i r k/(R Ns)}, r = 1..R-1, read from the
+// table (TWREC = false) or, TWREC = true, only r = 1 read and the others
+// formed as its powers (one table read per butterfly; used by the FP64
+// segment transforms of FP32 plans, whose table sits in global memory).
+template <typename C, int R, int NS, bool TWREC>
+__device__ __forceinline__ void twiddles(const C *tp, C (&w)[R]) {
+    if constexpr (TWREC) {
+        w[1] = tp[0];
+#pragma unroll
+        for (int r = 2; r < R; ++r) w[r] = cmul(w[r - 1], w[1]);
+    } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[r] = tp[(r - 1) * NS];
+    }
+}
+
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS, bool TWREC = false>
 __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
     constexpr int R = radix_of(P, PASS);
     constexpr int NS = ns_before(P, PASS);
@@ -49,12 +65,10 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
             int c = gb / (P / R), i = gb % (P / R);
             int k = i % NS;
             if constexpr (NS > 1) {
-                const C *tp = twl + twl_off(P, PASS) + k;
+                C w[R];
+                twiddles<C, R, NS, TWREC>(twl + twl_off(P, PASS) + k, w);
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    C w = tp[(r - 1) * NS];
-                    v[q][r] = SIGN > 0 ? cmul(v[q][r], w) : cmulc(v[q][r], w);
-                }
+                for (int r = 1; r < R; ++r) v[q][r] = SIGN > 0 ? cmul(v[q][r], w[r]) : cmulc(v[q][r], w[r]);
             }
             dftR<R, SIGN>(v[q]);
             int base = (i - k) * R + k;
@@ -69,7 +83,7 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
 // butterfly of consecutive columns), outputs go to emit(col, p, value).
 // SYNC: barrier between the LDS reads and the emits (needed when emit writes
 // back into buf).
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC, class F>
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC, class F, bool TWREC = false>
 __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
     constexpr int PASS = num_passes(P) - 1;
     constexpr int R = radix_of(P, PASS);
@@ -94,12 +108,10 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
         if (NB % NT == 0 || gb < NB) {
             int c = gb % NCOL, i = gb / NCOL;
             if constexpr (NS > 1) {
-                const C *tp = twl + twl_off(P, PASS) + i;
+                C w[R];
+                twiddles<C, R, NS, TWREC>(twl + twl_off(P, PASS) + i, w);
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    C w = tp[(r - 1) * NS];
-                    v[q][r] = SIGN > 0 ? cmul(v[q][r], w) : cmulc(v[q][r], w);
-                }
+                for (int r = 1; r < R; ++r) v[q][r] = SIGN > 0 ? cmul(v[q][r], w[r]) : cmulc(v[q][r], w[r]);
             }
             dftR<R, SIGN>(v[q]);
 #pragma unroll
@@ -108,20 +120,20 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
     }
 }
 
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS>
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS, bool TWREC = false>
 __device__ __forceinline__ void cols_mid_from(C *buf, const C *twl) {
     if constexpr (PASS + 1 < num_passes(P)) {
-        cols_pass_mid<C, P, NCOL, NT, LD, SIGN, PASS>(buf, twl);
-        cols_mid_from<C, P, NCOL, NT, LD, SIGN, PASS + 1>(buf, twl);
+        cols_pass_mid<C, P, NCOL, NT, LD, SIGN, PASS, TWREC>(buf, twl);
+        cols_mid_from<C, P, NCOL, NT, LD, SIGN, PASS + 1, TWREC>(buf, twl);
     }
 }
 
 // Full transform of NCOL columns in buf (filled and synchronised by the
 // caller).  Outputs are emitted in natural order positions p.
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC_LAST, class F>
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC_LAST, class F, bool TWREC = false>
 __device__ __forceinline__ void cols_fft(C *buf, const C *twl, F &emit) {
-    cols_mid_from<C, P, NCOL, NT, LD, SIGN, 0>(buf, twl);
-    cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST>(buf, twl, emit);
+    cols_mid_from<C, P, NCOL, NT, LD, SIGN, 0, TWREC>(buf, twl);
+    cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST, F, TWREC>(buf, twl, emit);
 }
 
 // Pass 0 (radix 16, Ns = 1) from registers: thread t owns butterfly

@@ -111,3 +111,15 @@ def test_host_only_periodic_smooth_uses_n():
     assert p.fft_len == 4096 * 9
     q = cwt.Plan(5000, "periodic", "mexhat", [2.0, 900.0], host_only=True, fft_mode="whole")
     assert q.fft_len >= 5000 + 2 * math.ceil(8 * 900)
+
+
+def test_batch_workspace_layout_host_only():
+    # the batch workspace holds every plan's own workspace (256-aligned) plus
+    # the launch tables of the merged launches
+    plans = [cwt.Plan(n, "zero", "morlet", [2.0, 30.0, 500.0], param=6.0, precision="fp32", host_only=True)
+             for n in (1000, 5000, 20000)]
+    total = sum((p.workspace_bytes + 255) // 256 * 256 for p in plans)
+    wb = cwt.batch_workspace_bytes(plans)
+    assert wb > total
+    assert cwt.batch_workspace_bytes(plans[:1]) <= wb
+    assert cwt.batch_workspace_bytes([]) == 0
