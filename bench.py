@@ -15,7 +15,10 @@ that takes most of the step and the FP64 oracle timed on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--method fft|spline]
                     [--wavelet morlet|dog2|mexhat] [--boundary zero|periodic]
-                    [--no-cpu-baseline] [--copy-calibration]
+                    [--no-cpu-baseline] [--copy-calibration] [--batch COUNT]
+
+--batch COUNT times cwt_exec_batch over COUNT uneven instances instead (4096
+is the batched workload).
 """
 from __future__ import annotations
 
@@ -125,6 +128,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--method", default="fft", choices=["fft", "spline"])
+    ap.add_argument("--batch", type=int, default=0,
+                    help="time cwt_exec_batch on this many uneven instances instead (lengths 2^10..2^16, "
+                         "16..96 scales, Morlet(6) / Mexican hat, half periodic tones, half zero-boundary "
+                         "lognormal fields, FP32 form); 4096 is the batched workload")
     ap.add_argument("--wavelet", default=None, choices=["morlet", "dog2", "mexhat"])
     ap.add_argument("--boundary", default="zero", choices=["zero", "periodic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -143,6 +150,8 @@ def main():
     import paper_2302_03909_amd as cwt
     import synth
 
+    if args.batch > 0:
+        return bench_batch(args)
     if args.method == "fft":
         n, nscales, smax, precision = 1 << 22, 128, 2.0 ** 16, "fp32"
         seed, nname = synth.SEED_FIELD_4M, "2^22"
@@ -235,6 +244,67 @@ def main():
                        "scale_range": [2, int(smax)], "boundary": args.boundary, "wavelet": wname,
                        "precision": precision},
             "roofline": roof, "whole_step": whole, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args):
+    """One step = one cwt_exec_batch call over every instance (signals and
+    outputs resident in device memory)."""
+    import numpy as np
+    import torch
+    import paper_2302_03909_amd as cwt
+    import synth
+
+    dev = torch.device("cuda", 0)
+    print(f"bench: drawing {args.batch} instances", file=sys.stderr, flush=True)
+    insts = synth.batch_specs(count=args.batch)
+    t0 = time.perf_counter()
+    plans, sigs, outs = [], [], []
+    for k, inst in enumerate(insts):
+        if k % 512 == 0:
+            print(f"bench: planning instance {k} of {len(insts)}", file=sys.stderr, flush=True)
+        par = 6.0 if inst.wavelet == "morlet" else None
+        plans.append(cwt.Plan(inst.n, inst.boundary, inst.wavelet, inst.scales, param=par, precision="fp32"))
+        sigs.append(torch.as_tensor(inst.signal.astype(np.float32), device=dev))
+        outs.append(plans[-1].empty_output(dev))
+    plan_s = time.perf_counter() - t0
+    ws = torch.empty(cwt.batch_workspace_bytes(plans), dtype=torch.uint8, device=dev)
+    coeffs = sum(i.coefficients for i in insts)
+    out_bytes = sum(o.numel() * o.element_size() for o in outs)
+    for _ in range(args.warmup):
+        cwt.exec_batch(plans, sigs, outs, ws)
+    torch.cuda.synchronize()
+    plans[0].timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cwt.exec_batch(plans, sigs, outs, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plans[0].timing(False)
+    kern = plans[0].timing_read()
+    ms = (t1 - t0) * 1e3 / args.steps
+    name, (cnt, tot_ms, bpl) = max(kern.items(), key=lambda kv: kv[1][1])
+    avg_s = tot_ms / cnt * 1e-3
+    achieved = bpl / avg_s / 1e9
+    workload = (f"batch of {args.batch} uneven instances: N log-uniform 2^10..2^16, 16..96 log scales "
+                f"2..min(N/8, 2^16), Morlet(6) / Mexican hat, half periodic tones, half zero-boundary "
+                f"lognormal fields, fp32 form")
+    line = {"metric": "CWT coefficients/sec (N x scales) and % HBM peak at N=2^22, 128 scales",
+            "value": coeffs / (ms * 1e-3), "unit": "coefficients/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": workload, "instances": args.batch, "coefficients": coeffs,
+                       "plan_seconds": round(plan_s, 2)},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
+                         "kernel": name, "avg_launch_ms": round(tot_ms / cnt, 4),
+                         "algorithmic_bytes_per_launch": bpl},
+            "whole_step": {"output_bytes": out_bytes,
+                           "hbm_frac_of_output_write": round(out_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "kernels": {k: {"launches": v[0], "ms_per_step": round(v[1] / args.steps, 4),
+                                           "bytes_per_launch": v[2]} for k, v in kern.items()}},
+            "cpu_baseline": None}
     print(json.dumps(line), flush=True)
 
 

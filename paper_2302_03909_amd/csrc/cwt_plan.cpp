@@ -9,6 +9,8 @@
 #include <cmath>
 #include <complex>
 #include <map>
+#include <tuple>
+#include <mutex>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -24,7 +26,17 @@ namespace cwt {
 static thread_local std::string g_err;
 
 // radius beyond which |psi| < rel * max|psi|
+static double time_radius_scan(const Wavelet &w, double rel);
 static double time_radius(const Wavelet &w, double rel) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, double, int, double>, double> cache;
+    const auto key = std::make_tuple(w.kind, w.w0, w.m, rel);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    return cache[key] = time_radius_scan(w, rel);
+}
+static double time_radius_scan(const Wavelet &w, double rel) {
     const double step = 1.0 / 1024.0;
     double mx = 0.0;
     for (int i = 0; i <= 64 * 1024; ++i) mx = std::max(mx, w.abs_time(i * step));
@@ -35,7 +47,22 @@ static double time_radius(const Wavelet &w, double rel) {
 }
 
 // [ulo, uhi] outside of which |psi^(u)| < rel * max|psi^|
+static void spectral_band_scan(const Wavelet &w, double rel, double &ulo, double &uhi);
 static void spectral_band(const Wavelet &w, double rel, double &ulo, double &uhi) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, double, int, double>, std::pair<double, double>> cache;
+    const auto key = std::make_tuple(w.kind, w.w0, w.m, rel);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        double a, b;
+        spectral_band_scan(w, rel, a, b);
+        it = cache.emplace(key, std::make_pair(a, b)).first;
+    }
+    ulo = it->second.first;
+    uhi = it->second.second;
+}
+static void spectral_band_scan(const Wavelet &w, double rel, double &ulo, double &uhi) {
     const double step = 1.0 / 512.0, lim = 64.0;
     double mx = 0.0;
     for (double u = -lim; u <= lim; u += step) mx = std::max(mx, std::fabs(w.amp(u)));
@@ -51,10 +78,14 @@ static void spectral_band(const Wavelet &w, double rel, double &ulo, double &uhi
 }
 
 // Psi_s(omega) = sum_q amp(s (omega + 2 pi q)), q over the images that can reach the band
-static double psi_aliased(const Wavelet &w, double s, double omega, double umax) {
-    int qi = (int)std::ceil((umax + 1.0) / (2.0 * M_PI * s)) + 1;
+// Psi_s(omega) = sum_q psi^(s (omega + 2 pi q)) (amplitude part), summed over
+// the images whose argument lies in the wavelet's band [ulo, uhi] (outside
+// it |psi^| < rel max|psi^|, the plan's truncation level)
+static double psi_aliased(const Wavelet &w, double s, double omega, double ulo, double uhi) {
+    const double tp = 2.0 * M_PI;
+    const long q0 = (long)std::ceil((ulo / s - omega) / tp), q1 = (long)std::floor((uhi / s - omega) / tp);
     double acc = 0.0;
-    for (int q = -qi; q <= qi; ++q) acc += w.amp(s * (omega + 2.0 * M_PI * q));
+    for (long q = q0; q <= q1; ++q) acc += w.amp(s * (omega + tp * (double)q));
     return acc;
 }
 
@@ -166,8 +197,15 @@ static std::vector<int> host_radices(int p) {
     if (k % 4) r.push_back(1 << (k % 4));
     return r;
 }
+// Twiddle tables depend only on their size; each is computed once (long
+// double arguments) and copied into every plan that needs it.
 template <typename R>
-static int64_t push_pass_twiddles(TableBuilder &tb, int P) {
+static const std::vector<R> &pass_twiddles(int P) {
+    static std::mutex mu;
+    static std::map<int, std::vector<R>> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(P);
+    if (it != cache.end()) return it->second;
     std::vector<R> v;
     int ns = 1;
     for (int rad : host_radices(P)) {
@@ -181,24 +219,32 @@ static int64_t push_pass_twiddles(TableBuilder &tb, int P) {
         ns *= rad;
     }
     if (v.empty()) v.assign(2, (R)0);
+    return cache.emplace(P, std::move(v)).first->second;
+}
+template <typename R>
+static int64_t push_pass_twiddles(TableBuilder &tb, int P) {
+    const std::vector<R> &v = pass_twiddles<R>(P);
     return tb.add(v.data(), v.size() * sizeof(R));
 }
 // w_{2^23}^x = hi[x >> 11] * lo[x & 2047] (FP64)
 static void push_w23(TableBuilder &tb, int64_t &hi_off, int64_t &lo_off) {
-    const int64_t L = int64_t(1) << 23;
-    std::vector<double> hi(2 * 4096), lo(2 * 2048);
-    for (int64_t j = 0; j < 4096; ++j) {
-        long double a = 2.0L * M_PIl * (long double)(j * 2048) / (long double)L;
-        hi[2 * j] = (double)std::cos(a);
-        hi[2 * j + 1] = (double)std::sin(a);
-    }
-    for (int64_t j = 0; j < 2048; ++j) {
-        long double a = 2.0L * M_PIl * (long double)j / (long double)L;
-        lo[2 * j] = (double)std::cos(a);
-        lo[2 * j + 1] = (double)std::sin(a);
-    }
-    hi_off = tb.add(hi.data(), hi.size() * sizeof(double));
-    lo_off = tb.add(lo.data(), lo.size() * sizeof(double));
+    static const std::pair<std::vector<double>, std::vector<double>> t = [] {
+        const int64_t L = int64_t(1) << 23;
+        std::vector<double> hi(2 * 4096), lo(2 * 2048);
+        for (int64_t j = 0; j < 4096; ++j) {
+            long double a = 2.0L * M_PIl * (long double)(j * 2048) / (long double)L;
+            hi[2 * j] = (double)std::cos(a);
+            hi[2 * j + 1] = (double)std::sin(a);
+        }
+        for (int64_t j = 0; j < 2048; ++j) {
+            long double a = 2.0L * M_PIl * (long double)j / (long double)L;
+            lo[2 * j] = (double)std::cos(a);
+            lo[2 * j + 1] = (double)std::sin(a);
+        }
+        return std::make_pair(std::move(hi), std::move(lo));
+    }();
+    hi_off = tb.add(t.first.data(), t.first.size() * sizeof(double));
+    lo_off = tb.add(t.second.data(), t.second.size() * sizeof(double));
 }
 
 static const int64_t kMaxN = int64_t(1) << 26;
@@ -241,7 +287,6 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
         std::sort(lj.begin(), lj.end());
         double ulo, uhi;
         spectral_band(w, p.rel, ulo, uhi);
-        double umax = std::max(std::fabs(ulo), std::fabs(uhi));
         size_t i = 0;
         while (i < lj.size()) {
             LocalGroup g;
@@ -259,7 +304,7 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
                 double s = p.scales[j];
                 for (int m = 0; m < g.L; ++m) {
                     int ms = m < g.L / 2 ? m : m - g.L;
-                    tab.push_back(psi_aliased(w, s, 2.0 * M_PI * ms / g.L, umax) / g.L);
+                    tab.push_back(psi_aliased(w, s, 2.0 * M_PI * ms / g.L, ulo, uhi) / g.L);
                 }
             }
             p.groups.push_back(std::move(g));
@@ -305,7 +350,6 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
 
         double ulo, uhi;
         spectral_band(w, p.rel, ulo, uhi);
-        double umax = std::max(std::fabs(ulo), std::fabs(uhi));
         struct Band {
             int j;
             int64_t mlo, B;
@@ -361,12 +405,12 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
             d.Q = Q;
             d.taba = (int64_t)tab.size();
             for (int64_t m = mlo; m < mlo + B; ++m)
-                tab.push_back(psi_aliased(w, p.scales[d.sa], 2.0 * M_PI * (double)m / p.M, umax) / p.M);
+                tab.push_back(psi_aliased(w, p.scales[d.sa], 2.0 * M_PI * (double)m / p.M, ulo, uhi) / p.M);
             d.tabb = d.taba;
             if (d.sb >= 0) {
                 d.tabb = (int64_t)tab.size();
                 for (int64_t m = mlo; m < mlo + B; ++m)
-                    tab.push_back(psi_aliased(w, p.scales[d.sb], 2.0 * M_PI * (double)m / p.M, umax) / p.M);
+                    tab.push_back(psi_aliased(w, p.scales[d.sb], 2.0 * M_PI * (double)m / p.M, ulo, uhi) / p.M);
             }
             ColumnLaunch *cl = nullptr;
             for (auto &c : p.columns)
@@ -470,7 +514,6 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     const int lg_max = 23;
     double ulo, uhi;
     spectral_band(w, p.rel, ulo, uhi);
-    double umax = std::max(std::fabs(ulo), std::fabs(uhi));
     p.pair_real = !p.cplx_out;
     p.path.assign(p.S, PATH_LOCAL);
 
@@ -527,7 +570,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         for (int j : g.scales)
             for (int m = 0; m < g.L; ++m) {
                 int ms = m < g.L / 2 ? m : m - g.L;
-                tab.push_back(psi_aliased(w, p.scales[j], 2.0 * M_PI * ms / g.L, umax) / g.L);
+                tab.push_back(psi_aliased(w, p.scales[j], 2.0 * M_PI * ms / g.L, ulo, uhi) / g.L);
             }
         g.twl_off = fp64 ? push_pass_twiddles<double>(tb, g.L) : push_pass_twiddles<float>(tb, g.L);
         g.twl64_off = fp64 ? g.twl_off : push_pass_twiddles<double>(tb, g.L);
@@ -586,7 +629,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         for (size_t u = 0; u < js.size(); ++u) {
             koff[u] = (int64_t)tab.size();
             for (int64_t m = g.klo; m < g.klo + g.B; ++m)
-                tab.push_back(psi_aliased(w, p.scales[js[u]], 2.0 * M_PI * (double)m / g.L, umax) / g.L);
+                tab.push_back(psi_aliased(w, p.scales[js[u]], 2.0 * M_PI * (double)m / g.L, ulo, uhi) / g.L);
         }
         // w_L^{m g}, g < 16
         {
