@@ -524,7 +524,9 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     std::vector<Cand> loc, band;
     for (int j = 0; j < p.S; ++j) {
         double s = p.scales[j];
-        int64_t L = std::max<int64_t>(64, next_pow2(8 * p.T[j] + 1));
+        // 8 T per segment for long signals; a short signal is a single
+        // segment just long enough for it and the halos
+        int64_t L = std::max<int64_t>(64, std::min(next_pow2(8 * p.T[j] + 1), next_pow2(p.N + 2 * align_halo(p.T[j]))));
         int lg = 0;
         while ((int64_t(1) << lg) < L) ++lg;
         if (lg > lg_max) fail(CWT_EUNSUPPORTED, "scale too large for the segmented transform (wavelet support above 2^20 samples)");
@@ -899,9 +901,10 @@ static void for_each_seg_launch(const Plan &p, F &&fn) {
     for (auto &l : p.seg_launches) {
         double xbytes = 0.0;
         for (auto &gd : l.gdev) xbytes += (double)gd.nseg * gd.B * 16.0;
-        fn(SegKernelId{1, l.P, p.precision, cplx}, l.key[0], (int64_t)l.fwd.size(),
+        // (the forward and reduce kernels do not depend on the output type)
+        fn(SegKernelId{1, l.P, p.precision, 0}, l.key[0], (int64_t)l.fwd.size(),
            nn * sb * (double)l.gdev.size() + xbytes);
-        fn(SegKernelId{2, l.P, p.precision, cplx}, l.key[1], (int64_t)l.red.size(), 2.0 * xbytes);
+        fn(SegKernelId{2, l.P, p.precision, 0}, l.key[1], (int64_t)l.red.size(), 2.0 * xbytes);
         fn(SegKernelId{3, l.P, p.precision, cplx}, l.key[2], (int64_t)l.inv.size(), nn * l.out_rows * eb + xbytes);
     }
 }
