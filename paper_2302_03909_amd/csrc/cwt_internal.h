@@ -143,6 +143,23 @@ struct BatchArgs {
     BatchInst i0;
 };
 
+// Plan-time evaluation of sampled wavelet spectra on the device
+// (cwt_tables.hip).  SpecWavelet: the wavelet's spectral amplitude and the
+// band [ulo, uhi] outside which it is negligible.
+struct SpecWavelet {
+    int32_t kind, m;
+    double w0, cmor, kappa, gnorm, ulo, uhi;
+};
+// count entries at tab[off..]: Psi_s(2 pi m / L) / L for m = m0 + e (full:
+// the signed bin of e in [0, L)); the job's workgroups start at block0
+struct SpecJob {
+    int64_t off, m0, count, L, block0;
+    double s;
+    int32_t full, pad;
+};
+hipError_t launch_spectrum_tables(const SpecWavelet &w, const SpecJob *jobs, int njobs, int64_t blocks, void *tab,
+                                  bool fp64, hipStream_t st);
+
 struct ColumnLaunch {
     int32_t P = 0, G = 0;
     std::vector<ColumnDesc> items;
@@ -211,7 +228,9 @@ struct Plan {
     SplineWork *d_spl_work = nullptr;
     size_t ws_maxp_off = 0, ws_fx_off = 0, ws_state_off = 0, ws_carry_off = 0, ws_H_off = 0;
 
-    // device tables (owned)
+    // device tables (owned).  Segmented plans keep all of them in one
+    // allocation, d_arena; the pointers below then point into it.
+    void *d_arena = nullptr;
     void *d_tab = nullptr;  // spectrum samples, plan precision (real)
     int64_t tab_elems = 0;
     void *d_tw_all = nullptr;  // all twiddle tables (one allocation); offsets in bytes

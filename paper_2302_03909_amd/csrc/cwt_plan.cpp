@@ -227,7 +227,7 @@ static int64_t push_pass_twiddles(TableBuilder &tb, int P) {
     return tb.add(v.data(), v.size() * sizeof(R));
 }
 // w_{2^23}^x = hi[x >> 11] * lo[x & 2047] (FP64)
-static void push_w23(TableBuilder &tb, int64_t &hi_off, int64_t &lo_off) {
+static const std::pair<std::vector<double>, std::vector<double>> &w23_tables() {
     static const std::pair<std::vector<double>, std::vector<double>> t = [] {
         const int64_t L = int64_t(1) << 23;
         std::vector<double> hi(2 * 4096), lo(2 * 2048);
@@ -243,6 +243,18 @@ static void push_w23(TableBuilder &tb, int64_t &hi_off, int64_t &lo_off) {
         }
         return std::make_pair(std::move(hi), std::move(lo));
     }();
+    return t;
+}
+// e^{+2 pi i x / L}, L = 2^lg <= 2^23, from the split tables (FP64, ~1 ulp)
+static std::complex<double> w23_at(int64_t x, int lg) {
+    const auto &t = w23_tables();
+    const int64_t y = (x & ((int64_t(1) << lg) - 1)) << (23 - lg);
+    const std::complex<double> a(t.first[2 * (y >> 11)], t.first[2 * (y >> 11) + 1]);
+    const std::complex<double> b(t.second[2 * (y & 2047)], t.second[2 * (y & 2047) + 1]);
+    return a * b;
+}
+static void push_w23(TableBuilder &tb, int64_t &hi_off, int64_t &lo_off) {
+    const auto &t = w23_tables();
     hi_off = tb.add(t.first.data(), t.first.size() * sizeof(double));
     lo_off = tb.add(t.second.data(), t.second.size() * sizeof(double));
 }
@@ -542,7 +554,22 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             p.path[j] = PATH_COLUMN;
         }
     }
-    std::vector<double> tab;
+    // spectrum samples: evaluated on the device at the end (jobs); tab_n
+    // counts the table's elements
+    std::vector<SpecJob> jobs;
+    int64_t tab_n = 0;
+    auto add_job = [&](double s, int64_t L, int64_t m0, int64_t count, bool full) {
+        SpecJob jb{};
+        jb.off = tab_n;
+        jb.m0 = m0;
+        jb.count = count;
+        jb.L = L;
+        jb.s = s;
+        jb.full = full ? 1 : 0;
+        jobs.push_back(jb);
+        tab_n += count;
+        return jb.off;
+    };
     TableBuilder tb;
     push_w23(tb, p.w23_hi_off, p.w23_lo_off);
     size_t ws = 0;
@@ -568,12 +595,8 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         g.V = g.L - 2 * g.Tg;
         if (g.V <= 0) fail(CWT_EUNSUPPORTED, "internal: segment too short for the halo");
         g.nseg = (p.N + g.V - 1) / g.V;
-        g.tab_off = (int64_t)tab.size();
-        for (int j : g.scales)
-            for (int m = 0; m < g.L; ++m) {
-                int ms = m < g.L / 2 ? m : m - g.L;
-                tab.push_back(psi_aliased(w, p.scales[j], 2.0 * M_PI * ms / g.L, ulo, uhi) / g.L);
-            }
+        g.tab_off = tab_n;
+        for (int j : g.scales) add_job(p.scales[j], g.L, 0, g.L, true);
         g.twl_off = fp64 ? push_pass_twiddles<double>(tb, g.L) : push_pass_twiddles<float>(tb, g.L);
         g.twl64_off = fp64 ? g.twl_off : push_pass_twiddles<double>(tb, g.L);
         p.segs.push_back(std::move(g));
@@ -628,20 +651,15 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         g.iters = (int32_t)(iters_total / nchunk);
         // spectrum samples of each scale on the group band
         std::vector<int64_t> koff(js.size());
-        for (size_t u = 0; u < js.size(); ++u) {
-            koff[u] = (int64_t)tab.size();
-            for (int64_t m = g.klo; m < g.klo + g.B; ++m)
-                tab.push_back(psi_aliased(w, p.scales[js[u]], 2.0 * M_PI * (double)m / g.L, ulo, uhi) / g.L);
-        }
+        for (size_t u = 0; u < js.size(); ++u) koff[u] = add_job(p.scales[js[u]], g.L, g.klo, g.B, false);
         // w_L^{m g}, g < 16
         {
             std::vector<double> gt(2 * 16 * (size_t)g.B);
             for (int gg = 0; gg < 16; ++gg)
                 for (int k = 0; k < g.B; ++k) {
-                    int64_t x = ((g.klo + k) * gg) & (int64_t)(g.L - 1);
-                    long double a = 2.0L * M_PIl * (long double)x / (long double)g.L;
-                    gt[2 * ((size_t)gg * g.B + k)] = (double)std::cos(a);
-                    gt[2 * ((size_t)gg * g.B + k) + 1] = (double)std::sin(a);
+                    const std::complex<double> v = w23_at((g.klo + k) * gg, g.lgL);
+                    gt[2 * ((size_t)gg * g.B + k)] = v.real();
+                    gt[2 * ((size_t)gg * g.B + k) + 1] = v.imag();
                 }
             if (fp64) g.gtw_off = tb.add(gt.data(), gt.size() * sizeof(double));
             else {
@@ -703,57 +721,92 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         p.segs.push_back(std::move(g));
     }
     p.ws_bytes = ws;
-    p.tab_elems = (int64_t)tab.size();
+    p.tab_elems = tab_n;
     if (p.host_only) return;
 
-    if (!tab.empty()) {
-        size_t bytes = tab.size() * (fp64 ? 8 : 4);
-        HIPCHK(hipMalloc(&p.d_tab, bytes));
-        p.table_bytes += bytes;
-        if (fp64) {
-            HIPCHK(hipMemcpy(p.d_tab, tab.data(), bytes, hipMemcpyHostToDevice));
-        } else {
-            std::vector<float> t32(tab.begin(), tab.end());
-            HIPCHK(hipMemcpy(p.d_tab, t32.data(), bytes, hipMemcpyHostToDevice));
-        }
-    }
-    HIPCHK(hipMalloc(&p.d_tw_all, tb.host.size()));
-    p.table_bytes += tb.host.size();
-    HIPCHK(hipMemcpy(p.d_tw_all, tb.host.data(), tb.host.size(), hipMemcpyHostToDevice));
-    auto upload = [&](const void *src, size_t bytes, void **dst) {
-        if (bytes == 0) return;
-        HIPCHK(hipMalloc(dst, bytes));
-        p.table_bytes += bytes;
-        HIPCHK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    // One device allocation holds every table of the plan:
+    //   twiddles | spectrum samples | spectrum jobs | scale ids | units |
+    //   per band size: groups, forward / reduce / inverse work | launch keys
+    const size_t eb = fp64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = (off + 255) & ~size_t(255);
+        off = o + bytes;
+        return o;
     };
-    for (auto &g : p.segs)
-        if (g.kind == SegGroup::LOCAL)
-            upload(g.scales.data(), g.scales.size() * sizeof(int32_t), reinterpret_cast<void **>(&g.d_scales));
-    upload(p.units.data(), p.units.size() * sizeof(SegUnit), reinterpret_cast<void **>(&p.d_units));
-    for (auto &l : p.seg_launches) {
-        upload(l.gdev.data(), l.gdev.size() * sizeof(SegGroupDev), reinterpret_cast<void **>(&l.d_groups));
-        upload(l.fwd.data(), l.fwd.size() * sizeof(SegWork), reinterpret_cast<void **>(&l.d_fwd));
-        upload(l.red.data(), l.red.size() * sizeof(SegWork), reinterpret_cast<void **>(&l.d_red));
-        upload(l.inv.data(), l.inv.size() * sizeof(SegWork), reinterpret_cast<void **>(&l.d_inv));
+    const size_t o_tw = take(tb.host.size());
+    const size_t o_tab = take((size_t)tab_n * eb);
+    int64_t spec_blocks = 0;
+    for (auto &jb : jobs) {
+        jb.block0 = spec_blocks;
+        spec_blocks += (jb.count + 255) / 256;
+    }
+    const size_t o_jobs = take(jobs.size() * sizeof(SpecJob));
+    std::vector<size_t> o_sc(p.segs.size(), 0);
+    for (size_t gi = 0; gi < p.segs.size(); ++gi)
+        if (p.segs[gi].kind == SegGroup::LOCAL) o_sc[gi] = take(p.segs[gi].scales.size() * sizeof(int32_t));
+    const size_t o_units = take(p.units.size() * sizeof(SegUnit));
+    struct LaunchOffs {
+        size_t groups, fwd, red, inv;
+    };
+    std::vector<LaunchOffs> o_l;
+    for (auto &l : p.seg_launches)
+        o_l.push_back({take(l.gdev.size() * sizeof(SegGroupDev)), take(l.fwd.size() * sizeof(SegWork)),
+                       take(l.red.size() * sizeof(SegWork)), take(l.inv.size() * sizeof(SegWork))});
+    size_t nkeys = 0;
+    for (auto &g : p.segs) nkeys += g.kind == SegGroup::LOCAL ? 1 : 0;
+    nkeys += 3 * p.seg_launches.size();
+    const size_t o_keys = take(nkeys * sizeof(KeyDesc));
+    const size_t total = off;
+
+    HIPCHK(hipMalloc(&p.d_arena, total));
+    p.table_bytes += total;
+    char *base = static_cast<char *>(p.d_arena);
+    p.d_tw_all = base + o_tw;
+    p.d_tab = base + o_tab;
+    std::vector<char> img(total, 0);
+    auto put = [&](size_t o, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(img.data() + o, src, bytes);
+    };
+    put(o_tw, tb.host.data(), tb.host.size());
+    put(o_jobs, jobs.data(), jobs.size() * sizeof(SpecJob));
+    for (size_t gi = 0; gi < p.segs.size(); ++gi) {
+        SegGroup &g = p.segs[gi];
+        if (g.kind != SegGroup::LOCAL) continue;
+        put(o_sc[gi], g.scales.data(), g.scales.size() * sizeof(int32_t));
+        g.d_scales = reinterpret_cast<int32_t *>(base + o_sc[gi]);
+    }
+    put(o_units, p.units.data(), p.units.size() * sizeof(SegUnit));
+    p.d_units = reinterpret_cast<SegUnit *>(base + o_units);
+    for (size_t li = 0; li < p.seg_launches.size(); ++li) {
+        SegLaunch &l = p.seg_launches[li];
+        put(o_l[li].groups, l.gdev.data(), l.gdev.size() * sizeof(SegGroupDev));
+        put(o_l[li].fwd, l.fwd.data(), l.fwd.size() * sizeof(SegWork));
+        put(o_l[li].red, l.red.data(), l.red.size() * sizeof(SegWork));
+        put(o_l[li].inv, l.inv.data(), l.inv.size() * sizeof(SegWork));
+        l.d_groups = reinterpret_cast<SegGroupDev *>(base + o_l[li].groups);
+        l.d_fwd = reinterpret_cast<SegWork *>(base + o_l[li].fwd);
+        l.d_red = reinterpret_cast<SegWork *>(base + o_l[li].red);
+        l.d_inv = reinterpret_cast<SegWork *>(base + o_l[li].inv);
     }
 
     // launch keys
     const char *tw = static_cast<const char *>(p.d_tw_all);
     const char *dtab = static_cast<const char *>(p.d_tab);
-    KeyDesc base{};
-    base.N = p.N;
-    base.periodic = p.boundary == CWT_PERIODIC ? 1 : 0;
-    base.cph = p.cph;
-    base.units = p.d_units;
-    base.ktab = dtab;
-    base.twbase = tw;
-    base.whi = reinterpret_cast<const double2 *>(tw + p.w23_hi_off);
-    base.wlo = reinterpret_cast<const double2 *>(tw + p.w23_lo_off);
+    KeyDesc kb{};
+    kb.N = p.N;
+    kb.periodic = p.boundary == CWT_PERIODIC ? 1 : 0;
+    kb.cph = p.cph;
+    kb.units = p.d_units;
+    kb.ktab = dtab;
+    kb.twbase = tw;
+    kb.whi = reinterpret_cast<const double2 *>(tw + p.w23_hi_off);
+    kb.wlo = reinterpret_cast<const double2 *>(tw + p.w23_lo_off);
     p.keys.clear();
     for (auto &g : p.segs) {
         if (g.kind != SegGroup::LOCAL) continue;
-        KeyDesc k = base;
-        k.ktab = dtab + (size_t)g.tab_off * (fp64 ? 8 : 4);
+        KeyDesc k = kb;
+        k.ktab = dtab + (size_t)g.tab_off * eb;
         k.twl = tw + g.twl_off;
         k.twl64 = tw + g.twl64_off;
         k.Tg = g.Tg;
@@ -767,7 +820,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         p.keys.push_back(k);
     }
     for (auto &l : p.seg_launches) {
-        KeyDesc k = base;
+        KeyDesc k = kb;
         k.groups = l.d_groups;
         k.twl = tw + l.twl_off;
         const SegWork *lists[3] = {l.d_fwd, l.d_red, l.d_inv};
@@ -777,11 +830,43 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             p.keys.push_back(k);
         }
     }
-    upload(p.keys.data(), p.keys.size() * sizeof(KeyDesc), reinterpret_cast<void **>(&p.d_keys));
+    put(o_keys, p.keys.data(), p.keys.size() * sizeof(KeyDesc));
+    p.d_keys = reinterpret_cast<KeyDesc *>(base + o_keys);
+
+    // upload and evaluate the spectra on a stream of this thread, then wait
+    // for it only (work of other streams keeps running)
+    static thread_local hipStream_t plan_stream = nullptr;
+    if (!plan_stream) HIPCHK(hipStreamCreateWithFlags(&plan_stream, hipStreamNonBlocking));
+    HIPCHK(hipMemcpyAsync(base, img.data(), total, hipMemcpyHostToDevice, plan_stream));
+    SpecWavelet sw{};
+    sw.kind = w.kind;
+    sw.m = w.m;
+    sw.w0 = w.w0;
+    sw.cmor = w.cmor;
+    sw.kappa = w.kappa;
+    sw.gnorm = w.gnorm;
+    sw.ulo = ulo;
+    sw.uhi = uhi;
+    HIPCHK(launch_spectrum_tables(sw, reinterpret_cast<const SpecJob *>(base + o_jobs), (int)jobs.size(),
+                                  spec_blocks, p.d_tab, fp64, plan_stream));
+    HIPCHK(hipStreamSynchronize(plan_stream));
 }
 
 static void free_plan(Plan *p) {
     if (!p) return;
+    if (p->d_arena) {
+        // every table of a segmented plan sits in the arena
+        (void)hipFree(p->d_arena);
+        for (void *x : p->d_extra)
+            if (x) (void)hipFree(x);
+        for (auto &r : p->timing_recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : p->event_pool) (void)hipEventDestroy(e);
+        delete p;
+        return;
+    }
     if (p->d_tab) (void)hipFree(p->d_tab);
     if (p->d_tw_all) (void)hipFree(p->d_tw_all);
     if (p->d_dtab) (void)hipFree(p->d_dtab);
