@@ -132,6 +132,12 @@ def main():
                     help="time cwt_exec_batch on this many uneven instances instead (lengths 2^10..2^16, "
                          "16..96 scales, Morlet(6) / Mexican hat, half periodic tones, half zero-boundary "
                          "lognormal fields, FP32 form); 4096 is the batched workload")
+    ap.add_argument("--serve", action="store_true",
+                    help="served form instead: Poisson request streams (2^12..2^22 samples, 32..256 scales, "
+                         "Morlet(6) / Mexican hat / DOG(4), FP32) at 0.5, 0.8 and 0.95 of the plain-batched "
+                         "capacity, continuous batching against plain batching, p50 / p99 latency")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--wavelet", default=None, choices=["morlet", "dog2", "mexhat"])
     ap.add_argument("--boundary", default="zero", choices=["zero", "periodic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -152,6 +158,8 @@ def main():
 
     if args.batch > 0:
         return bench_batch(args)
+    if args.serve:
+        return bench_serve(args)
     if args.method == "fft":
         n, nscales, smax, precision = 1 << 22, 128, 2.0 ** 16, "fp32"
         seed, nname = synth.SEED_FIELD_4M, "2^22"
@@ -305,6 +313,73 @@ def bench_batch(args):
                            "kernels": {k: {"launches": v[0], "ms_per_step": round(v[1] / args.steps, 4),
                                            "bytes_per_launch": v[2]} for k, v in kern.items()}},
             "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Served form: requests take the first N samples of one of a few
+    device-resident signals of 2^22 samples (periodic tones + noise for the
+    periodic ones, lognormal fields for the zero-boundary ones).  Latency is
+    arrival to device completion; outputs are dropped once complete."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_03909_amd.serve import (ContinuousScheduler, GpuExecutor, Request, StaticBatcher,
+                                            latency_summary, run_open_loop)
+
+    dev = torch.device("cuda", 0)
+    print("bench: drawing signal pool", file=sys.stderr, flush=True)
+    nmax = 1 << 22
+    pool = {"periodic": [torch.as_tensor(synth.tones_noise(nmax, seed=s).astype(np.float32), device=dev)
+                         for s in (1, 2)],
+            "zero": [torch.as_tensor(synth.lognormal_field(nmax, seed=s).astype(np.float32), device=dev)
+                     for s in (3, 4)]}
+    torch.cuda.synchronize()
+    par_of = {"morlet": 6.0, "mexhat": None, "dog": 4.0}
+
+    def make(specs):
+        out = []
+        for i, d in enumerate(specs):
+            sig = pool[d["boundary"]][d["seed"] % 2][:d["n"]]
+            out.append(Request(i, d["n"], d["boundary"], d["wavelet"], par_of[d["wavelet"]], d["scales"], "fp32",
+                               sig, arrival=d["arrival"]))
+        return out
+
+    total = args.serve_requests + args.serve_warmup
+    budget = 64 << 30
+    mean_coef = synth.mean_request_coefficients()
+    # plain-batched capacity: every request available at once
+    print("bench: measuring plain-batched capacity", file=sys.stderr, flush=True)
+    specs = synth.request_specs(min(total, 600), rate_hz=1e9, seed=synth.SEED_SERVE + 1)
+    ex = GpuExecutor(streams=1, keep_outputs=False)
+    done = run_open_loop(StaticBatcher(ex, max_batch=32, window=0.0), make(specs))
+    torch.cuda.synchronize()
+    cap = latency_summary(done)["coefficients_per_s"]
+    cap_rps = cap / mean_coef
+    results = {}
+    for load in (0.5, 0.8, 0.95):
+        specs = synth.request_specs(total, rate_hz=load * cap_rps, seed=synth.SEED_SERVE)
+        for mode in ("continuous", "plain"):
+            print(f"bench: load {load} {mode}", file=sys.stderr, flush=True)
+            ex = GpuExecutor(streams=2, keep_outputs=False)
+            sched = (ContinuousScheduler(ex, budget_bytes=budget, streams=2) if mode == "continuous"
+                     else StaticBatcher(ex, max_batch=32, window=2e-3))
+            done = run_open_loop(sched, make(specs))
+            torch.cuda.synchronize()
+            summ = latency_summary(done, skip=args.serve_warmup)
+            summ["mean_batch"] = float(np.mean(sched.batches))
+            results[f"{mode}@{load}"] = summ
+    top = results["continuous@0.95"]
+    line = {"metric": "served CWT coefficients/s and p50/p99 latency at 0.95 x plain-batched capacity",
+            "value": top["coefficients_per_s"], "unit": "coefficients/s", "n_gpus": 1,
+            "steps": args.serve_requests, "warmup": args.serve_warmup, "ms_per_step": top["mean_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "Poisson request stream: N log-uniform 2^12..2^22, 32..256 log scales, "
+                                   "Morlet(6) / Mexican hat / DOG(4), periodic or zero boundary, fp32 form",
+                       "plain_batched_capacity_coef_per_s": cap, "capacity_requests_per_s": cap_rps,
+                       "mean_request_coefficients": mean_coef, "budget_bytes": budget},
+            "serve": results, "roofline": None, "cpu_baseline": None}
     print(json.dumps(line), flush=True)
 
 

@@ -132,11 +132,13 @@ struct BatchRange {
 };
 
 // kernel argument of every segmented kernel.  nranges == 0: one transform,
-// key and buffers by value (k0, i0); else block b belongs to
-// ranges[blockmap[b]].
+// key and buffers by value (k0, i0); else block b belongs to the last range
+// with block0 <= b, which lies between ranges coarse[b / 256] and
+// coarse[b / 256 + 1] (the ranges holding blocks 256 (b / 256) and
+// 256 (b / 256 + 1), or the last one).
 struct BatchArgs {
     const BatchRange *ranges;
-    const int32_t *blockmap;
+    const int32_t *coarse;
     const BatchInst *insts;
     int32_t nranges, pad;
     KeyDesc k0;

@@ -519,6 +519,16 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
 // group gives the same outputs.
 static int64_t align_halo(int64_t t) { return (t + 15) & ~int64_t(15); }
 
+// Stream of the calling thread for plan construction and release
+// (non-blocking, default priority): plan tables are allocated, filled and
+// freed in its order, so building or destroying a plan never waits for the
+// work other streams are running.
+static hipStream_t plan_stream() {
+    static thread_local hipStream_t st = nullptr;
+    if (!st) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    return st;
+}
+
 static void build_seg_plan(Plan &p, const Wavelet &w) {
     const bool fp64 = p.precision == CWT_FP64;
     const int lmax_local = 4096;
@@ -759,7 +769,8 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     const size_t o_keys = take(nkeys * sizeof(KeyDesc));
     const size_t total = off;
 
-    HIPCHK(hipMalloc(&p.d_arena, total));
+    hipStream_t pst = plan_stream();
+    HIPCHK(hipMallocAsync(&p.d_arena, total, pst));
     p.table_bytes += total;
     char *base = static_cast<char *>(p.d_arena);
     p.d_tw_all = base + o_tw;
@@ -833,11 +844,9 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     put(o_keys, p.keys.data(), p.keys.size() * sizeof(KeyDesc));
     p.d_keys = reinterpret_cast<KeyDesc *>(base + o_keys);
 
-    // upload and evaluate the spectra on a stream of this thread, then wait
+    // upload and evaluate the spectra on the stream of this thread, then wait
     // for it only (work of other streams keeps running)
-    static thread_local hipStream_t plan_stream = nullptr;
-    if (!plan_stream) HIPCHK(hipStreamCreateWithFlags(&plan_stream, hipStreamNonBlocking));
-    HIPCHK(hipMemcpyAsync(base, img.data(), total, hipMemcpyHostToDevice, plan_stream));
+    HIPCHK(hipMemcpyAsync(base, img.data(), total, hipMemcpyHostToDevice, pst));
     SpecWavelet sw{};
     sw.kind = w.kind;
     sw.m = w.m;
@@ -848,15 +857,20 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     sw.ulo = ulo;
     sw.uhi = uhi;
     HIPCHK(launch_spectrum_tables(sw, reinterpret_cast<const SpecJob *>(base + o_jobs), (int)jobs.size(),
-                                  spec_blocks, p.d_tab, fp64, plan_stream));
-    HIPCHK(hipStreamSynchronize(plan_stream));
+                                  spec_blocks, p.d_tab, fp64, pst));
+    HIPCHK(hipStreamSynchronize(pst));
 }
 
 static void free_plan(Plan *p) {
     if (!p) return;
     if (p->d_arena) {
-        // every table of a segmented plan sits in the arena
-        (void)hipFree(p->d_arena);
+        // every table of a segmented plan sits in the arena (stream-ordered
+        // release: the caller guarantees no stream still uses the plan)
+        try {
+            (void)hipFreeAsync(p->d_arena, plan_stream());
+        } catch (...) {
+            (void)hipFree(p->d_arena);
+        }
         for (void *x : p->d_extra)
             if (x) (void)hipFree(x);
         for (auto &r : p->timing_recs) {
@@ -1212,7 +1226,6 @@ struct BatchLayout {
     struct Merged {
         SegKernelId id;
         std::vector<BatchRange> ranges;
-        std::vector<int32_t> blockmap;
         int64_t blocks = 0;
         double bytes = 0.0;
         size_t ranges_off = 0, map_off = 0;  // within the tables
@@ -1258,7 +1271,7 @@ static BatchLayout batch_layout(const cwt_plan_t *plans, int32_t n) {
         m.ranges_off = t;
         t = align256(t + m.ranges.size() * sizeof(BatchRange));
         m.map_off = t;
-        t = align256(t + (size_t)m.blocks * sizeof(int32_t));
+        t = align256(t + (size_t)((m.blocks + 255) / 256 + 1) * sizeof(int32_t));
     }
     bl.tables_bytes = t;
     bl.bytes = off + t;
@@ -1307,10 +1320,14 @@ int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals, void *co
             for (int32_t i = 0; i < n; ++i) insts[i] = {signals[i], outs[i], ws + bl.ws_off[i]};
             for (auto &m : bl.merged) {
                 std::memcpy(host.data() + m.ranges_off, m.ranges.data(), m.ranges.size() * sizeof(cwt::BatchRange));
-                auto *map = reinterpret_cast<int32_t *>(host.data() + m.map_off);
-                for (size_t r = 0; r < m.ranges.size(); ++r) {
-                    const int64_t end = r + 1 < m.ranges.size() ? m.ranges[r + 1].block0 : m.blocks;
-                    for (int64_t b = m.ranges[r].block0; b < end; ++b) map[b] = (int32_t)r;
+                // coarse[c]: the range holding block 256 c (the last range past the end)
+                auto *coarse = reinterpret_cast<int32_t *>(host.data() + m.map_off);
+                const int64_t nc = (m.blocks + 255) / 256 + 1;
+                size_t r = 0;
+                for (int64_t c = 0; c < nc; ++c) {
+                    const int64_t b = std::min<int64_t>(c * 256, m.blocks - 1);
+                    while (r + 1 < m.ranges.size() && m.ranges[r + 1].block0 <= b) ++r;
+                    coarse[c] = (int32_t)r;
                 }
             }
             HIPCHK(hipMemcpyAsync(tables, host.data(), host.size(), hipMemcpyHostToDevice, st));
@@ -1318,7 +1335,7 @@ int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals, void *co
             for (auto &m : bl.merged) {
                 cwt::BatchArgs a{};
                 a.ranges = reinterpret_cast<const cwt::BatchRange *>(tables + m.ranges_off);
-                a.blockmap = reinterpret_cast<const int32_t *>(tables + m.map_off);
+                a.coarse = reinterpret_cast<const int32_t *>(tables + m.map_off);
                 a.insts = reinterpret_cast<const cwt::BatchInst *>(tables + bl.insts_off);
                 a.nranges = (int32_t)m.ranges.size();
                 cwt::timed(tp, st, cwt::seg_kernel_id_name(m.id), m.bytes, "batched segment launch",

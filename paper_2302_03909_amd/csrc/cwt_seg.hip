@@ -111,7 +111,14 @@ __device__ __forceinline__ Resolved resolve(const BatchArgs &a) {
     if (a.nranges == 0) {
         rv = {a.k0, a.i0, (int64_t)blockIdx.x};
     } else {
-        const BatchRange r = cload(a.ranges + cload(a.blockmap + blockIdx.x));
+        const int64_t b = blockIdx.x;
+        int lo = cload(a.coarse + (b >> 8)), hi = cload(a.coarse + (b >> 8) + 1);
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cload(a.ranges + mid).block0 <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchRange r = cload(a.ranges + lo);
         rv = {cload(r.key), cload(a.insts + r.inst), (int64_t)blockIdx.x - r.block0};
     }
     rv.bi.f = uni(rv.bi.f);

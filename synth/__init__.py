@@ -123,12 +123,11 @@ def batch_specs(count: int = 4096, seed: int = SEED_BATCH, log2_lo: float = 10.0
     return out
 
 
-def request_stream(count: int, rate_hz: float, seed: int = SEED_SERVE,
-                   log2_lo: float = 12.0, log2_hi: float = 22.0, s_lo: int = 32,
-                   s_hi: int = 256) -> list[Instance]:
-    """Poisson arrivals at rate_hz; lengths log-uniform in [2^12, 2^22],
-    32-256 scales, wavelet uniform over Morlet(6) / Mexican hat / DOG(4),
-    boundary periodic or zero 50/50."""
+def request_specs(count: int, rate_hz: float, seed: int = SEED_SERVE,
+                  log2_lo: float = 12.0, log2_hi: float = 22.0, s_lo: int = 32,
+                  s_hi: int = 256) -> list[dict]:
+    """The draws of ``request_stream`` without the signals: arrival time,
+    length, scales, wavelet, boundary and the seed its signal would use."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -139,11 +138,25 @@ def request_stream(count: int, rate_hz: float, seed: int = SEED_SERVE,
         sub = int(rng.integers(0, 2 ** 31))
         w = int(rng.integers(0, 3))
         wav, par = [("morlet", 6.0), ("mexhat", 2.0), ("dog", 4.0)][w]
-        if rng.uniform() < 0.5:
-            sig, bc = tones_noise(n, seed=sub), "periodic"
+        bc = "periodic" if rng.uniform() < 0.5 else "zero"
+        out.append({"arrival": t, "n": n, "scales": _scales_for(n, s), "wavelet": wav, "param": par,
+                    "boundary": bc, "seed": sub})
+    return out
+
+
+def request_stream(count: int, rate_hz: float, seed: int = SEED_SERVE,
+                   log2_lo: float = 12.0, log2_hi: float = 22.0, s_lo: int = 32,
+                   s_hi: int = 256) -> list[Instance]:
+    """Poisson arrivals at rate_hz; lengths log-uniform in [2^12, 2^22],
+    32-256 scales, wavelet uniform over Morlet(6) / Mexican hat / DOG(4),
+    boundary periodic (tones + noise) or zero (lognormal field) 50/50."""
+    out = []
+    for d in request_specs(count, rate_hz, seed, log2_lo, log2_hi, s_lo, s_hi):
+        if d["boundary"] == "periodic":
+            sig = tones_noise(d["n"], seed=d["seed"])
         else:
-            sig, bc = lognormal_field(n, seed=sub), "zero"
-        out.append(Instance(sig, bc, wav, par, _scales_for(n, s), arrival=t))
+            sig = lognormal_field(d["n"], seed=d["seed"])
+        out.append(Instance(sig, d["boundary"], d["wavelet"], d["param"], d["scales"], arrival=d["arrival"]))
     return out
 
 
