@@ -208,6 +208,17 @@ double cwt_plan_spline_hstar(cwt_plan_t plan);
 int cwt_plan_scale_path(cwt_plan_t plan, int32_t *path);
 
 /*
+ * cwt_plan_describe -- a text summary of the plan (one line per segment
+ * group: local or band, segment length L, band transform size P, band bins
+ * B, halo, outputs per segment, segments, column chunks, scales; one line
+ * per band launch with its work item counts).  Writes at most size bytes
+ * including the terminating NUL into buf (host memory, owned by the
+ * caller); returns the full length of the text, or CWT_EINVAL for a NULL
+ * plan or a NULL buf with size > 0.
+ */
+int cwt_plan_describe(cwt_plan_t plan, char *buf, size_t size);
+
+/*
  * Launch timing for benchmarks.  While enabled on a plan, every cwt_exec of
  * that plan brackets each kernel launch with HIP events recorded on the
  * launch stream.  cwt_plan_timing_read waits for those events and reports,

@@ -47,7 +47,7 @@ class _Opts(ctypes.Structure):
 EXPORTS = ["cwt_plan", "cwt_destroy", "cwt_out_is_complex", "cwt_out_elems", "cwt_out_elem_bytes",
            "cwt_workspace_bytes", "cwt_footprint_bytes", "cwt_exec", "cwt_batch_workspace_bytes",
            "cwt_exec_batch", "cwt_plan_fft_len", "cwt_plan_spline_delta", "cwt_plan_spline_taps", "cwt_plan_spline_hstar",
-           "cwt_plan_scale_path", "cwt_plan_timing_enable", "cwt_plan_timing_read", "cwt_last_error"]
+           "cwt_plan_scale_path", "cwt_plan_describe", "cwt_plan_timing_enable", "cwt_plan_timing_read", "cwt_last_error"]
 
 _lib = None
 
@@ -82,6 +82,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cwt_plan_fft_len.restype = ctypes.c_int64
     lib.cwt_plan_spline_delta.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.cwt_plan_spline_taps.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.cwt_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.cwt_plan_spline_hstar.argtypes = [vp]
     lib.cwt_plan_spline_hstar.restype = ctypes.c_double
     lib.cwt_plan_scale_path.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -181,6 +182,14 @@ class Plan:
         out = np.zeros(self.num_scales, dtype=np.int32)
         _check(load().cwt_plan_spline_taps(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return out
+
+    def describe(self) -> str:
+        """Text summary of the plan's segment groups and launches."""
+        n = load().cwt_plan_describe(self.handle, None, 0)
+        _check(n if n < 0 else 0)
+        buf = ctypes.create_string_buffer(n + 1)
+        load().cwt_plan_describe(self.handle, buf, n + 1)
+        return buf.value.decode()
 
     def spline_hstar(self) -> float:
         return float(load().cwt_plan_spline_hstar(self.handle))

@@ -78,7 +78,8 @@ struct SegUnit {
 };
 
 // one workgroup of a fused launch: group g, segment seg, and idx = column
-// chunk (forward), 16-bin block (reduce) or first column r0 (inverse)
+// chunk (forward), 16-bin block (reduce) or first column r0 (inverse); pad =
+// number of consecutive segments (forward and reduce)
 struct SegWork {
     int32_t g, seg, idx, pad;
 };
@@ -167,6 +168,11 @@ struct ColumnLaunch {
     std::vector<ColumnDesc> items;
     ColumnDesc *d_items = nullptr;
 };
+
+// Bytes of LDS the band inverse kernel stages spectrum samples in (the plan
+// sizes band groups to fit): with the P = 256 transform buffer it keeps three
+// workgroups per compute unit.
+constexpr int kSegKlsBytes = 14336;
 
 // Spline method (Sec. 3.3 with integer knot spacing, see cwt_spline.hip).
 // Per scale: knot spacing delta, wavelet coefficients d'[n] = conj(d[n - nd]) /

@@ -628,8 +628,8 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             int64_t nlo = std::min(klo, band[i].klo), nhi = std::max(khi, band[i].khi);
             int64_t P = std::max<int64_t>(64, next_pow2(nhi - nlo + 1));
             if (!js.empty() && (P > pmax || P * 16 > g.L)) break;
-            // the inverse stages all spectrum samples of a group in 16 KiB of LDS
-            int64_t kls_cap = std::max<int64_t>(2 * P, 16384 / (fp64 ? 8 : 4));
+            // the inverse stages all spectrum samples of a group in LDS
+            int64_t kls_cap = std::max<int64_t>(2 * P, kSegKlsBytes / (fp64 ? 8 : 4));
             // (a real-wavelet pair takes two tables even when its second scale is absent)
             int64_t ntab = ((int64_t)js.size() + 1 + per_unit - 1) / per_unit * per_unit;
             if (!js.empty() && ntab * (nhi - nlo + 1) > kls_cap) break;
@@ -644,7 +644,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         g.P = (int32_t)std::max<int64_t>(64, next_pow2(g.B));
         {
             int64_t ntab = ((int64_t)js.size() + per_unit - 1) / per_unit * per_unit;
-            if (ntab * g.B > std::max<int64_t>(2 * g.P, 16384 / (fp64 ? 8 : 4)))
+            if (ntab * g.B > std::max<int64_t>(2 * g.P, kSegKlsBytes / (fp64 ? 8 : 4)))
                 fail(CWT_EUNSUPPORTED, "internal: band group tables exceed the staging area");
         }
         for (int j : js) g.Tg = std::max(g.Tg, p.T[j]);
@@ -723,11 +723,20 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         sl->gdev.push_back(gd);
         sl->groups.push_back((int32_t)p.segs.size());
         sl->out_rows += (double)js.size();
-        for (int64_t sg = 0; sg < g.nseg; ++sg) {
-            for (int32_t c = 0; c < g.nchunk; ++c) sl->fwd.push_back({gi, (int32_t)sg, c, 0});
-            for (int32_t kb = 0; kb * 16 < g.B; ++kb) sl->red.push_back({gi, (int32_t)sg, kb, 0});
+        // forward and reduce items cover `pad` consecutive segments, about
+        // 256 items per group: each workgroup then has enough work to repay
+        // its set-up (twiddle tables, band factors)
+        const int64_t nkb = (g.B + 15) / 16;
+        const int64_t fsw = std::max<int64_t>(1, g.nseg * g.nchunk / 256);
+        const int64_t rsw = std::max<int64_t>(1, g.nseg * nkb / 256);
+        for (int64_t sg = 0; sg < g.nseg; sg += fsw)
+            for (int32_t c = 0; c < g.nchunk; ++c)
+                sl->fwd.push_back({gi, (int32_t)sg, c, (int32_t)std::min(fsw, g.nseg - sg)});
+        for (int64_t sg = 0; sg < g.nseg; sg += rsw)
+            for (int32_t kb = 0; kb < nkb; ++kb)
+                sl->red.push_back({gi, (int32_t)sg, kb, (int32_t)std::min(rsw, g.nseg - sg)});
+        for (int64_t sg = 0; sg < g.nseg; ++sg)
             for (int64_t r0 = 0; r0 < Q; r0 += 16) sl->inv.push_back({gi, (int32_t)sg, (int32_t)r0, 0});
-        }
         p.segs.push_back(std::move(g));
     }
     p.ws_bytes = ws;
@@ -1368,6 +1377,35 @@ int cwt_plan_spline_taps(cwt_plan_t plan, int32_t *taps) {
 }
 
 double cwt_plan_spline_hstar(cwt_plan_t plan) { return plan ? plan->p->hstar : 0.0; }
+
+int cwt_plan_describe(cwt_plan_t plan, char *buf, size_t size) {
+    if (!plan || (!buf && size)) return CWT_EINVAL;
+    const Plan &p = *plan->p;
+    std::string s;
+    char line[256];
+    auto add = [&](const char *fmt, auto... a) {
+        std::snprintf(line, sizeof line, fmt, a...);
+        s += line;
+    };
+    add("N=%lld S=%d method=%s precision=%s workspace=%zu tables=%zu\n", (long long)p.N, p.S,
+        p.method == CWT_METHOD_SPLINE ? "spline" : (p.fft_mode == CWT_FFT_WHOLE ? "fft-whole" : "fft-segmented"),
+        p.precision == CWT_FP64 ? "fp64" : "fp32", p.ws_bytes, p.table_bytes);
+    for (const auto &g : p.segs)
+        add("%s L=%d P=%d B=%d Tg=%lld V=%lld nseg=%lld nchunk=%d iters=%d scales=%zu\n",
+            g.kind == cwt::SegGroup::LOCAL ? "local" : "band", g.L, g.P, g.B, (long long)g.Tg, (long long)g.V,
+            (long long)g.nseg, g.nchunk, g.iters, g.scales.size());
+    for (const auto &l : p.seg_launches)
+        add("launch P=%d groups=%zu forward=%zu reduce=%zu inverse=%zu\n", l.P, l.gdev.size(), l.fwd.size(),
+            l.red.size(), l.inv.size());
+    if (p.method == CWT_METHOD_SPLINE)
+        add("spline h*=%.6f E=%lld tiles=%zu\n", p.hstar, (long long)p.spl_E, p.spl_work.size());
+    if (size) {
+        const size_t n = std::min(size - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return (int)std::min<size_t>(s.size(), 0x7fffffff);
+}
 
 int cwt_plan_scale_path(cwt_plan_t plan, int32_t *path) {
     if (!plan || !path) return CWT_EINVAL;

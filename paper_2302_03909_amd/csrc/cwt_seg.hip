@@ -171,69 +171,92 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
     const SegGroupDev gd = cload(kd->groups + w.g);
     const int64_t L = int64_t(1) << gd.lgL, Q = L >> log2_exact(P);
     const int sh = 23 - gd.lgL;
-    const int64_t x0 = (int64_t)w.seg * gd.V - gd.Tg;
     const int tid = threadIdx.x;
     const int B = gd.B;
-    double2 acc = make_double2(0.0, 0.0), base = acc, step = acc, w16 = acc;
+    // bins of this thread: step w_L^{-m}, w_L^{-2m} (two interleaved
+    // accumulation chains over the 16 columns), w_L^{-16 m}, and the chunk's
+    // first-column factor base0 = w_L^{-q0 m}
+    const int64_t q0 = (int64_t)w.idx * gd.iters * G;
+    double2 acc = make_double2(0.0, 0.0), base0 = acc, base = acc, step = acc, step2 = acc, w16 = acc;
     int kap = 0;
     if (tid < B) {
         int64_t mm = (gd.klo + tid) & (L - 1);
         kap = (int)(mm & (P - 1));
         double2 s1 = w23(whi, wlo, mm << sh);
         step = make_double2(s1.x, -s1.y);
+        step2 = cmul(step, step);
         double2 s16 = w23(whi, wlo, ((16 * mm) & (L - 1)) << sh);
         w16 = make_double2(s16.x, -s16.y);
-        int64_t qf = (int64_t)w.idx * gd.iters * G;
-        double2 b = w23(whi, wlo, ((qf * mm) & (L - 1)) << sh);
-        base = make_double2(b.x, -b.y);
+        double2 b = w23(whi, wlo, ((q0 * mm) & (L - 1)) << sh);
+        base0 = make_double2(b.x, -b.y);
+        base = base0;
     }
-    R xn[E];
-    {
-        const int64_t q0 = (int64_t)w.idx * gd.iters * G;
+    // flat loop over (segment, iteration) pairs of this work item: w.pad
+    // consecutive segments, gd.iters iterations of 16 columns each; the next
+    // step's samples are loaded during this step
+    const int total = w.pad * gd.iters;
+    // sample e of step t: x[sg V - Tg + q + tid % G + Q (tid / G + e NT / G)]
+    // (idx = tid + e NT, NT a multiple of G).  Zero boundary: raw buffer
+    // loads over f[0, N) with 32-bit offsets; positions outside, negative
+    // ones included (they wrap to large unsigned offsets), read 0.
+    const __amdgpu_buffer_rsrc_t fr = make_rsrc(f, (uint32_t)(N * (int64_t)sizeof(R)));
+    auto pos0 = [&](int t) {
+        const int64_t sg = w.seg + t / gd.iters;
+        const int64_t q = q0 + (int64_t)(t % gd.iters) * G;
+        return sg * gd.V - gd.Tg + q + (tid % G) + Q * (tid / G);
+    };
+    const int64_t estep = Q * (NT / G);
+    auto load_step = [&](int t, R (&x)[E]) {
+        const int64_t x0 = pos0(t);
+        if (periodic) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            int idx = tid + e * NT;
-            xn[e] = sig_seg(f, N, periodic, x0 + q0 + (idx % G) + Q * (idx / G));
+            for (int e = 0; e < E; ++e) x[e] = sig_seg(f, N, 1, x0 + e * estep);
+        } else {
+            const uint32_t o0 = (uint32_t)(x0 * (int64_t)sizeof(R)), os = (uint32_t)(estep * (int64_t)sizeof(R));
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = bload((const R *)nullptr, fr, o0 + (uint32_t)e * os);
         }
-    }
+    };
+    R xn[E];
+    load_step(0, xn);
     auto emit = [&](int c, int p, C v) { buf[c * LD + lidx(p)] = v; };
-    for (int it = 0; it < gd.iters; ++it) {
+    for (int t = 0; t < total; ++t) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             int idx = tid + e * NT;
             buf[(idx % G) * LD + lidx(idx / G)] = mk<C>(xn[e], (decltype(C::x))0);
         }
-        if (it + 1 < gd.iters) {
-            const int64_t q1 = ((int64_t)w.idx * gd.iters + it + 1) * G;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                int idx = tid + e * NT;
-                xn[e] = sig_seg(f, N, periodic, x0 + q1 + (idx % G) + Q * (idx / G));
-            }
-        }
+        if (t + 1 < total) load_step(t + 1, xn);
         __syncthreads();
         cols_fft<C, P, G, NT, LD, -1, true>(buf, twl, emit);
         __syncthreads();
         if (tid < B) {
-            double2 b = base;
+            double2 b0 = base, b1 = cmul(base, step);
+            double2 a0 = make_double2(0.0, 0.0), a1 = a0;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                double2 y = to_d(buf[g * LD + lidx(kap)]);
-                acc = cadd(acc, cmul(y, b));
-                b = cmul(b, step);
+            for (int g = 0; g < G; g += 2) {
+                a0 = cadd(a0, cmul(to_d(buf[g * LD + lidx(kap)]), b0));
+                a1 = cadd(a1, cmul(to_d(buf[(g + 1) * LD + lidx(kap)]), b1));
+                b0 = cmul(b0, step2);
+                b1 = cmul(b1, step2);
             }
+            acc = cadd(acc, cadd(a0, a1));
             base = cmul(base, w16);
+            if (t % gd.iters == gd.iters - 1) {  // segment complete
+                const int64_t sg = w.seg + t / gd.iters;
+                double2 *Xp = reinterpret_cast<double2 *>(ws + gd.xp_off);
+                Xp[(sg * gd.nchunk + w.idx) * B + tid] = acc;
+                acc = make_double2(0.0, 0.0);
+                base = base0;
+            }
         }
         __syncthreads();
-    }
-    if (tid < B) {
-        double2 *Xp = reinterpret_cast<double2 *>(ws + gd.xp_off);
-        Xp[((int64_t)w.seg * gd.nchunk + w.idx) * B + tid] = acc;
     }
 }
 
 // X[seg][k] = sum over the column chunks of the partial sums, 16 bins per
-// workgroup, 16 lanes per bin, fixed summation order
+// workgroup, 16 lanes per bin, fixed summation order; w.pad consecutive
+// segments per workgroup
 __global__ __launch_bounds__(256) void seg_reduce_kernel(const BatchArgs args) {
     __shared__ double2 part[256];
     const Resolved rv = resolve(args);
@@ -243,25 +266,27 @@ __global__ __launch_bounds__(256) void seg_reduce_kernel(const BatchArgs args) {
     const int kb = threadIdx.x / 16, lane = threadIdx.x % 16;
     const int k = w.idx * 16 + kb;
     const double2 *Xp = reinterpret_cast<const double2 *>(ws + gd.xp_off);
-    double2 a = make_double2(0.0, 0.0);
-    if (k < gd.B)
-        for (int c = lane; c < gd.nchunk; c += 16) a = cadd(a, Xp[((int64_t)w.seg * gd.nchunk + c) * gd.B + k]);
-    part[threadIdx.x] = a;
-    __syncthreads();
-    for (int st = 8; st > 0; st >>= 1) {
-        if (lane < st) part[threadIdx.x] = cadd(part[threadIdx.x], part[threadIdx.x + st]);
+    double2 *X = reinterpret_cast<double2 *>(ws + gd.x_off);
+    for (int64_t sg = w.seg; sg < (int64_t)w.seg + w.pad; ++sg) {
+        double2 a = make_double2(0.0, 0.0);
+        if (k < gd.B)
+            for (int c = lane; c < gd.nchunk; c += 16) a = cadd(a, Xp[(sg * gd.nchunk + c) * gd.B + k]);
+        part[threadIdx.x] = a;
         __syncthreads();
-    }
-    if (lane == 0 && k < gd.B) {
-        double2 *X = reinterpret_cast<double2 *>(ws + gd.x_off);
-        X[(int64_t)w.seg * gd.B + k] = part[threadIdx.x];
+        for (int st = 8; st > 0; st >>= 1) {
+            if (lane < st) part[threadIdx.x] = cadd(part[threadIdx.x], part[threadIdx.x + st]);
+            __syncthreads();
+        }
+        if (lane == 0 && k < gd.B) X[sg * gd.B + k] = part[threadIdx.x];
+        __syncthreads();
     }
 }
 
 // LDS elements for the staged spectrum samples of one BAND group: at most
-// 16 KiB, and at least one unit (two tables for a real-wavelet pair) of P bins
+// kSegKlsBytes, and at least one unit (two tables for a real-wavelet pair) of
+// P bins
 constexpr int seg_kls_elems(int rbytes, int P) {
-    int n = 16384 / rbytes;
+    int n = kSegKlsBytes / rbytes;
     return n < 2 * P ? 2 * P : n;
 }
 

@@ -215,10 +215,13 @@ constexpr int ns_before(int p, int pass) {
     return ns;
 }
 
-// LDS layout: one padding element every 32, so power-of-two strides do not
-// all land in the same bank.
-__device__ __forceinline__ int lidx(int j) { return j + (j >> 5); }
-constexpr int lds_len(int p) { return p + p / 32 + 1; }
+// LDS layout: one padding element every 16.  The radix-16 first pass has
+// each lane write 16 consecutive elements (lane stride 16); with the padding
+// that stride becomes 17 elements, an odd number of 8-byte words, so the 16
+// lanes served together hit distinct banks.  Unit-stride accesses stay
+// contiguous within each run of 16.
+__device__ __forceinline__ int lidx(int j) { return j + (j >> 4); }
+constexpr int lds_len(int p) { return p + p / 16 + 1; }
 
 // One Stockham pass over NCOL columns held in LDS (column c starts at c*LD).
 template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int R, int NS>
