@@ -280,7 +280,7 @@ hipError_t launch_seg_kernel(const SegKernelId &id, const BatchArgs &a, int64_t 
 std::string seg_kernel_id_name(const SegKernelId &id);
 bool local2_size_ok(int L, int precision);
 bool seg_size_ok(int P, int precision);
-int local2_segs_per_block(int L, bool pair);
+int local2_segs_per_block(int L, bool pair, bool fp64);
 
 // names of the kernel instantiations a launch uses (timing labels)
 std::string local_kernel_name(const Plan &p, const LocalGroup &g);

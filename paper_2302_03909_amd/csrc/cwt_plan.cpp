@@ -694,7 +694,8 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         }
         g.nunits = (int32_t)p.units.size() - g.unit0;
         g.ws_xp_off = ws_take((size_t)g.nseg * g.nchunk * g.B * 16);
-        g.ws_x_off = ws_take((size_t)g.nseg * g.B * 16);
+        // one column chunk: the partial sums are the band spectra (no reduce)
+        g.ws_x_off = g.nchunk == 1 ? g.ws_xp_off : ws_take((size_t)g.nseg * g.B * 16);
         // attach to the launch of its P
         SegLaunch *sl = nullptr;
         for (auto &l : p.seg_launches)
@@ -723,18 +724,19 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         sl->gdev.push_back(gd);
         sl->groups.push_back((int32_t)p.segs.size());
         sl->out_rows += (double)js.size();
-        // forward and reduce items cover `pad` consecutive segments, about
-        // 256 items per group: each workgroup then has enough work to repay
-        // its set-up (twiddle tables, band factors)
+        // forward items cover `pad` consecutive segments, about 256 items
+        // per group: each workgroup then has enough work to repay its set-up
+        // (twiddle tables, band factors); reduce items one segment each
         const int64_t nkb = (g.B + 15) / 16;
         const int64_t fsw = std::max<int64_t>(1, g.nseg * g.nchunk / 256);
-        const int64_t rsw = std::max<int64_t>(1, g.nseg * nkb / 256);
+        const int64_t rsw = 1;
         for (int64_t sg = 0; sg < g.nseg; sg += fsw)
             for (int32_t c = 0; c < g.nchunk; ++c)
                 sl->fwd.push_back({gi, (int32_t)sg, c, (int32_t)std::min(fsw, g.nseg - sg)});
-        for (int64_t sg = 0; sg < g.nseg; sg += rsw)
-            for (int32_t kb = 0; kb < nkb; ++kb)
-                sl->red.push_back({gi, (int32_t)sg, kb, (int32_t)std::min(rsw, g.nseg - sg)});
+        if (g.nchunk > 1)
+            for (int64_t sg = 0; sg < g.nseg; sg += rsw)
+                for (int32_t kb = 0; kb < nkb; ++kb)
+                    sl->red.push_back({gi, (int32_t)sg, kb, (int32_t)std::min(rsw, g.nseg - sg)});
         for (int64_t sg = 0; sg < g.nseg; ++sg)
             for (int64_t r0 = 0; r0 < Q; r0 += 16) sl->inv.push_back({gi, (int32_t)sg, (int32_t)r0, 0});
         p.segs.push_back(std::move(g));
@@ -834,7 +836,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         k.nseg = g.nseg;
         k.nscale = (int32_t)g.scales.size();
         k.scale_ids = g.d_scales;
-        const int64_t per = local2_segs_per_block(g.L, p.pair_real);
+        const int64_t per = local2_segs_per_block(g.L, p.pair_real, fp64);
         g.blocks = (g.nseg + per - 1) / per;
         g.key = (int32_t)p.keys.size();
         p.keys.push_back(k);

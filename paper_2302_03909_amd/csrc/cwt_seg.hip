@@ -413,18 +413,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
 // ---------------------------------------------------------------------------
 // fused full-spectrum segments (small scales)
 
-template <typename R, int L, int NCOL, int NT, bool PAIR, bool CPLX>
+// G columns of L points per workgroup (G L = 16 NT): one radix-16 butterfly
+// per thread in every pass of the inverse.  The segment transform is taken in
+// FP64 whatever the plan precision: an FP32 forward spreads rounding noise of
+// order eps |f| over every bin, which for red spectra swamps the weak
+// high-frequency bands the small scales read.  To keep the FP64 forward
+// within the LDS of the inverse buffer, it runs on G/2 complex columns:
+//  * complex output: real segments 2z and 2z+1 share column z as real and
+//    imaginary part; with Z = DFT(a + i b),  A[k] = (Z[k] + conj Z[-k]) / 2
+//    and B[k] = (Z[k] - conj Z[-k]) / (2 i);
+//  * real-wavelet pairs: column c already holds segments 2c and 2c+1 (the
+//    product with the real spectrum keeps them apart), and the forward runs
+//    in two rounds of G/2 columns.
+// With G = 1 the single column takes the whole FP64 buffer.
+template <typename R, int L, int G, int NT, bool PAIR, bool CPLX>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void local2_kernel(
     const BatchArgs a) {
     using C = cplx_t<R>;
     constexpr int LD = lds_len(L);
-    constexpr int E = NCOL * L / NT;
-    static_assert((NCOL * L) % NT == 0, "whole elements per thread");
-    // The segment transform is taken in FP64 whatever the plan precision:
-    // an FP32 forward spreads rounding noise of order eps |f| over every bin,
-    // which for red spectra swamps the weak high-frequency bands the small
-    // scales read.  The FP32 inverse buffer aliases the FP64 one.
-    __shared__ double2 bufF[NCOL * LD];
+    static_assert(G * L == 16 * NT, "one radix-16 butterfly per thread");
+    constexpr int FCOL = G >= 2 ? G / 2 : 1;           // FP64 columns per round
+    constexpr int NROUND = (PAIR && G >= 2) ? 2 : 1;    // forward rounds
+    constexpr bool TWO = !PAIR && G >= 2;               // two real segments per FP64 column
+    constexpr int BUF_BYTES = (FCOL * LD * 16 > G * LD * (int)sizeof(C)) ? FCOL * LD * 16 : G * LD * (int)sizeof(C);
+    __shared__ double2 bufF[BUF_BYTES / 16];
     C *buf = reinterpret_cast<C *>(bufF);
     __shared__ C twl[twl_len(L)];
     const Resolved rv = resolve(a);
@@ -441,34 +453,54 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const double2 *twF = sizeof(R) == 8 ? reinterpret_cast<const double2 *>(twl)
                                         : static_cast<const double2 *>(kd->twl64);
     const int tid = threadIdx.x;
-    constexpr int SEGS = PAIR ? 2 : 1;
-    const int64_t seg0 = rv.local * NCOL * SEGS;
-    for (int idx = tid; idx < NCOL * L; idx += NT) {
-        int c = idx / L, u = idx % L;
-        int64_t s = seg0 + (int64_t)c * SEGS;
-        double a = (double)sig_seg(f, N, periodic, s * V - Tg + u);
-        double b = PAIR ? (double)sig_seg(f, N, periodic, (s + 1) * V - Tg + u) : 0.0;
-        bufF[c * LD + lidx(u)] = make_double2(a, b);
-    }
-    __syncthreads();
-    {
-        auto emit = [&](int c, int p, double2 v) { bufF[c * LD + lidx(p)] = v; };
-        cols_fft<double2, L, NCOL, NT, LD, -1, true, decltype(emit), sizeof(R) == 4>(bufF, twF, emit);
-    }
-    __syncthreads();
-    // spectra in registers in the pass-0 layout of the inverse transforms:
-    // thread t owns column c = t / (L/16), positions i + r L/16
-    static_assert(E == 16, "one radix-16 butterfly per thread");
+    constexpr int SEGS = PAIR ? 2 : 1;  // segments per inverse column
+    const int64_t seg0 = rv.local * G * SEGS;
+    // inverse pass-0 layout: thread t owns column cc = t / (L/16), positions
+    // ii + r L/16
     constexpr int NB = L / 16;
     const int cc = tid / NB, ii = tid % NB;
     C Xr[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r)  // phase i^cph folded in
-        Xr[r] = to_c<C>(mul_i_pow(bufF[cc * LD + lidx(ii + r * NB)], cph));
+    for (int h = 0; h < NROUND; ++h) {
+        // FP64 column z of this round: segments s0(z) and s0(z) + 1
+        for (int idx = tid; idx < FCOL * L; idx += NT) {
+            const int z = idx / L, u = idx % L;
+            const int64_t s = seg0 + (TWO ? 2 * (int64_t)z : (int64_t)(h * FCOL + z) * SEGS);
+            const double x = (double)sig_seg(f, N, periodic, s * V - Tg + u);
+            const double y = (PAIR || TWO) ? (double)sig_seg(f, N, periodic, (s + 1) * V - Tg + u) : 0.0;
+            bufF[z * LD + lidx(u)] = make_double2(x, y);
+        }
+        __syncthreads();
+        {
+            auto emit = [&](int c, int p, double2 v) { bufF[c * LD + lidx(p)] = v; };
+            cols_fft<double2, L, FCOL, NT, LD, -1, true, decltype(emit), sizeof(R) == 4>(bufF, twF, emit);
+        }
+        __syncthreads();
+        // spectra of this thread's column, phase i^cph folded in
+        if constexpr (TWO) {
+            const int z = cc >> 1;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int k = ii + r * NB;
+                const double2 zk = bufF[z * LD + lidx(k)], zm = bufF[z * LD + lidx((L - k) & (L - 1))];
+                // even column: (Z[k] + conj Z[-k]) / 2; odd: (Z[k] - conj Z[-k]) / (2 i)
+                const double2 x = (cc & 1) ? make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x))
+                                           : make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
+                Xr[r] = to_c<C>(mul_i_pow(x, cph));
+            }
+        } else {
+            const int z = cc - h * FCOL;
+            if (z >= 0 && z < FCOL) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) Xr[r] = to_c<C>(mul_i_pow(bufF[z * LD + lidx(ii + r * NB)], cph));
+            }
+        }
+        __syncthreads();
+    }
     R kv[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) kv[r] = ktab[ii + r * NB];
-    __syncthreads();
+    constexpr uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
     for (int j = 0; j < nscale; ++j) {
         C v[16];
 #pragma unroll
@@ -480,10 +512,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
         }
         // keep the prefetch loads ahead of this scale's stores (no code emitted)
         asm volatile("" ::: "memory");
-        cols_pass0_regs<C, L, NCOL, NT, LD, +1>(buf, v);
-        constexpr uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
+        cols_pass0_regs<C, L, G, NT, LD, +1>(buf, v);
         const __amdgpu_buffer_rsrc_t rr =
             make_rsrc(out + (int64_t)cload(scale_ids + j) * N * (CPLX ? 2 : 1), (uint32_t)(N * eb));
+        // position-fastest last pass: consecutive lanes store consecutive
+        // outputs of one segment
         auto emit = [&](int c, int p, C val) {
             const bool inside = p >= Tg && p < Tg + V;
             const int64_t sgi = seg0 + (int64_t)c * SEGS;
@@ -495,7 +528,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
                 if (PAIR) bstore(val.y, rr, (inside && sgi + 1 < nseg) ? (uint32_t)((b + V) * (int64_t)eb) : kOOB);
             }
         };
-        cols_fft_after0<C, L, NCOL, NT, LD, +1, false>(buf, twl, emit);
+        cols_fft_after0<C, L, G, NT, LD, +1, false, decltype(emit), true>(buf, twl, emit);
         __syncthreads();
     }
 }
@@ -503,20 +536,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
 // ---------------------------------------------------------------------------
 // launchers
 
-static constexpr int local2_ncol(int L) { return L >= 1024 ? 1 : 1024 / L; }
-static constexpr int local2_nt(int L) { return local2_ncol(L) * L / 16 < 64 ? 64 : local2_ncol(L) * L / 16; }
+// columns per workgroup: 4096 points (FP32) or 2048 points (FP64), at least one
+static constexpr int local2_ncol(int L, bool fp64) { return (fp64 ? 2048 : 4096) / L > 1 ? (fp64 ? 2048 : 4096) / L : 1; }
+static constexpr int local2_nt(int L, bool fp64) { return local2_ncol(L, fp64) * L / 16; }
 
 bool local2_size_ok(int L, int precision) {
     (void)precision;
     int lmax = 4096;
     return L >= 64 && L <= lmax && (L & (L - 1)) == 0;
 }
-int local2_segs_per_block(int L, bool pair) { return local2_ncol(L) * (pair ? 2 : 1); }
+int local2_segs_per_block(int L, bool pair, bool fp64) { return local2_ncol(L, fp64) * (pair ? 2 : 1); }
 
 template <typename R, int L>
 static hipError_t local2_launch_L(const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
-    constexpr int NCOL = local2_ncol(L);
-    constexpr int NT = local2_nt(L);
+    constexpr int NCOL = local2_ncol(L, sizeof(R) == 8);
+    constexpr int NT = local2_nt(L, sizeof(R) == 8);
     if (cplx)
         hipLaunchKernelGGL((local2_kernel<R, L, NCOL, NT, false, true>), dim3((unsigned)blocks), dim3(NT), 0, st, a);
     else

@@ -80,10 +80,13 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
 }
 
 // last pass: column-fastest thread mapping (consecutive threads take the same
-// butterfly of consecutive columns), outputs go to emit(col, p, value).
+// butterfly of consecutive columns) or, POSFAST, position-fastest (consecutive
+// threads take consecutive butterflies of one column, so that for each r they
+// emit consecutive positions); outputs go to emit(col, p, value).
 // SYNC: barrier between the LDS reads and the emits (needed when emit writes
 // back into buf).
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC, class F, bool TWREC = false>
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC, class F, bool TWREC = false,
+          bool POSFAST = false>
 __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
     constexpr int PASS = num_passes(P) - 1;
     constexpr int R = radix_of(P, PASS);
@@ -96,7 +99,7 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
     for (int q = 0; q < PER; ++q) {
         int gb = tid + q * NT;
         if (NB % NT == 0 || gb < NB) {
-            int c = gb % NCOL, i = gb / NCOL;
+            int c = POSFAST ? gb / (P / R) : gb % NCOL, i = POSFAST ? gb % (P / R) : gb / NCOL;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = buf[c * LD + lidx(i + r * (P / R))];
         }
@@ -106,7 +109,7 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
     for (int q = 0; q < PER; ++q) {
         int gb = tid + q * NT;
         if (NB % NT == 0 || gb < NB) {
-            int c = gb % NCOL, i = gb / NCOL;
+            int c = POSFAST ? gb / (P / R) : gb % NCOL, i = POSFAST ? gb % (P / R) : gb / NCOL;
             if constexpr (NS > 1) {
                 C w[R];
                 twiddles<C, R, NS, TWREC>(twl + twl_off(P, PASS) + i, w);
@@ -150,11 +153,11 @@ __device__ __forceinline__ void cols_pass0_regs(C *buf, C *v) {
 }
 
 // remaining passes after cols_pass0_regs
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC_LAST, class F>
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC_LAST, class F, bool POSFAST = false>
 __device__ __forceinline__ void cols_fft_after0(C *buf, const C *twl, F &emit) {
     static_assert(num_passes(P) >= 2, "at least two passes");
     cols_mid_from<C, P, NCOL, NT, LD, SIGN, 1>(buf, twl);
-    cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST>(buf, twl, emit);
+    cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST, F, false, POSFAST>(buf, twl, emit);
 }
 
 // copy a per-pass twiddle table from global memory into LDS
