@@ -81,7 +81,7 @@ __global__ __launch_bounds__(NT) void forward_single(const RS *__restrict__ f, i
     constexpr int LD = lds_len(P);
     __shared__ double2 buf[LD];
     for (int n = threadIdx.x; n < P; n += NT) buf[lidx(n)] = make_double2(fwd_input(f, N, mode, P, T, n), 0.0);
-    __syncthreads();
+    lds_barrier();
     block_fft<double2, P, 1, NT, LD, -1>(buf, tw);
     for (int k = threadIdx.x; k < P; k += NT) {
         double2 v = buf[lidx(k)];
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(NT) void forward_pass1(const RS *__restrict__ f, in
         int64_t n = n1_0 + c + M1 * n2;
         buf[c * LD + lidx(n2)] = make_double2(fwd_input(f, N, mode, M, T, n), 0.0);
     }
-    __syncthreads();
+    lds_barrier();
     block_fft<double2, P, G, NT, LD, -1>(buf, tw);
     for (int idx = threadIdx.x; idx < G * P; idx += NT) {
         int c = idx % G, k2 = idx / G;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(NT) void forward_pass2(const double2 *__restrict__ 
         int c = idx / P, n1 = idx % P;
         buf[c * LD + lidx(n1)] = Y[(k2_0 + c) * P + n1];
     }
-    __syncthreads();
+    lds_barrier();
     block_fft<double2, P, G, NT, LD, -1>(buf, tw);
     for (int idx = threadIdx.x; idx < G * P; idx += NT) {
         int c = idx % G, k1 = idx / G;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(NT) void local_kernel(const R *__restrict__ f, int6
         double b = PAIR ? (double)sig_at(f, N, periodic, x0 + V + u) : 0.0;
         bufF[lidx(u)] = make_double2(a, b);
     }
-    __syncthreads();
+    lds_barrier();
     block_fft<double2, L, 1, NT, LD, -1>(bufF, tw64);
     C X[E];
 #pragma unroll
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(NT) void local_kernel(const R *__restrict__ f, int6
         const double2 v = bufF[lidx(tid + i * NT)];
         X[i] = mk<C>((R)v.x, (R)v.y);
     }
-    __syncthreads();
+    lds_barrier();
     const int64_t b0 = seg * V;
     const bool second = PAIR && (seg + 1 < nseg);
     for (int j = 0; j < nscale; ++j) {
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NT) void local_kernel(const R *__restrict__ f, int6
             int m = tid + i * NT;
             buf[lidx(m)] = mul_iq(cscale(X[i], kt[m]), cph);
         }
-        __syncthreads();
+        lds_barrier();
         block_fft<C, L, 1, NT, LD, +1>(buf, tw);
         R *row = out + (int64_t)scale_ids[j] * N * (CPLX ? 2 : 1);
         for (int64_t u = tid; u < V; u += NT) {
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(NT) void local_kernel(const R *__restrict__ f, int6
                 if (second && b + V < N) row[b + V] = v.y;
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(NT) void column_kernel(const cplx_t<R> *__restrict_
 #pragma unroll
         for (int g = 0; g < G; ++g) buf[g * LD + lidx(k)] = acc[g];
     }
-    __syncthreads();
+    lds_barrier();
     block_fft<C, P, G, NT, LD, +1>(buf, tw);
     R *rowa = out + (int64_t)d.sa * N * (CPLX ? 2 : 1);
     R *rowb = (PAIR && d.sb >= 0) ? out + (int64_t)d.sb * N : nullptr;

@@ -53,7 +53,6 @@ struct SegGroup {
     int64_t tab_off = 0;          // LOCAL: offset (elements) of the L-point tables
     int32_t *d_scales = nullptr;
     int64_t twl_off = -1;  // LOCAL: per-pass LDS twiddle table of size L, bytes
-    int64_t twl64_off = -1;  // LOCAL: the same table in FP64, bytes
     int64_t gtw_off = -1;  // BAND: w_L^{m g}, g < 16, m in band, bytes
     size_t ws_xp_off = 0, ws_x_off = 0;
     int32_t unit0 = 0, nunits = 0;  // BAND: range in Plan::units
@@ -110,7 +109,6 @@ struct KeyDesc {
     const void *ktab;      // spectrum samples, plan precision (LOCAL: this group's L-point tables)
     const char *twbase;    // the plan's twiddle allocation
     const void *twl;       // per-pass LDS twiddle table of the key's transform size
-    const void *twl64;     // LOCAL: the same table in FP64 (segment forward transform)
     const double2 *whi, *wlo;  // FP64 w_{2^23} = hi[x >> 11] lo[x & 2047]
     int64_t Tg, V, nseg;   // LOCAL group
     int32_t nscale, pad;

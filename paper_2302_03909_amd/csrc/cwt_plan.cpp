@@ -608,7 +608,6 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         g.tab_off = tab_n;
         for (int j : g.scales) add_job(p.scales[j], g.L, 0, g.L, true);
         g.twl_off = fp64 ? push_pass_twiddles<double>(tb, g.L) : push_pass_twiddles<float>(tb, g.L);
-        g.twl64_off = fp64 ? g.twl_off : push_pass_twiddles<double>(tb, g.L);
         p.segs.push_back(std::move(g));
     }
 
@@ -830,7 +829,6 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         KeyDesc k = kb;
         k.ktab = dtab + (size_t)g.tab_off * eb;
         k.twl = tw + g.twl_off;
-        k.twl64 = tw + g.twl64_off;
         k.Tg = g.Tg;
         k.V = g.V;
         k.nseg = g.nseg;

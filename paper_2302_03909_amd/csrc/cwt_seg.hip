@@ -136,7 +136,6 @@ __device__ __forceinline__ Resolved resolve(const BatchArgs &a) {
     k.ktab = uni(k.ktab);
     k.twbase = uni(k.twbase);
     k.twl = uni(k.twl);
-    k.twl64 = uni(k.twl64);
     k.whi = uni(k.whi);
     k.wlo = uni(k.wlo);
     k.scale_ids = uni(k.scale_ids);
@@ -227,9 +226,9 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
             buf[(idx % G) * LD + lidx(idx / G)] = mk<C>(xn[e], (decltype(C::x))0);
         }
         if (t + 1 < total) load_step(t + 1, xn);
-        __syncthreads();
+        lds_barrier();
         cols_fft<C, P, G, NT, LD, -1, true>(buf, twl, emit);
-        __syncthreads();
+        lds_barrier();
         if (tid < B) {
             double2 b0 = base, b1 = cmul(base, step);
             double2 a0 = make_double2(0.0, 0.0), a1 = a0;
@@ -250,7 +249,7 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
                 base = base0;
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -272,13 +271,13 @@ __global__ __launch_bounds__(256) void seg_reduce_kernel(const BatchArgs args) {
         if (k < gd.B)
             for (int c = lane; c < gd.nchunk; c += 16) a = cadd(a, Xp[(sg * gd.nchunk + c) * gd.B + k]);
         part[threadIdx.x] = a;
-        __syncthreads();
+        lds_barrier();
         for (int st = 8; st > 0; st >>= 1) {
             if (lane < st) part[threadIdx.x] = cadd(part[threadIdx.x], part[threadIdx.x + st]);
-            __syncthreads();
+            lds_barrier();
         }
         if (lane == 0 && k < gd.B) X[sg * gd.B + k] = part[threadIdx.x];
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -335,7 +334,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
         const double2 *X = reinterpret_cast<const double2 *>(ws + gd.x_off);
         xs[tid] = to_c<C>(cmul(X[(int64_t)w.seg * B + tid], w23(whi, wlo, ((mm * r0) & (L - 1)) << sh)));
     }
-    __syncthreads();
+    lds_barrier();
     // pass-0 inputs of this thread: column c, positions kap = i + r P/16; the
     // band bin congruent to kap modulo P (if any) and w_L^{m c}
     const int c = tid / NB, i = tid % NB;
@@ -367,7 +366,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
         fro[r] = fr < B ? fr : 0;
         xg[r] = mul_i_pow(xg[r], cph);
     }
-    __syncthreads();  // xs (in buf) is no longer read
+    lds_barrier();  // xs (in buf) is no longer read
     const int64_t ob = (int64_t)w.seg * gd.V - gd.Tg;
     const uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
     for (int u = 0; u < nunits; ++u) {
@@ -406,7 +405,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             }
         };
         cols_fft_after0<C, P, G, NT, LD, +1, false>(buf, twl, emit);
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -444,14 +443,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const R *__restrict__ f = static_cast<const R *>(rv.bi.f);
     R *__restrict__ out = static_cast<R *>(rv.bi.out);
     const int64_t N = kd->N, Tg = kd->Tg, V = kd->V, nseg = kd->nseg;
-    const int periodic = kd->periodic, nscale = kd->nscale, cph = kd->cph;
+    const int periodic = __builtin_amdgcn_readfirstlane(kd->periodic);
+    const int nscale = kd->nscale, cph = kd->cph;
     const int32_t *__restrict__ scale_ids = kd->scale_ids;
     const R *__restrict__ ktab = static_cast<const R *>(kd->ktab);
     load_twl<C, L, NT>(twl, static_cast<const C *>(kd->twl));
-    // FP64 forward twiddles: the LDS table for FP64 plans, else the plan's
-    // FP64 table in global memory
-    const double2 *twF = sizeof(R) == 8 ? reinterpret_cast<const double2 *>(twl)
-                                        : static_cast<const double2 *>(kd->twl64);
+    // FP64 forward twiddles: the LDS table for FP64 plans, else evaluated
+    const double2 *twF = reinterpret_cast<const double2 *>(twl);
     const int tid = threadIdx.x;
     constexpr int SEGS = PAIR ? 2 : 1;  // segments per inverse column
     const int64_t seg0 = rv.local * G * SEGS;
@@ -460,22 +458,48 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     constexpr int NB = L / 16;
     const int cc = tid / NB, ii = tid % NB;
     C Xr[16];
+    // Zero boundary: raw buffer loads over f[0, N) with 32-bit offsets;
+    // positions outside, negative ones included (they wrap to large unsigned
+    // offsets), read 0.  All loads of a round are issued before the first
+    // LDS write.
+    const __amdgpu_buffer_rsrc_t fr = make_rsrc(f, (uint32_t)(N * (int64_t)sizeof(R)));
+    constexpr int EL = FCOL * L / NT;  // FP64 column elements per thread and round
+    static_assert((FCOL * L) % NT == 0, "whole column elements per thread");
+    constexpr bool TWOSEG = PAIR || TWO;
 #pragma unroll
     for (int h = 0; h < NROUND; ++h) {
         // FP64 column z of this round: segments s0(z) and s0(z) + 1
-        for (int idx = tid; idx < FCOL * L; idx += NT) {
-            const int z = idx / L, u = idx % L;
+        R xa[EL], xb[EL];
+        auto pos = [&](int e) {
+            const int idx = tid + e * NT, z = idx / L, u = idx % L;
             const int64_t s = seg0 + (TWO ? 2 * (int64_t)z : (int64_t)(h * FCOL + z) * SEGS);
-            const double x = (double)sig_seg(f, N, periodic, s * V - Tg + u);
-            const double y = (PAIR || TWO) ? (double)sig_seg(f, N, periodic, (s + 1) * V - Tg + u) : 0.0;
-            bufF[z * LD + lidx(u)] = make_double2(x, y);
+            return s * V - Tg + u;
+        };
+        if (periodic) {
+#pragma unroll
+            for (int e = 0; e < EL; ++e) {
+                xa[e] = sig_seg(f, N, 1, pos(e));
+                xb[e] = TWOSEG ? sig_seg(f, N, 1, pos(e) + V) : (R)0;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < EL; ++e) {
+                const int64_t pa = pos(e);
+                xa[e] = bload((const R *)nullptr, fr, (uint32_t)(pa * (int64_t)sizeof(R)));
+                xb[e] = TWOSEG ? bload((const R *)nullptr, fr, (uint32_t)((pa + V) * (int64_t)sizeof(R))) : (R)0;
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EL; ++e) {
+            const int idx = tid + e * NT;
+            bufF[(idx / L) * LD + lidx(idx % L)] = make_double2((double)xa[e], (double)xb[e]);
+        }
+        lds_barrier();
         {
             auto emit = [&](int c, int p, double2 v) { bufF[c * LD + lidx(p)] = v; };
             cols_fft<double2, L, FCOL, NT, LD, -1, true, decltype(emit), sizeof(R) == 4>(bufF, twF, emit);
         }
-        __syncthreads();
+        lds_barrier();
         // spectra of this thread's column, phase i^cph folded in
         if constexpr (TWO) {
             const int z = cc >> 1;
@@ -495,20 +519,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
                 for (int r = 0; r < 16; ++r) Xr[r] = to_c<C>(mul_i_pow(bufF[z * LD + lidx(ii + r * NB)], cph));
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
+    // spectrum samples through buffer loads: flat loads would also count as
+    // LDS operations and make every LDS wait wait for them
+    const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, (uint32_t)((int64_t)nscale * L * (int64_t)sizeof(R)));
     R kv[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) kv[r] = ktab[ii + r * NB];
+    for (int r = 0; r < 16; ++r) kv[r] = bload(ktab, kr, (uint32_t)((ii + r * NB) * sizeof(R)));
     constexpr uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
     for (int j = 0; j < nscale; ++j) {
         C v[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = cscale(Xr[r], kv[r]);
         if (j + 1 < nscale) {  // prefetch the next scale's spectrum samples
-            const R *kt = ktab + (int64_t)(j + 1) * L;
+            const uint32_t o = (uint32_t)((j + 1) * L * (int)sizeof(R));
 #pragma unroll
-            for (int r = 0; r < 16; ++r) kv[r] = kt[ii + r * NB];
+            for (int r = 0; r < 16; ++r) kv[r] = bload(ktab, kr, o + (uint32_t)((ii + r * NB) * sizeof(R)));
         }
         // keep the prefetch loads ahead of this scale's stores (no code emitted)
         asm volatile("" ::: "memory");
@@ -529,7 +556,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             }
         };
         cols_fft_after0<C, L, G, NT, LD, +1, false, decltype(emit), true>(buf, twl, emit);
-        __syncthreads();
+        lds_barrier();
     }
 }
 

@@ -24,23 +24,27 @@ constexpr int twl_len(int P) { return twl_off(P, num_passes(P)) > 0 ? twl_off(P,
 
 // middle pass: LDS -> LDS, column-major thread mapping (consecutive threads
 // take consecutive butterflies of one column)
-// Twiddles of a butterfly: e^{+2 pi i r k/(R Ns)}, r = 1..R-1, read from the
-// table (TWREC = false) or, TWREC = true, only r = 1 read and the others
-// formed as its powers (one table read per butterfly; used by the FP64
-// segment transforms of FP32 plans, whose table sits in global memory).
-template <typename C, int R, int NS, bool TWREC>
-__device__ __forceinline__ void twiddles(const C *tp, C (&w)[R]) {
-    if constexpr (TWREC) {
-        w[1] = tp[0];
+// Twiddles of butterfly k: e^{+2 pi i r k/(R Ns)}, r = 1..R-1, read from the
+// table (TWCALC = false) or, TWCALC = true (FP64 only), w^1 evaluated with
+// sincospi and the other powers formed by products.  The FP64 segment
+// transforms of FP32 plans use the latter: a table read from global memory
+// in the middle of a pass would expose its full latency.
+template <typename C, int R, int NS, bool TWCALC>
+__device__ __forceinline__ void twiddles(const C *tab, int k, C (&w)[R]) {
+    if constexpr (TWCALC) {
+        static_assert(sizeof(decltype(C::x)) == 8, "computed twiddles are FP64");
+        double sn, cs;
+        sincospi((double)(2 * k) / (double)(R * NS), &sn, &cs);
+        w[1] = mk<C>(cs, sn);
 #pragma unroll
         for (int r = 2; r < R; ++r) w[r] = cmul(w[r - 1], w[1]);
     } else {
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[r] = tp[(r - 1) * NS];
+        for (int r = 1; r < R; ++r) w[r] = tab[k + (r - 1) * NS];
     }
 }
 
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS, bool TWREC = false>
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS, bool TWCALC = false>
 __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
     constexpr int R = radix_of(P, PASS);
     constexpr int NS = ns_before(P, PASS);
@@ -57,7 +61,7 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
             for (int r = 0; r < R; ++r) v[q][r] = buf[c * LD + lidx(i + r * (P / R))];
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         int gb = tid + q * NT;
@@ -66,7 +70,7 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
             int k = i % NS;
             if constexpr (NS > 1) {
                 C w[R];
-                twiddles<C, R, NS, TWREC>(twl + twl_off(P, PASS) + k, w);
+                twiddles<C, R, NS, TWCALC>(twl + twl_off(P, PASS), k, w);
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[q][r] = SIGN > 0 ? cmul(v[q][r], w[r]) : cmulc(v[q][r], w[r]);
             }
@@ -76,7 +80,7 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
             for (int r = 0; r < R; ++r) buf[c * LD + lidx(base + r * NS)] = v[q][r];
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // last pass: column-fastest thread mapping (consecutive threads take the same
@@ -85,7 +89,7 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
 // emit consecutive positions); outputs go to emit(col, p, value).
 // SYNC: barrier between the LDS reads and the emits (needed when emit writes
 // back into buf).
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC, class F, bool TWREC = false,
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC, class F, bool TWCALC = false,
           bool POSFAST = false>
 __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
     constexpr int PASS = num_passes(P) - 1;
@@ -104,7 +108,7 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
             for (int r = 0; r < R; ++r) v[q][r] = buf[c * LD + lidx(i + r * (P / R))];
         }
     }
-    if constexpr (SYNC) __syncthreads();
+    if constexpr (SYNC) lds_barrier();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         int gb = tid + q * NT;
@@ -112,7 +116,7 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
             int c = POSFAST ? gb / (P / R) : gb % NCOL, i = POSFAST ? gb % (P / R) : gb / NCOL;
             if constexpr (NS > 1) {
                 C w[R];
-                twiddles<C, R, NS, TWREC>(twl + twl_off(P, PASS) + i, w);
+                twiddles<C, R, NS, TWCALC>(twl + twl_off(P, PASS), i, w);
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[q][r] = SIGN > 0 ? cmul(v[q][r], w[r]) : cmulc(v[q][r], w[r]);
             }
@@ -123,20 +127,20 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
     }
 }
 
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS, bool TWREC = false>
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS, bool TWCALC = false>
 __device__ __forceinline__ void cols_mid_from(C *buf, const C *twl) {
     if constexpr (PASS + 1 < num_passes(P)) {
-        cols_pass_mid<C, P, NCOL, NT, LD, SIGN, PASS, TWREC>(buf, twl);
-        cols_mid_from<C, P, NCOL, NT, LD, SIGN, PASS + 1, TWREC>(buf, twl);
+        cols_pass_mid<C, P, NCOL, NT, LD, SIGN, PASS, TWCALC>(buf, twl);
+        cols_mid_from<C, P, NCOL, NT, LD, SIGN, PASS + 1, TWCALC>(buf, twl);
     }
 }
 
 // Full transform of NCOL columns in buf (filled and synchronised by the
 // caller).  Outputs are emitted in natural order positions p.
-template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC_LAST, class F, bool TWREC = false>
+template <typename C, int P, int NCOL, int NT, int LD, int SIGN, bool SYNC_LAST, class F, bool TWCALC = false>
 __device__ __forceinline__ void cols_fft(C *buf, const C *twl, F &emit) {
-    cols_mid_from<C, P, NCOL, NT, LD, SIGN, 0, TWREC>(buf, twl);
-    cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST, F, TWREC>(buf, twl, emit);
+    cols_mid_from<C, P, NCOL, NT, LD, SIGN, 0, TWCALC>(buf, twl);
+    cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST, F, TWCALC>(buf, twl, emit);
 }
 
 // Pass 0 (radix 16, Ns = 1) from registers: thread t owns butterfly
@@ -149,7 +153,7 @@ __device__ __forceinline__ void cols_pass0_regs(C *buf, C *v) {
     dftR<16, SIGN>(v);
 #pragma unroll
     for (int r = 0; r < 16; ++r) buf[c * LD + lidx(i * 16 + r)] = v[r];
-    __syncthreads();
+    lds_barrier();
 }
 
 // remaining passes after cols_pass0_regs

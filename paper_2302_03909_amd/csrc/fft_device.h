@@ -21,6 +21,17 @@
 
 namespace cwt {
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// waits until every global store the wave issued has completed, which
+// serialises a kernel's output stores with its next FFT; the kernels here
+// never read back, within a launch, global memory that another wave wrote,
+// so their barriers need only the LDS fence.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename R> struct cplx_of;
 template <> struct cplx_of<float> { using type = float2; };
 template <> struct cplx_of<double> { using type = double2; };
@@ -239,7 +250,7 @@ __device__ __forceinline__ void stockham_pass(C *buf, const C *__restrict__ tw) 
             for (int r = 0; r < R; ++r) v[q][r] = buf[c * LD + lidx(i + r * (P / R))];
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         int gb = tid + q * NT;
@@ -259,7 +270,7 @@ __device__ __forceinline__ void stockham_pass(C *buf, const C *__restrict__ tw) 
             for (int r = 0; r < R; ++r) buf[c * LD + lidx(base + r * NS)] = v[q][r];
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS>
@@ -271,7 +282,7 @@ __device__ __forceinline__ void block_fft_from(C *buf, const C *__restrict__ tw)
 }
 
 // In-place FFT of NCOL columns of length P in LDS.  Callers must
-// __syncthreads() after filling buf; the function ends with a barrier.
+// lds_barrier() after filling buf; the function ends with a barrier.
 template <typename C, int P, int NCOL, int NT, int LD, int SIGN>
 __device__ __forceinline__ void block_fft(C *buf, const C *__restrict__ tw) {
     block_fft_from<C, P, NCOL, NT, LD, SIGN, 0>(buf, tw);
