@@ -229,6 +229,12 @@ int cwt_plan_describe(cwt_plan_t plan, char *buf, size_t size);
  * It returns the number of kernels (at most max_kernels are written) and
  * clears the records.  Not thread-safe with respect to concurrent cwt_exec
  * calls on the same plan; enabling costs two event records per launch.
+ * Without timing, the local-group kernels of a segmented plan run on a
+ * second stream of the calling thread, beside the band kernels on the
+ * caller's stream (forked after, and joined back into, the caller's
+ * stream).  With timing on, every launch of the call stays on the caller's
+ * stream, so each recorded duration is that kernel's alone.  For
+ * cwt_exec_batch the first plan's setting applies.
  */
 int cwt_plan_timing_enable(cwt_plan_t plan, int32_t on);
 int cwt_plan_timing_read(cwt_plan_t plan, int32_t max_kernels, char *names,

@@ -1017,6 +1017,54 @@ static void for_each_seg_launch(const Plan &p, F &&fn) {
     }
 }
 
+// Second stream of the calling thread on the current device (non-blocking,
+// default priority) with a fork/join event pair.  The local-group kernels of
+// a call run on it while the band kernels (forward, reduce, inverse, which
+// depend on each other) run on the caller's stream: the two chains write
+// disjoint output rows and only read the signal, and running them side by
+// side lets one chain's latency-bound phases (segment loads and transforms,
+// launch tails) overlap the other's output stores.
+struct SideStream {
+    hipStream_t st = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+static SideStream &side_stream() {
+    static thread_local std::map<int, SideStream> m;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    SideStream &s = m[dev];
+    if (!s.st) {
+        HIPCHK(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&s.join, hipEventDisableTiming));
+    }
+    return s;
+}
+
+// Stream assignment of one call's segmented launches: local kernels (kind 0)
+// on the side stream when the call also has band launches (and launch timing
+// is off, so that timed durations are each kernel's own), everything else on
+// the caller's stream.  begin() forks after the work already queued on the
+// caller's stream, end() joins.
+struct SegStreams {
+    hipStream_t main, side;
+    SideStream *ss = nullptr;
+    SegStreams(hipStream_t st, bool split) : main(st), side(st) {
+        if (!split) return;
+        ss = &side_stream();
+        side = ss->st;
+        HIPCHK(hipEventRecord(ss->fork, main));
+        HIPCHK(hipStreamWaitEvent(side, ss->fork, 0));
+    }
+    hipStream_t of(int kind) const { return kind == 0 ? side : main; }
+    void end() {
+        if (!ss) return;
+        HIPCHK(hipEventRecord(ss->join, side));
+        HIPCHK(hipStreamWaitEvent(main, ss->join, 0));
+        ss = nullptr;
+    }
+};
+
 // Runs `launch` and, when timing is on, brackets it with events on `st`.
 template <typename F>
 static void timed(Plan &p, hipStream_t st, const std::string &name, double bytes, const char *what, F &&launch) {
@@ -1146,11 +1194,18 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, vo
                                           "segment inverse launch"};
             cwt::BatchArgs a{};
             a.i0 = {signal, out, static_cast<char *>(workspace)};
+            bool has_local = false, has_band = false;
+            cwt::for_each_seg_launch(p, [&](const cwt::SegKernelId &id, int32_t, int64_t, double) {
+                (id.kind == 0 ? has_local : has_band) = true;
+            });
+            cwt::SegStreams ss(st, has_local && has_band && !p.timing);
             cwt::for_each_seg_launch(p, [&](const cwt::SegKernelId &id, int32_t key, int64_t blocks, double bytes) {
                 a.k0 = p.keys[key];
-                cwt::timed(p, st, cwt::seg_kernel_id_name(id), bytes, what[id.kind],
-                           [&] { return cwt::launch_seg_kernel(id, a, blocks, st); });
+                hipStream_t ks = ss.of(id.kind);
+                cwt::timed(p, ks, cwt::seg_kernel_id_name(id), bytes, what[id.kind],
+                           [&] { return cwt::launch_seg_kernel(id, a, blocks, ks); });
             });
+            ss.end();
         }
         if (p.M > 0)
             cwt::timed(p, st, "forward", nn * sb + (double)p.M * fb, "forward launch",
@@ -1341,15 +1396,20 @@ int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals, void *co
             }
             HIPCHK(hipMemcpyAsync(tables, host.data(), host.size(), hipMemcpyHostToDevice, st));
             Plan &tp = *plans[0]->p;  // timing records go to the first plan
+            bool has_local = false, has_band = false;
+            for (auto &m : bl.merged) (m.id.kind == 0 ? has_local : has_band) = true;
+            cwt::SegStreams ss(st, has_local && has_band && !tp.timing);
             for (auto &m : bl.merged) {
                 cwt::BatchArgs a{};
                 a.ranges = reinterpret_cast<const cwt::BatchRange *>(tables + m.ranges_off);
                 a.coarse = reinterpret_cast<const int32_t *>(tables + m.map_off);
                 a.insts = reinterpret_cast<const cwt::BatchInst *>(tables + bl.insts_off);
                 a.nranges = (int32_t)m.ranges.size();
-                cwt::timed(tp, st, cwt::seg_kernel_id_name(m.id), m.bytes, "batched segment launch",
-                           [&] { return cwt::launch_seg_kernel(m.id, a, m.blocks, st); });
+                hipStream_t ks = ss.of(m.id.kind);
+                cwt::timed(tp, ks, cwt::seg_kernel_id_name(m.id), m.bytes, "batched segment launch",
+                           [&] { return cwt::launch_seg_kernel(m.id, a, m.blocks, ks); });
             }
+            ss.end();
         }
         for (int32_t i = 0; i < n; ++i) {
             if (cwt::seg_plan(*plans[i]->p)) continue;
