@@ -653,9 +653,13 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         const int64_t Q = g.L / g.P;
         const int64_t iters_total = Q / 16;
         // column chunks of the forward: enough workgroups to fill the device,
-        // at most 256 partial sums per bin
+        // at most 256 partial sums per bin.  A chunk keeps at least two
+        // 16-column iterations: a wave reads 16 consecutive FP32 columns (half
+        // a 128-byte line) per row, and the other half is then read by the
+        // same workgroup one iteration later instead of by another workgroup,
+        // often on another XCD with its own L2.
         int64_t nchunk = 1;
-        while (nchunk * 2 <= iters_total && nchunk * 2 <= 256 && g.nseg * nchunk < 2048) nchunk *= 2;
+        while (nchunk * 4 <= iters_total && nchunk * 2 <= 256 && g.nseg * nchunk < 2048) nchunk *= 2;
         g.nchunk = (int32_t)nchunk;
         g.iters = (int32_t)(iters_total / nchunk);
         // spectrum samples of each scale on the group band
