@@ -546,9 +546,12 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     std::vector<Cand> loc, band;
     for (int j = 0; j < p.S; ++j) {
         double s = p.scales[j];
-        // 8 T per segment for long signals; a short signal is a single
+        // 8 T per segment for long signals, at least 256 samples (a group of
+        // shorter segments holds only the few smallest scales, too few to
+        // amortise its segment transforms); a short signal is a single
         // segment just long enough for it and the halos
-        int64_t L = std::max<int64_t>(64, std::min(next_pow2(8 * p.T[j] + 1), next_pow2(p.N + 2 * align_halo(p.T[j]))));
+        int64_t L = std::min(std::max<int64_t>(256, next_pow2(8 * p.T[j] + 1)),
+                             std::max<int64_t>(64, next_pow2(p.N + 2 * align_halo(p.T[j]))));
         int lg = 0;
         while ((int64_t(1) << lg) < L) ++lg;
         if (lg > lg_max) fail(CWT_EUNSUPPORTED, "scale too large for the segmented transform (wavelet support above 2^20 samples)");
