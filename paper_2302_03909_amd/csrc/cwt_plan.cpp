@@ -592,6 +592,21 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         return off;
     };
 
+    // Local scales of an FP32 plan of a long signal whose segments would be
+    // at most 2048 samples long are taken together at the longest of those
+    // lengths: the cost per scale of a local group hardly depends on L up to
+    // 2048 (the output stores dominate), while every group pays one FP64
+    // transform of all its segments.  (At the longer length a short signal
+    // would compute more halo, and FP64 groups of 2048 run at half the
+    // occupancy, so neither is merged.)
+    if (!fp64) {
+        int lgm = 0;
+        for (auto &c : loc)
+            if (c.lg <= 11) lgm = std::max(lgm, c.lg);
+        if (lgm > 0 && p.N >= (int64_t(8) << lgm))
+            for (auto &c : loc)
+                if (c.lg <= 11) c.lg = lgm;
+    }
     // LOCAL groups by L
     std::sort(loc.begin(), loc.end(), [](const Cand &a, const Cand &b) { return a.lg < b.lg || (a.lg == b.lg && a.j < b.j); });
     for (size_t i = 0; i < loc.size();) {
