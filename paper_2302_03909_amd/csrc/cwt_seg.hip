@@ -76,6 +76,13 @@ __device__ __forceinline__ double bload(const double *, __amdgpu_buffer_rsrc_t r
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
+__device__ __forceinline__ float2 bload(const float2 *, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ double2 bload(const double2 *, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 template <typename C> __device__ __forceinline__ C to_c(double2 v) { return mk<C>((decltype(C::x))v.x, (decltype(C::x))v.y); }
 template <typename C> __device__ __forceinline__ double2 to_d(C v) { return make_double2((double)v.x, (double)v.y); }
 
@@ -305,7 +312,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     static_assert(NT == P, "one pass-0 butterfly per thread");
     __shared__ C buf[G * LD];
     __shared__ C twl[twl_len(P)];
-    __shared__ SegUnit us[MAXU];
     __shared__ R kls[KLS];  // spectrum samples of the group's units (and pair partners)
     const Resolved rv = resolve(a);
     const KeyDesc *kd = &rv.kd;
@@ -317,16 +323,35 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const char *__restrict__ twbase = kd->twbase;
     const SegUnit *__restrict__ units = kd->units;
     const double2 *__restrict__ whi = kd->whi, *__restrict__ wlo = kd->wlo;
-    load_twl<C, P, NT>(twl, static_cast<const C *>(kd->twl));
     const SegWork w = cload(kd->work + rv.local);
     const SegGroupDev gd = cload(kd->groups + w.g);
     const int nunits = gd.nunits < MAXU ? gd.nunits : MAXU;
-    for (int u = threadIdx.x; u < nunits; u += NT) us[u] = units[gd.unit0 + u];
     const int64_t L = int64_t(1) << gd.lgL, Q = L >> log2_exact(P);
     const int sh = 23 - gd.lgL;
     const int tid = threadIdx.x;
     const int B = gd.B;
     const int64_t r0 = w.idx;
+    // Every global read of the set-up is a buffer load issued before the
+    // first wait (flat loads would also count as LDS operations), so the
+    // set-up costs one memory latency instead of one per load.
+    // pass-0 inputs of this thread: column c, positions kap = i + r P/16; the
+    // band bin congruent to kap modulo P (if any) and w_L^{m c}
+    const int c = tid / NB, i = tid % NB;
+    // first(r): band bin congruent to i + r P/16 (valid when < B)
+    const int f0 = (int)(((int64_t)i - gd.klo) & (P - 1));
+    auto first_of = [&](int r) { return (f0 + r * NB) & (P - 1); };
+    // w_L^{m c} of the band bins this thread reads; 0 for positions outside
+    // the band (out-of-range offsets read 0)
+    C gv[16];
+    {
+        const __amdgpu_buffer_rsrc_t gr =
+            make_rsrc(uni(twbase + gd.gtw_off), __builtin_amdgcn_readfirstlane((uint32_t)(16 * B * (int)sizeof(C))));
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int fr = first_of(r);
+            gv[r] = bload((const C *)nullptr, gr, fr < B ? (uint32_t)((c * B + fr) * (int)sizeof(C)) : kOOB);
+        }
+    }
     // band spectrum of the segment times w_L^{m r0}, staged in LDS (reuses buf)
     C *xs = buf;
     if (tid < B) {
@@ -334,46 +359,50 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
         const double2 *X = reinterpret_cast<const double2 *>(ws + gd.x_off);
         xs[tid] = to_c<C>(cmul(X[(int64_t)w.seg * B + tid], w23(whi, wlo, ((mm * r0) & (L - 1)) << sh)));
     }
-    lds_barrier();
-    // pass-0 inputs of this thread: column c, positions kap = i + r P/16; the
-    // band bin congruent to kap modulo P (if any) and w_L^{m c}
-    const int c = tid / NB, i = tid % NB;
-    // first(r): band bin congruent to i + r P/16 (valid when < B)
-    const int f0 = (int)(((int64_t)i - gd.klo) & (P - 1));
-    auto first_of = [&](int r) { return (f0 + r * NB) & (P - 1); };
-    C xg[16];
-    {
-        const C *gtw = reinterpret_cast<const C *>(twbase + gd.gtw_off) + (int64_t)c * B;
+    load_twl<C, P, NT>(twl, static_cast<const C *>(kd->twl));
+    // spectrum samples of every unit of the group (and pair partners),
+    // staged in LDS once, eight units per batch of loads
+    if (tid < B) {
+        const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, 0x7ffffff0u);
+        for (int u0 = 0; u0 < nunits; u0 += 8) {
+            R ka[8], kb[8];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            int fr = first_of(r);
-            xg[r] = fr < B ? cmul(xs[fr], gtw[fr]) : mk<C>(0, 0);
+            for (int j = 0; j < 8; ++j) {
+                const int u = u0 + j < nunits ? u0 + j : nunits - 1;
+                const SegUnit su = cload(units + gd.unit0 + u);
+                ka[j] = bload(ktab, kr, (uint32_t)((su.ka + tid) * (int64_t)sizeof(R)));
+                if constexpr (PAIR)
+                    kb[j] = su.sb >= 0 ? bload(ktab, kr, (uint32_t)((su.kb + tid) * (int64_t)sizeof(R))) : (R)0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (u0 + j < nunits) {
+                    kls[(u0 + j) * B + tid] = ka[j];
+                    if constexpr (PAIR) kls[nunits * B + (u0 + j) * B + tid] = kb[j];
+                }
+            }
         }
     }
-    // spectrum samples of every unit of the group, staged in LDS once
-    for (int t = tid; t < nunits * B; t += NT) {
-        const int u = t / B, k = t % B;
-        kls[u * B + k] = ktab[us[u].ka + k];
-        if constexpr (PAIR) kls[nunits * B + u * B + k] = us[u].sb >= 0 ? ktab[us[u].kb + k] : (R)0;
-    }
+    lds_barrier();
+    C xg[16];
     // band bin read for position r; bins outside the band read bin 0, which
     // is harmless because xg[r] is zero there.  The phase i^cph of the
     // wavelet's spectrum is common to every unit and folded into xg.
     int fro[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        int fr = first_of(r);
+        const int fr = first_of(r);
         fro[r] = fr < B ? fr : 0;
-        xg[r] = mul_i_pow(xg[r], cph);
+        xg[r] = mul_i_pow(cmul(xs[fro[r]], gv[r]), cph);
     }
     lds_barrier();  // xs (in buf) is no longer read
     const int64_t ob = (int64_t)w.seg * gd.V - gd.Tg;
     const uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
     for (int u = 0; u < nunits; ++u) {
-        // unit fields are uniform; say so, so that the store descriptors
-        // live in scalar registers
-        const int sa = __builtin_amdgcn_readfirstlane(us[u].sa);
-        const int sb = __builtin_amdgcn_readfirstlane(us[u].sb);
+        // unit fields come from scalar loads, so the store descriptors live
+        // in scalar registers
+        const SegUnit su = cload(units + gd.unit0 + u);
+        const int sa = su.sa, sb = su.sb;
         C v[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
