@@ -476,8 +476,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const int nscale = kd->nscale, cph = kd->cph;
     const int32_t *__restrict__ scale_ids = kd->scale_ids;
     const R *__restrict__ ktab = static_cast<const R *>(kd->ktab);
-    load_twl<C, L, NT>(twl, static_cast<const C *>(kd->twl));
-    // FP64 forward twiddles: the LDS table for FP64 plans, else evaluated
+    // pass twiddles in LDS: needed by the FP64 forward of FP64 plans (FP32
+    // plans evaluate those, and load the table after the forward)
+    if constexpr (sizeof(R) == 8) load_twl<C, L, NT>(twl, static_cast<const C *>(kd->twl));
     const double2 *twF = reinterpret_cast<const double2 *>(twl);
     const int tid = threadIdx.x;
     constexpr int SEGS = PAIR ? 2 : 1;  // segments per inverse column
@@ -548,6 +549,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
                 for (int r = 0; r < 16; ++r) Xr[r] = to_c<C>(mul_i_pow(bufF[z * LD + lidx(ii + r * NB)], cph));
             }
         }
+        lds_barrier();
+    }
+    if constexpr (sizeof(R) == 4) {
+        load_twl<C, L, NT>(twl, static_cast<const C *>(kd->twl));
         lds_barrier();
     }
     // spectrum samples through buffer loads: flat loads would also count as

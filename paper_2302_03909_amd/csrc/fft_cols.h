@@ -29,18 +29,25 @@ constexpr int twl_len(int P) { return twl_off(P, num_passes(P)) > 0 ? twl_off(P,
 // sincospi and the other powers formed by products.  The FP64 segment
 // transforms of FP32 plans use the latter: a table read from global memory
 // in the middle of a pass would expose its full latency.
-template <typename C, int R, int NS, bool TWCALC>
-__device__ __forceinline__ void twiddles(const C *tab, int k, C (&w)[R]) {
+template <typename C, int R, int NS, int SIGN, bool TWCALC>
+__device__ __forceinline__ void apply_twiddles(const C *tab, int k, C (&v)[R]) {
     if constexpr (TWCALC) {
         static_assert(sizeof(decltype(C::x)) == 8, "computed twiddles are FP64");
         double sn, cs;
         sincospi((double)(2 * k) / (double)(R * NS), &sn, &cs);
-        w[1] = mk<C>(cs, sn);
+        const C w1 = mk<C>(cs, sn);
+        C w = w1;  // w^r along the chain: two twiddles live, not R - 1
 #pragma unroll
-        for (int r = 2; r < R; ++r) w[r] = cmul(w[r - 1], w[1]);
+        for (int r = 1; r < R; ++r) {
+            if (r > 1) w = cmul(w, w1);
+            v[r] = SIGN > 0 ? cmul(v[r], w) : cmulc(v[r], w);
+        }
     } else {
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[r] = tab[k + (r - 1) * NS];
+        for (int r = 1; r < R; ++r) {
+            const C w = tab[k + (r - 1) * NS];
+            v[r] = SIGN > 0 ? cmul(v[r], w) : cmulc(v[r], w);
+        }
     }
 }
 
@@ -68,12 +75,7 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
         if (NB % NT == 0 || gb < NB) {
             int c = gb / (P / R), i = gb % (P / R);
             int k = i % NS;
-            if constexpr (NS > 1) {
-                C w[R];
-                twiddles<C, R, NS, TWCALC>(twl + twl_off(P, PASS), k, w);
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = SIGN > 0 ? cmul(v[q][r], w[r]) : cmulc(v[q][r], w[r]);
-            }
+            if constexpr (NS > 1) apply_twiddles<C, R, NS, SIGN, TWCALC>(twl + twl_off(P, PASS), k, v[q]);
             dftR<R, SIGN>(v[q]);
             int base = (i - k) * R + k;
 #pragma unroll
@@ -114,12 +116,7 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
         int gb = tid + q * NT;
         if (NB % NT == 0 || gb < NB) {
             int c = POSFAST ? gb / (P / R) : gb % NCOL, i = POSFAST ? gb % (P / R) : gb / NCOL;
-            if constexpr (NS > 1) {
-                C w[R];
-                twiddles<C, R, NS, TWCALC>(twl + twl_off(P, PASS), i, w);
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = SIGN > 0 ? cmul(v[q][r], w[r]) : cmulc(v[q][r], w[r]);
-            }
+            if constexpr (NS > 1) apply_twiddles<C, R, NS, SIGN, TWCALC>(twl + twl_off(P, PASS), i, v[q]);
             dftR<R, SIGN>(v[q]);
 #pragma unroll
             for (int r = 0; r < R; ++r) emit(c, i + r * NS, v[q][r]);
@@ -164,10 +161,29 @@ __device__ __forceinline__ void cols_fft_after0(C *buf, const C *twl, F &emit) {
     cols_pass_last<C, P, NCOL, NT, LD, SIGN, SYNC_LAST, F, false, POSFAST>(buf, twl, emit);
 }
 
-// copy a per-pass twiddle table from global memory into LDS
+// copy a per-pass twiddle table from global memory into LDS: every load is
+// issued before the first LDS write, through the global address space (a
+// flat load would also count as an LDS operation, so later LDS waits would
+// wait for it too)
 template <typename C, int P, int NT>
 __device__ __forceinline__ void load_twl(C *twl_s, const C *__restrict__ twl_g) {
-    for (int j = threadIdx.x; j < twl_len(P); j += NT) twl_s[j] = twl_g[j];
+    constexpr int N = twl_len(P), K = (N + NT - 1) / NT;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const __attribute__((address_space(1))) C *g = (const __attribute__((address_space(1))) C *)twl_g;
+#else
+    const C *g = twl_g;  // host pass of the kernel templates; never executed
+#endif
+    C v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int j = threadIdx.x + k * NT;
+        if (N % NT == 0 || j < N) v[k] = g[j];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int j = threadIdx.x + k * NT;
+        if (N % NT == 0 || j < N) twl_s[j] = v[k];
+    }
 }
 
 }  // namespace cwt
