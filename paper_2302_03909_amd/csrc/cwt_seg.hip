@@ -370,9 +370,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             for (int j = 0; j < 8; ++j) {
                 const int u = u0 + j < nunits ? u0 + j : nunits - 1;
                 const SegUnit su = cload(units + gd.unit0 + u);
-                ka[j] = bload(ktab, kr, (uint32_t)((su.ka + tid) * (int64_t)sizeof(R)));
+                ka[j] = bload(ktab, kr, (uint32_t)((uni(su.ka) + tid) * (int64_t)sizeof(R)));
                 if constexpr (PAIR)
-                    kb[j] = su.sb >= 0 ? bload(ktab, kr, (uint32_t)((su.kb + tid) * (int64_t)sizeof(R))) : (R)0;
+                    kb[j] = __builtin_amdgcn_readfirstlane(su.sb) >= 0
+                                ? bload(ktab, kr, (uint32_t)((uni(su.kb) + tid) * (int64_t)sizeof(R)))
+                                : (R)0;
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -399,10 +401,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const int64_t ob = (int64_t)w.seg * gd.V - gd.Tg;
     const uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
     for (int u = 0; u < nunits; ++u) {
-        // unit fields come from scalar loads, so the store descriptors live
-        // in scalar registers
+        // unit fields are uniform; say so, so that the store descriptors
+        // live in scalar registers (no waterfall loop around the stores)
         const SegUnit su = cload(units + gd.unit0 + u);
-        const int sa = su.sa, sb = su.sb;
+        const int sa = __builtin_amdgcn_readfirstlane(su.sa);
+        const int sb = __builtin_amdgcn_readfirstlane(su.sb);
         C v[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
