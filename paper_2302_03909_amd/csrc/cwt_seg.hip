@@ -13,8 +13,9 @@
 // Larger scales (the spectrum at length L occupies B <= P << L bins): the
 // segment spectrum is needed only on the band [klo, klo + B).  With L = P Q:
 //   forward  X[m] = sum_q w_L^{-q m} DFT_P(x[q + Q p])[m mod P]
-//            (seg_forward_kernel: 16 columns q per iteration, FP64 sums,
-//             partial sums per column chunk, then seg_reduce_kernel)
+//            (seg_forward_kernel: 16 real columns q per iteration, packed
+//             two per complex P-point FFT, FP64 sums, partial sums per
+//             column chunk, then seg_reduce_kernel)
 //   inverse  W[r + Q p] = DFT_P^{-1}( Y[m] w_L^{m r} )[p],  m = k mod P
 //            (seg_inverse_kernel: 16 consecutive columns r per workgroup, so
 //             the last FFT pass stores 16-element runs straight to HBM).
@@ -159,11 +160,12 @@ __device__ __forceinline__ Resolved resolve(const BatchArgs &a) {
 template <typename R, int P, int NT>
 __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
     using C = cplx_t<R>;
-    constexpr int G = 16;
+    constexpr int G = 16;       // real columns per iteration
+    constexpr int GC = G / 2;   // complex columns: real columns 2z and 2z+1 share column z
     constexpr int LD = lds_len(P);
     constexpr int E = G * P / NT;  // samples per thread per iteration
     static_assert(NT >= P && (G * P) % NT == 0, "launch shape");
-    __shared__ C buf[G * LD];
+    __shared__ C buf[GC * LD];
     __shared__ C twl[twl_len(P)];
     const Resolved rv = resolve(a);
     const KeyDesc *kd = &rv.kd;
@@ -180,14 +182,15 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
     const int tid = threadIdx.x;
     const int B = gd.B;
     // bins of this thread: step w_L^{-m}, w_L^{-2m} (two interleaved
-    // accumulation chains over the 16 columns), w_L^{-16 m}, and the chunk's
-    // first-column factor base0 = w_L^{-q0 m}
+    // accumulation chains, even and odd columns), w_L^{-16 m}, and the
+    // chunk's first-column factor base0 = w_L^{-q0 m}
     const int64_t q0 = (int64_t)w.idx * gd.iters * G;
     double2 acc = make_double2(0.0, 0.0), base0 = acc, base = acc, step = acc, step2 = acc, w16 = acc;
-    int kap = 0;
+    int kap = 0, kam = 0;
     if (tid < B) {
         int64_t mm = (gd.klo + tid) & (L - 1);
         kap = (int)(mm & (P - 1));
+        kam = (P - kap) & (P - 1);
         double2 s1 = w23(whi, wlo, mm << sh);
         step = make_double2(s1.x, -s1.y);
         step2 = cmul(step, step);
@@ -226,27 +229,36 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
     R xn[E];
     load_step(0, xn);
     auto emit = [&](int c, int p, C v) { buf[c * LD + lidx(p)] = v; };
+    R *bufr = reinterpret_cast<R *>(buf);
     for (int t = 0; t < total; ++t) {
+        // real column g of row p -> component g & 1 of complex column g / 2
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            int idx = tid + e * NT;
-            buf[(idx % G) * LD + lidx(idx / G)] = mk<C>(xn[e], (decltype(C::x))0);
+            const int idx = tid + e * NT, g = idx % G;
+            bufr[2 * ((g >> 1) * LD + lidx(idx / G)) + (g & 1)] = xn[e];
         }
         if (t + 1 < total) load_step(t + 1, xn);
         lds_barrier();
-        cols_fft<C, P, G, NT, LD, -1, true>(buf, twl, emit);
+        cols_fft<C, P, GC, NT, LD, -1, true>(buf, twl, emit);
         lds_barrier();
         if (tid < B) {
+            // with Z = DFT(x_{2z} + i x_{2z+1}):  DFT(x_{2z})[k] = (Z[k] + conj Z[-k]) / 2
+            // and DFT(x_{2z+1})[k] = (Z[k] - conj Z[-k]) / 2i; the 1/2 is applied
+            // once per step
             double2 b0 = base, b1 = cmul(base, step);
             double2 a0 = make_double2(0.0, 0.0), a1 = a0;
 #pragma unroll
-            for (int g = 0; g < G; g += 2) {
-                a0 = cadd(a0, cmul(to_d(buf[g * LD + lidx(kap)]), b0));
-                a1 = cadd(a1, cmul(to_d(buf[(g + 1) * LD + lidx(kap)]), b1));
+            for (int z = 0; z < GC; ++z) {
+                const double2 zk = to_d(buf[z * LD + lidx(kap)]), zm = to_d(buf[z * LD + lidx(kam)]);
+                const double2 ye = make_double2(zk.x + zm.x, zk.y - zm.y);
+                const double2 yo = make_double2(zk.y + zm.y, zm.x - zk.x);
+                a0 = cadd(a0, cmul(ye, b0));
+                a1 = cadd(a1, cmul(yo, b1));
                 b0 = cmul(b0, step2);
                 b1 = cmul(b1, step2);
             }
-            acc = cadd(acc, cadd(a0, a1));
+            const double2 s = cadd(a0, a1);
+            acc = cadd(acc, make_double2(0.5 * s.x, 0.5 * s.y));
             base = cmul(base, w16);
             if (t % gd.iters == gd.iters - 1) {  // segment complete
                 const int64_t sg = w.seg + t / gd.iters;
