@@ -181,11 +181,12 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
     const int sh = 23 - gd.lgL;
     const int tid = threadIdx.x;
     const int B = gd.B;
-    // bins of this thread: step w_L^{-m}, w_L^{-2m} (two interleaved
-    // accumulation chains, even and odd columns), w_L^{-16 m}, and the
-    // chunk's first-column factor base0 = w_L^{-q0 m}
+    // bins of this thread: step = w_L^{-m}, step2 = w_L^{-2m}, w14 =
+    // w_L^{-14 m}, w16 = w_L^{-16 m}, and the chunk's first-column factor
+    // base0 = w_L^{-q0 m}
     const int64_t q0 = (int64_t)w.idx * gd.iters * G;
-    double2 acc = make_double2(0.0, 0.0), base0 = acc, base = acc, step = acc, step2 = acc, w16 = acc;
+    double2 acc = make_double2(0.0, 0.0), base0 = acc, base = acc, step = acc, step2 = acc, w14 = acc, w16 = acc;
+    double cc2 = 0.0;  // 2 cos(2 theta), theta = 2 pi m / L
     int kap = 0, kam = 0;
     if (tid < B) {
         int64_t mm = (gd.klo + tid) & (L - 1);
@@ -194,6 +195,9 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
         double2 s1 = w23(whi, wlo, mm << sh);
         step = make_double2(s1.x, -s1.y);
         step2 = cmul(step, step);
+        cc2 = 2.0 * step2.x;
+        double2 s14 = w23(whi, wlo, ((14 * mm) & (L - 1)) << sh);
+        w14 = make_double2(s14.x, -s14.y);
         double2 s16 = w23(whi, wlo, ((16 * mm) & (L - 1)) << sh);
         w16 = make_double2(s16.x, -s16.y);
         double2 b = w23(whi, wlo, ((q0 * mm) & (L - 1)) << sh);
@@ -242,23 +246,30 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
         cols_fft<C, P, GC, NT, LD, -1, true>(buf, twl, emit);
         lds_barrier();
         if (tid < B) {
-            // with Z = DFT(x_{2z} + i x_{2z+1}):  DFT(x_{2z})[k] = (Z[k] + conj Z[-k]) / 2
-            // and DFT(x_{2z+1})[k] = (Z[k] - conj Z[-k]) / 2i; the 1/2 is applied
-            // once per step
-            double2 b0 = base, b1 = cmul(base, step);
-            double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+            // With Z = DFT(x_{2z} + i x_{2z+1}):  DFT(x_{2z})[k] = (Z[k] + conj Z[-k]) / 2
+            // and DFT(x_{2z+1})[k] = (Z[k] - conj Z[-k]) / 2i (the 1/2 is applied
+            // once per step).  The sum over the 16 columns,
+            //   sum_z ye_z e^{-2 i theta z} + e^{-i theta} sum_z yo_z e^{-2 i theta z},
+            // is taken by two Goertzel recurrences at angle 2 theta (even and
+            // odd columns): s_z = y_z + 2 cos(2 theta) s_{z-1} - s_{z-2}, and
+            //   sum_{z<8} y_z e^{-2 i theta z} = e^{-14 i theta} (s_7 - e^{-2 i theta} s_6).
+            // Eight terms per recurrence keep its rounding at a few tens of ulps.
+            double2 e1 = make_double2(0.0, 0.0), e2 = e1, o1 = e1, o2 = e1;
 #pragma unroll
             for (int z = 0; z < GC; ++z) {
                 const double2 zk = to_d(buf[z * LD + lidx(kap)]), zm = to_d(buf[z * LD + lidx(kam)]);
                 const double2 ye = make_double2(zk.x + zm.x, zk.y - zm.y);
                 const double2 yo = make_double2(zk.y + zm.y, zm.x - zk.x);
-                a0 = cadd(a0, cmul(ye, b0));
-                a1 = cadd(a1, cmul(yo, b1));
-                b0 = cmul(b0, step2);
-                b1 = cmul(b1, step2);
+                const double2 en = make_double2(fma(cc2, e1.x, ye.x - e2.x), fma(cc2, e1.y, ye.y - e2.y));
+                const double2 on = make_double2(fma(cc2, o1.x, yo.x - o2.x), fma(cc2, o1.y, yo.y - o2.y));
+                e2 = e1;
+                e1 = en;
+                o2 = o1;
+                o1 = on;
             }
-            const double2 s = cadd(a0, a1);
-            acc = cadd(acc, make_double2(0.5 * s.x, 0.5 * s.y));
+            const double2 te = csub(e1, cmul(step2, e2)), tq = csub(o1, cmul(step2, o2));
+            const double2 sum = cmul(cmul(base, w14), cadd(te, cmul(step, tq)));
+            acc = cadd(acc, make_double2(0.5 * sum.x, 0.5 * sum.y));
             base = cmul(base, w16);
             if (t % gd.iters == gd.iters - 1) {  // segment complete
                 const int64_t sg = w.seg + t / gd.iters;
