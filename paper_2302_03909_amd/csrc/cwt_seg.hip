@@ -287,7 +287,6 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
 // workgroup, 16 lanes per bin, fixed summation order; w.pad consecutive
 // segments per workgroup
 __global__ __launch_bounds__(256) void seg_reduce_kernel(const BatchArgs args) {
-    __shared__ double2 part[256];
     const Resolved rv = resolve(args);
     char *__restrict__ ws = rv.bi.ws;
     const SegWork w = cload(rv.kd.work + rv.local);
@@ -300,14 +299,14 @@ __global__ __launch_bounds__(256) void seg_reduce_kernel(const BatchArgs args) {
         double2 a = make_double2(0.0, 0.0);
         if (k < gd.B)
             for (int c = lane; c < gd.nchunk; c += 16) a = cadd(a, Xp[(sg * gd.nchunk + c) * gd.B + k]);
-        part[threadIdx.x] = a;
-        lds_barrier();
+        // the 16 lanes of a bin are consecutive lanes of one wave: fixed-order
+        // butterfly reduction across them, no LDS
+#pragma unroll
         for (int st = 8; st > 0; st >>= 1) {
-            if (lane < st) part[threadIdx.x] = cadd(part[threadIdx.x], part[threadIdx.x + st]);
-            lds_barrier();
+            a.x += __shfl_xor(a.x, st, 16);
+            a.y += __shfl_xor(a.y, st, 16);
         }
-        if (lane == 0 && k < gd.B) X[sg * gd.B + k] = part[threadIdx.x];
-        lds_barrier();
+        if (lane == 0 && k < gd.B) X[sg * gd.B + k] = a;
     }
 }
 
