@@ -312,23 +312,36 @@ __global__ __launch_bounds__(256) void spl_tap_kernel(int64_t N, int64_t E, cons
     const int F = fx[0];
     const int bad = fx[1];
     if (active) {
-        // rows in batches of 8: S rows m0..m0+7 need H rows i - 2 .. i + 2,
-        // i.e. the 12 rows starting at i0 - nd + m0 - 2, loaded together
-        const int ch = 8 * ((rowsS + 8 * ngrp - 1) / (8 * ngrp));
+        // rows in batches of BR: S rows m0..m0+BR-1 need H rows i - 2 .. i + 2,
+        // i.e. the BR + 4 rows starting at i0 - nd + m0 - 2, loaded together
+        // (one memory latency per batch)
+        constexpr int BR = 16;
+        const int ch = BR * ((rowsS + BR * ngrp - 1) / (BR * ngrp));
         const int mb = g * ch, me = min(rowsS, mb + ch);
-        const u128 *hc = H + (E + w.r0 + r - 2);  // H row rho of this column: hc[rho delta]
-        for (int m0 = mb; m0 < me; m0 += 8) {
-            u128 h[12];
+        // H row rho of this column: H[E + r0 + r - 2 + rho delta], read with
+        // raw buffer loads and 32-bit byte offsets (H holds N + 2E < 2^27 values)
+        const __amdgpu_buffer_rsrc_t hr = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<u128 *>(H), 0, (int)__builtin_amdgcn_readfirstlane((uint32_t)((N + 2 * E) * 16)), 0x00020000);
+        const uint32_t hb = (uint32_t)((E + w.r0 + r - 2) * 16), hs = (uint32_t)(delta * 16);
+        const int32_t rho0 = (int32_t)(w.i0 - nd - 2), rmax = (int32_t)rho_max;
+        for (int m0 = mb; m0 < me; m0 += BR) {
+            u128 h[BR + 4];
 #pragma unroll
-            for (int q = 0; q < 12; ++q) {
-                const int64_t rho = min(w.i0 - nd + m0 - 2 + q, rho_max);
-                h[q] = hc[rho * delta];
+            for (int q = 0; q < BR + 4; ++q) {
+                const int32_t rho = min(rho0 + m0 + q, rmax);
+                h[q] = __builtin_bit_cast(u128, __builtin_amdgcn_raw_buffer_load_b128(hr, hb + (uint32_t)rho * hs, 0, 0));
+            }
+            // S = fourth difference at spacing delta, taken as four rounds of
+            // first differences over the BR + 4 rows (subtractions modulo
+            // 2^128 instead of the weighted sum's multiplies and adds)
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+#pragma unroll
+                for (int q = 0; q < BR + 3 - d; ++q) h[q] = h[q + 1] - h[q];
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const u128 sv = h[k] + h[k + 4] + 6 * h[k + 2] - 4 * (h[k + 1] + h[k + 3]);
-                if (m0 + k < me) S[stile_idx(m0 + k, R, r)] = i128_to_double(sv);
-            }
+            for (int k = 0; k < BR; ++k)
+                if (m0 + k < me) S[stile_idx(m0 + k, R, r)] = i128_to_double(h[k]);
         }
     }
     __syncthreads();

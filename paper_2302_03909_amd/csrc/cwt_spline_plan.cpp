@@ -203,6 +203,9 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
     if (p.N + 2 * E > (int64_t(1) << 31)) fail(CWT_EUNSUPPORTED, "spline method: signal plus wavelet support above 2^31");
     p.spl_E = E;
     p.spl_len = p.N + 2 * E;
+    // the tap kernel addresses the running sums with 32-bit byte offsets
+    if (p.spl_len * 16 >= (int64_t(1) << 31))
+        fail(CWT_EUNSUPPORTED, "spline method: signal plus wavelet support above 2^27 samples");
     // fixed-point bits: |5040 beta7 * box^4 q| <= 5040 delta^4 max|q| must stay below 2^127
     const int qb = (int)std::floor(127.0 - std::log2(5040.0) - 4.0 * std::log2((double)delta_max)) - 1;
     p.spl_qbits = std::min(62, qb);
