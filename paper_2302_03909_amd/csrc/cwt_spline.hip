@@ -36,6 +36,7 @@
 
 #include "../../include/cwt.h"
 #include "cwt_internal.h"
+#include "fft_device.h"
 
 namespace cwt {
 
@@ -109,10 +110,10 @@ __global__ __launch_bounds__(kSNT) void spl_maxabs_kernel(const R *__restrict__ 
         if (i < N) m = nmax(m, fabs((double)f[i]));
     }
     red[threadIdx.x] = m;
-    __syncthreads();
+    lds_barrier();
     for (int s = kSNT / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) red[threadIdx.x] = nmax(red[threadIdx.x], red[threadIdx.x + s]);
-        __syncthreads();
+        lds_barrier();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
@@ -124,10 +125,10 @@ __global__ __launch_bounds__(kSNT) void spl_exponent_kernel(const double *__rest
     double m = 0.0;
     for (int k = threadIdx.x; k < nb; k += kSNT) m = nmax(m, part[k]);
     red[threadIdx.x] = m;
-    __syncthreads();
+    lds_barrier();
     for (int s = kSNT / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) red[threadIdx.x] = nmax(red[threadIdx.x], red[threadIdx.x + s]);
-        __syncthreads();
+        lds_barrier();
     }
     if (threadIdx.x == 0) {
         const double b = 3.0 * red[0];
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
     const int64_t l0 = (int64_t)blockIdx.x * kSB;
     const int64_t x0 = l0 - E;
     for (int k = tid; k < FS; k += kSNT) fs[k] = sig_ext(f, N, periodic, x0 - 3 - kFIR + k);
-    __syncthreads();
+    lds_barrier();
     // spline coefficients c = (beta3)^{-1} f (Eq. interp_coeffs) as the
     // symmetric FIR sqrt(3) sum_t z1^|t| f[x - t], then fixed point
     for (int k = tid; k < QS; k += kSNT) {
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
         c *= 1.7320508075688772935;
         qs[k] = bad ? 0ll : (long long)rint(ldexp(c, F));
     }
-    __syncthreads();
+    lds_barrier();
     // 5040 beta7 * q at this thread's positions, local running sums
     Sums loc = {0, 0, 0, 0};
     i128 q7v[kSPT];
@@ -204,15 +205,15 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
     // inclusive scan of the thread states (each covers kSPT positions)
     Sums inc = loc;
     scan[tid] = inc;
-    __syncthreads();
+    lds_barrier();
     for (int d = 1; d < kSNT; d <<= 1) {
         Sums left;
         const bool has = tid >= d;
         if (has) left = scan[tid - d];
-        __syncthreads();
+        lds_barrier();
         if (has) inc = sums_then(left, inc, (uint64_t)(d * kSPT));
         scan[tid] = inc;
-        __syncthreads();
+        lds_barrier();
     }
     if (!FINAL) {
         if (tid == kSNT - 1) state[blockIdx.x] = inc;
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(kCNT) void spl_carry_kernel(const Sums *__restrict_
     }
     sc[tid] = acc;
     ln[tid] = len;
-    __syncthreads();
+    lds_barrier();
     for (int d = 1; d < kCNT; d <<= 1) {
         Sums left;
         int64_t llen = 0;
@@ -258,14 +259,14 @@ __global__ __launch_bounds__(kCNT) void spl_carry_kernel(const Sums *__restrict_
             left = sc[tid - d];
             llen = ln[tid - d];
         }
-        __syncthreads();
+        lds_barrier();
         if (has) {
             acc = sums_then(left, acc, (uint64_t)len);
             len += llen;
         }
         sc[tid] = acc;
         ln[tid] = len;
-        __syncthreads();
+        lds_barrier();
     }
     Sums st = {0, 0, 0, 0};
     if (tid > 0) st = sc[tid - 1];
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(256) void spl_tap_kernel(int64_t N, int64_t E, cons
                 if (m0 + k < me) S[stile_idx(m0 + k, R, r)] = i128_to_double(h[k]);
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (!active) return;
     const int u0 = g * 16;
     // rows u0 + m for m in [16 q, 16 q + 16) start at stile_idx(u0 + 16 q) and
