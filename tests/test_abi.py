@@ -123,3 +123,48 @@ def test_batch_workspace_layout_host_only():
     assert wb > total
     assert cwt.batch_workspace_bytes(plans[:1]) <= wb
     assert cwt.batch_workspace_bytes([]) == 0
+
+
+def _groups(plan):
+    """(kind, L, P, B, Tg, V, nseg, nchunk, iters, scales) of every segment
+    group in a plan's summary."""
+    out = []
+    for line in plan.describe().splitlines():
+        parts = line.split()
+        if parts and parts[0] in ("local", "band"):
+            kv = dict(x.split("=") for x in parts[1:])
+            out.append((parts[0],) + tuple(int(kv[k]) for k in
+                                           ("L", "P", "B", "Tg", "V", "nseg", "nchunk", "iters", "scales")))
+    return out
+
+
+def test_segment_groups_of_the_headline_plan():
+    scales = np.geomspace(2, 2 ** 16, 128)
+    p = cwt.Plan(1 << 22, "zero", "morlet", scales, param=6.0, precision="fp32", host_only=True)
+    g = _groups(p)
+    local = [x for x in g if x[0] == "local"]
+    band = [x for x in g if x[0] == "band"]
+    # long FP32 signal: every local scale in one group of 2048-sample segments
+    assert len(local) == 1 and local[0][1] == 2048
+    assert sum(x[9] for x in g) == 128
+    for kind, L, P, B, Tg, V, nseg, nchunk, iters, s in g:
+        assert Tg % 16 == 0 and V == L - 2 * Tg and V > 0
+        assert nseg * V >= (1 << 22) > (nseg - 1) * V
+        if kind == "band":
+            assert B <= P <= L // 16
+            # each forward chunk reads at least two 16-column blocks
+            assert iters * nchunk * 16 == L // P
+            assert nchunk == 1 or iters >= 2
+
+
+def test_segment_groups_not_merged_for_fp64_or_short_signals():
+    scales = np.geomspace(2, 2 ** 12, 48)
+    p = cwt.Plan(1 << 20, "zero", "morlet", scales, param=6.0, precision="fp64", host_only=True)
+    local = [x for x in _groups(p) if x[0] == "local"]
+    assert len(local) > 1 and len({x[1] for x in local}) == len(local)
+    # segments of at least 256 samples for a long signal
+    assert min(x[1] for x in local) >= 256
+    # a short signal keeps single segments just long enough for it
+    q = cwt.Plan(700, "zero", "mexhat", [2.0, 8.0, 30.0], precision="fp32", host_only=True)
+    for x in _groups(q):
+        assert x[1] <= 2048 and x[6] >= 1
