@@ -51,7 +51,11 @@ template <typename C> __device__ __forceinline__ C mul_i_pow(C a, int q) {
 // Raw buffer accesses (vector memory instructions) with the descriptor's
 // bounds check: an access whose byte offset lies beyond num_records is
 // dropped (store) or returns zero (load), so predicated lanes need no branch
-// and every wave issues the same number of memory instructions.
+// and every wave issues the same number of memory instructions.  The stores
+// (the transform's output, written once and far larger than the caches)
+// carry the non-temporal hint, so they stream to HBM instead of displacing
+// the signal, spectra and tables the other kernels read.
+constexpr int kStoreNT = 2;  // cache-policy operand: nt
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr uint32_t kOOB = 0x80000000u;  // beyond every descriptor used here (< 2 GiB)
@@ -59,16 +63,16 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
 }
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, kStoreNT);
 }
 __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kStoreNT);
 }
 __device__ __forceinline__ void bstore(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kStoreNT);
 }
 __device__ __forceinline__ void bstore(double2 v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, kStoreNT);
 }
 __device__ __forceinline__ float bload(const float *, __amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
