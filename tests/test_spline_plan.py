@@ -21,7 +21,7 @@ def test_hstar_matches_oracle(wav, par):
 
 
 def test_hstar_values():
-    # h* of the spec wavelets at AE_M = 5e-4 (three digits; the same
+    # h* of the benchmark wavelets at AE_M = 5e-4 (three digits; the same
     # criterion reproduces the three h of Table 3 for GDW, CW-GDW and MW)
     for wav, par, h in [("mexhat", None, 0.3722), ("morlet", 6.0, 0.1167), ("dog", 4.0, 0.3010)]:
         assert abs(host_plan(1024, wav, par, [3.0]).spline_hstar() - h) < 5e-4
