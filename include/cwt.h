@@ -171,6 +171,11 @@ size_t cwt_footprint_bytes(cwt_plan_t plan);
  * Errors: CWT_EINVAL for a NULL plan/signal/out, a NULL workspace when one is
  * needed, or a pointer not aligned to its element size; CWT_EDEVICE when a
  * launch fails.  NaN/Inf in the signal propagate; they are not checked.
+ * The call only enqueues kernels and event dependencies (no allocation, no
+ * host copy), so it may be captured into a HIP graph.  Part of the work may
+ * run on a second stream of the calling thread, forked from `stream` and
+ * joined back into it before the call returns.  The plan is only read, so
+ * calls on different streams with different workspaces may overlap.
  */
 int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace,
              void *stream);
@@ -180,7 +185,9 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace,
  * (lengths, scales, wavelets, boundaries and precisions may differ), in one
  * enqueue on `stream`.  signals[i], outs[i] as for cwt_exec with plans[i].
  * workspace: at least cwt_batch_workspace_bytes(plans, n) bytes.  Every
- * result is bit-identical to cwt_exec of the same plan and signal.
+ * result is bit-identical to cwt_exec of the same plan and signal.  The
+ * launch tables are copied from host memory at call time, so this call must
+ * not be captured into a HIP graph.
  */
 size_t cwt_batch_workspace_bytes(const cwt_plan_t *plans, int32_t n);
 int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals,
