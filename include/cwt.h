@@ -174,8 +174,10 @@ size_t cwt_footprint_bytes(cwt_plan_t plan);
  * The call only enqueues kernels and event dependencies (no allocation, no
  * host copy), so it may be captured into a HIP graph.  Part of the work may
  * run on a second stream of the calling thread, forked from `stream` and
- * joined back into it before the call returns.  The plan is only read, so
- * calls on different streams with different workspaces may overlap.
+ * joined back into it before the call returns; that stream and its two
+ * events are created on the thread's first call, so run one call before
+ * capturing.  The plan is only read, so calls on different streams with
+ * different workspaces may overlap.
  */
 int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace,
              void *stream);

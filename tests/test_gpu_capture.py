@@ -1,0 +1,50 @@
+"""cwt_exec under HIP stream capture.  The segmented FFT method forks its
+local-group kernels onto a second stream and joins them back; captured into a
+graph, that must replay the transform exactly.  The graph is replayed several
+times with eager work of another plan and synchronisations in between, and
+every replay is compared with the eager result."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("wavelet,param", [("morlet", 6.0), ("dog", 2.0)])
+def test_exec_graph_replays_match_eager(torch_cuda, wavelet, param):
+    import paper_2302_03909_amd as cwt
+    torch = torch_cuda
+    n = 1 << 17
+    scales = synth.log_scales(2.0, 2.0 ** 12, 24)
+    plan = cwt.Plan(n, "zero", wavelet, scales, param=param, precision="fp32")
+    paths = set(plan.scale_path().tolist())
+    assert paths == {cwt.PATH_LOCAL, cwt.PATH_COLUMN}, "the plan must take both kernel chains"
+    f = torch.as_tensor(synth.lognormal_field(n, seed=11).astype(np.float32), device="cuda")
+    ws = plan.empty_workspace()
+    ref = plan(f, plan.empty_output(), ws)  # eager (also creates the second stream before capture)
+    torch.cuda.synchronize()
+    # another plan's eager work between replays
+    other = cwt.Plan(5000, "periodic", "mexhat", [2.0, 17.0, 90.0], precision="fp32")
+    g_in = torch.as_tensor(synth.tones_noise(5000).astype(np.float32), device="cuda")
+    g_out = other.empty_output()
+    out = plan.empty_output()
+    side = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        plan(f, out, ws)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        other(g_in, g_out, other.empty_workspace())
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {rep} differs from the eager transform"
