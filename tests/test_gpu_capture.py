@@ -48,3 +48,23 @@ def test_exec_graph_replays_match_eager(torch_cuda, wavelet, param):
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, ref), f"replay {rep} differs from the eager transform"
+
+
+@pytest.mark.parametrize("wavelet,param", [("morlet", 6.0), ("dog", 2.0)])
+def test_two_stream_execution_equals_serialized(torch_cuda, wavelet, param):
+    # with launch timing on, every launch stays on the caller's stream; the
+    # two kernel chains write disjoint rows, so the results are bit-identical
+    import paper_2302_03909_amd as cwt
+    torch = torch_cuda
+    n = 200003
+    scales = synth.log_scales(2.0, 2.0 ** 13, 40)
+    plan = cwt.Plan(n, "zero", wavelet, scales, param=param, precision="fp32")
+    f = torch.as_tensor(synth.lognormal_field(n, seed=12).astype(np.float32), device="cuda")
+    ws = plan.empty_workspace()
+    a = plan(f, plan.empty_output(), ws)
+    plan.timing(True)
+    b = plan(f, plan.empty_output(), ws)
+    plan.timing(False)
+    plan.timing_read()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
