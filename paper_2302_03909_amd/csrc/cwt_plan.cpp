@@ -529,6 +529,32 @@ static hipStream_t plan_stream() {
     return st;
 }
 
+// Shortest single segment that holds the whole signal for a wavelet of
+// radius T.  Zero boundary: the signal at offset 0 followed by zeros; the
+// circular correlation over L >= N + T + 1 samples then reads, for every
+// output b in [0, N), the true neighbours f[b + t], |t| <= T, or zeros (the
+// left neighbours of the first outputs wrap into the zero tail).  Periodic
+// boundary: halos of T wrapped samples on both sides.
+static int64_t single_segment_len(const Plan &p, int64_t T) {
+    return p.boundary == CWT_ZERO ? p.N + T + 1 : p.N + 2 * align_halo(T);
+}
+
+// Frames a segment group: halo Tg, kept outputs V per segment, segment count.
+// A zero-boundary group whose segment holds the whole signal uses the
+// single-segment framing above (no left halo, V = N).
+static void frame_group(const Plan &p, SegGroup &g) {
+    if (p.boundary == CWT_ZERO && g.L >= p.N + g.Tg + 1) {
+        g.Tg = 0;
+        g.V = p.N;
+        g.nseg = 1;
+        return;
+    }
+    g.Tg = align_halo(g.Tg);
+    g.V = g.L - 2 * g.Tg;
+    if (g.V <= 0) fail(CWT_EUNSUPPORTED, "internal: segment too short for the halo");
+    g.nseg = (p.N + g.V - 1) / g.V;
+}
+
 static void build_seg_plan(Plan &p, const Wavelet &w) {
     const bool fp64 = p.precision == CWT_FP64;
     const int lmax_local = 4096;
@@ -549,9 +575,9 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         // 8 T per segment for long signals, at least 256 samples (a group of
         // shorter segments holds only the few smallest scales, too few to
         // amortise its segment transforms); a short signal is a single
-        // segment just long enough for it and the halos
+        // segment just long enough for it and the halos (see single_segment)
         int64_t L = std::min(std::max<int64_t>(256, next_pow2(8 * p.T[j] + 1)),
-                             std::max<int64_t>(64, next_pow2(p.N + 2 * align_halo(p.T[j]))));
+                             std::max<int64_t>(64, next_pow2(single_segment_len(p, p.T[j]))));
         int lg = 0;
         while ((int64_t(1) << lg) < L) ++lg;
         if (lg > lg_max) fail(CWT_EUNSUPPORTED, "scale too large for the segmented transform (wavelet support above 2^20 samples)");
@@ -619,10 +645,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             g.Tg = std::max(g.Tg, p.T[loc[i].j]);
             ++i;
         }
-        g.Tg = align_halo(g.Tg);
-        g.V = g.L - 2 * g.Tg;
-        if (g.V <= 0) fail(CWT_EUNSUPPORTED, "internal: segment too short for the halo");
-        g.nseg = (p.N + g.V - 1) / g.V;
+        frame_group(p, g);
         g.tab_off = tab_n;
         for (int j : g.scales) add_job(p.scales[j], g.L, 0, g.L, true);
         g.twl_off = fp64 ? push_pass_twiddles<double>(tb, g.L) : push_pass_twiddles<float>(tb, g.L);
@@ -665,9 +688,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
                 fail(CWT_EUNSUPPORTED, "internal: band group tables exceed the staging area");
         }
         for (int j : js) g.Tg = std::max(g.Tg, p.T[j]);
-        g.Tg = align_halo(g.Tg);
-        g.V = g.L - 2 * g.Tg;
-        g.nseg = (p.N + g.V - 1) / g.V;
+        frame_group(p, g);
         const int64_t Q = g.L / g.P;
         const int64_t iters_total = Q / 16;
         // column chunks of the forward: enough workgroups to fill the device,
