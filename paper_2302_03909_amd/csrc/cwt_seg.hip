@@ -475,23 +475,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
 // FP64 whatever the plan precision: an FP32 forward spreads rounding noise of
 // order eps |f| over every bin, which for red spectra swamps the weak
 // high-frequency bands the small scales read.  To keep the FP64 forward
-// within the LDS of the inverse buffer, it runs on G/2 complex columns:
-//  * complex output: real segments 2z and 2z+1 share column z as real and
-//    imaginary part; with Z = DFT(a + i b),  A[k] = (Z[k] + conj Z[-k]) / 2
-//    and B[k] = (Z[k] - conj Z[-k]) / (2 i);
-//  * real-wavelet pairs: column c already holds segments 2c and 2c+1 (the
-//    product with the real spectrum keeps them apart), and the forward runs
-//    in two rounds of G/2 columns.
-// With G = 1 the single column takes the whole FP64 buffer.
+// within the LDS of the inverse buffer, it runs on G/2 complex columns: real
+// segments 2z and 2z+1 share column z as real and imaginary part; with
+// Z = DFT(a + i b),  A[k] = (Z[k] + conj Z[-k]) / 2 and
+// B[k] = (Z[k] - conj Z[-k]) / (2 i).  With G = 1 the single column takes the
+// whole FP64 buffer.
+// Real wavelets (PAIR): the spectrum of a scale, phase folded into X, is
+// Hermitian (real and even, or imaginary and odd), so X K_a + i X K_b inverts
+// to w_a + i w_b: one inverse yields two scales, real part and imaginary part.
 template <typename R, int L, int G, int NT, bool PAIR, bool CPLX>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void local2_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2))) void local2_kernel(
     const BatchArgs a) {
     using C = cplx_t<R>;
     constexpr int LD = lds_len(L);
     static_assert(G * L == 16 * NT, "one radix-16 butterfly per thread");
     constexpr int FCOL = G >= 2 ? G / 2 : 1;           // FP64 columns per round
-    constexpr int NROUND = (PAIR && G >= 2) ? 2 : 1;    // forward rounds
-    constexpr bool TWO = !PAIR && G >= 2;               // two real segments per FP64 column
+    constexpr int NROUND = 1;                           // forward rounds
+    constexpr bool TWO = G >= 2;                        // two real segments per FP64 column
     constexpr int BUF_BYTES = (FCOL * LD * 16 > G * LD * (int)sizeof(C)) ? FCOL * LD * 16 : G * LD * (int)sizeof(C);
     __shared__ double2 bufF[BUF_BYTES / 16];
     C *buf = reinterpret_cast<C *>(bufF);
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     if constexpr (sizeof(R) == 8) load_twl<C, L, NT>(twl, static_cast<const C *>(kd->twl));
     const double2 *twF = reinterpret_cast<const double2 *>(twl);
     const int tid = threadIdx.x;
-    constexpr int SEGS = PAIR ? 2 : 1;  // segments per inverse column
+    constexpr int SEGS = 1;  // segments per inverse column
     const int64_t seg0 = rv.local * G * SEGS;
     // inverse pass-0 layout: thread t owns column cc = t / (L/16), positions
     // ii + r L/16
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const __amdgpu_buffer_rsrc_t fr = make_rsrc(f, (uint32_t)(N * (int64_t)sizeof(R)));
     constexpr int EL = FCOL * L / NT;  // FP64 column elements per thread and round
     static_assert((FCOL * L) % NT == 0, "whole column elements per thread");
-    constexpr bool TWOSEG = PAIR || TWO;
+    constexpr bool TWOSEG = TWO;
 #pragma unroll
     for (int h = 0; h < NROUND; ++h) {
         // FP64 column z of this round: segments s0(z) and s0(z) + 1
@@ -587,24 +587,33 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     // spectrum samples through buffer loads: flat loads would also count as
     // LDS operations and make every LDS wait wait for them
     const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, (uint32_t)((int64_t)nscale * L * (int64_t)sizeof(R)));
-    R kv[16];
+    // scales per inverse: one (complex output) or two (real pair)
+    constexpr int SPI = PAIR ? 2 : 1;
+    R kv[SPI][16];
+    auto load_kv = [&](int j) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) kv[r] = bload(ktab, kr, (uint32_t)((ii + r * NB) * sizeof(R)));
+        for (int h = 0; h < SPI; ++h) {
+            // a missing second scale reads beyond the table: zeros
+            const uint32_t o = j + h < nscale ? (uint32_t)((j + h) * L * (int)sizeof(R)) : kOOB;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) kv[h][r] = bload(ktab, kr, o + (uint32_t)((ii + r * NB) * sizeof(R)));
+        }
+    };
+    load_kv(0);
     constexpr uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
-    for (int j = 0; j < nscale; ++j) {
+    for (int j = 0; j < nscale; j += SPI) {
         C v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = cscale(Xr[r], kv[r]);
-        if (j + 1 < nscale) {  // prefetch the next scale's spectrum samples
-            const uint32_t o = (uint32_t)((j + 1) * L * (int)sizeof(R));
-#pragma unroll
-            for (int r = 0; r < 16; ++r) kv[r] = bload(ktab, kr, o + (uint32_t)((ii + r * NB) * sizeof(R)));
-        }
+        for (int r = 0; r < 16; ++r) v[r] = PAIR ? cmul(Xr[r], mk<C>(kv[0][r], kv[1][r])) : cscale(Xr[r], kv[0][r]);
+        if (j + SPI < nscale) load_kv(j + SPI);  // prefetch the next scales' spectrum samples
         // keep the prefetch loads ahead of this scale's stores (no code emitted)
         asm volatile("" ::: "memory");
         cols_pass0_regs<C, L, G, NT, LD, +1>(buf, v);
         const __amdgpu_buffer_rsrc_t rr =
             make_rsrc(out + (int64_t)cload(scale_ids + j) * N * (CPLX ? 2 : 1), (uint32_t)(N * eb));
+        const bool has_b = PAIR && j + 1 < nscale;
+        const __amdgpu_buffer_rsrc_t rb =
+            make_rsrc(out + (int64_t)cload(scale_ids + (has_b ? j + 1 : j)) * N, (uint32_t)(N * eb));
         // position-fastest last pass: consecutive lanes store consecutive
         // outputs of one segment
         auto emit = [&](int c, int p, C val) {
@@ -615,7 +624,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             if (CPLX) bstore(val, rr, off);
             else {
                 bstore(val.x, rr, off);
-                if (PAIR) bstore(val.y, rr, (inside && sgi + 1 < nseg) ? (uint32_t)((b + V) * (int64_t)eb) : kOOB);
+                bstore(val.y, rb, has_b ? off : kOOB);
             }
         };
         cols_fft_after0<C, L, G, NT, LD, +1, false, decltype(emit), true>(buf, twl, emit);
@@ -635,7 +644,10 @@ bool local2_size_ok(int L, int precision) {
     int lmax = 4096;
     return L >= 64 && L <= lmax && (L & (L - 1)) == 0;
 }
-int local2_segs_per_block(int L, bool pair, bool fp64) { return local2_ncol(L, fp64) * (pair ? 2 : 1); }
+int local2_segs_per_block(int L, bool pair, bool fp64) {
+    (void)pair;  // real pairs share an inverse between two scales, not segments
+    return local2_ncol(L, fp64);
+}
 
 template <typename R, int L>
 static hipError_t local2_launch_L(const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
