@@ -53,7 +53,8 @@ struct SegGroup {
     int64_t tab_off = 0;          // LOCAL: offset (elements) of the L-point tables
     int32_t *d_scales = nullptr;
     int64_t twl_off = -1;  // LOCAL: per-pass LDS twiddle table of size L, bytes
-    int64_t gtw_off = -1;  // BAND: w_L^{m g}, g < 16, m in band, bytes
+    int64_t gtw_off = -1;  // BAND: column factors (w_L^{m g}, or column pairs), g < 16, m in band, bytes
+    int32_t colpair = 0;   // BAND, real output: complex column g holds columns 2g, 2g + 1 of one scale
     size_t ws_xp_off = 0, ws_x_off = 0;
     int32_t unit0 = 0, nunits = 0;  // BAND: range in Plan::units
     int32_t key = -1;               // LOCAL: index of its KeyDesc
@@ -64,13 +65,15 @@ struct SegGroup {
 struct SegGroupDev {
     int32_t lgL, B, nchunk, iters;
     int32_t unit0, nunits;
+    int32_t colpair, pad;
     int64_t V, Tg, klo, nseg;
     int64_t xp_off, x_off;  // workspace byte offsets of the partial and reduced band spectra
-    int64_t gtw_off;        // byte offset of w_L^{m g} in the twiddle allocation
+    int64_t gtw_off;        // byte offset of the column factors in the twiddle allocation
 };
 
 // one output unit of a BAND group: a scale, or a pair of real-wavelet scales
-// sharing one complex transform (sb = -1: none)
+// sharing one complex transform (sb = -1: none; always none in a column-pair
+// group)
 struct SegUnit {
     int32_t sa, sb;
     int64_t ka, kb;  // offsets of their spectrum samples in the spectrum table

@@ -691,6 +691,14 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         frame_group(p, g);
         const int64_t Q = g.L / g.P;
         const int64_t iters_total = Q / 16;
+        // Real FP32 output with rows of at least 32 columns: the inverse packs
+        // adjacent columns 2g, 2g + 1 of one scale into one complex column
+        // (each column's output is real), so that every lane stores two
+        // neighbouring outputs and a 16-lane run fills a 128-byte line.  Needs
+        // even output offsets (N even; V and Tg are multiples of 16 or V = N)
+        // and one unit per scale.  (FP64 runs of 16 columns fill whole lines
+        // already.)
+        g.colpair = p.pair_real && !fp64 && Q >= 32 && p.N % 2 == 0 && (int)js.size() <= kMaxUnits ? 1 : 0;
         // column chunks of the forward: enough workgroups to fill the device,
         // at most 256 partial sums per bin.  A chunk keeps at least two
         // 16-column iterations: a wave reads 16 consecutive FP32 columns (half
@@ -704,12 +712,16 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         // spectrum samples of each scale on the group band
         std::vector<int64_t> koff(js.size());
         for (size_t u = 0; u < js.size(); ++u) koff[u] = add_job(p.scales[js[u]], g.L, g.klo, g.B, false);
-        // w_L^{m g}, g < 16
+        // column factors, g < 16: w_L^{m g}, or w_L^{2 m g} (1 + i w_L^m) for
+        // the column pair (2g, 2g + 1)
         {
             std::vector<double> gt(2 * 16 * (size_t)g.B);
             for (int gg = 0; gg < 16; ++gg)
                 for (int k = 0; k < g.B; ++k) {
-                    const std::complex<double> v = w23_at((g.klo + k) * gg, g.lgL);
+                    const std::complex<double> v =
+                        g.colpair ? w23_at((g.klo + k) * 2 * gg, g.lgL) *
+                                        (1.0 + std::complex<double>(0.0, 1.0) * w23_at(g.klo + k, g.lgL))
+                                  : w23_at((g.klo + k) * gg, g.lgL);
                     gt[2 * ((size_t)gg * g.B + k)] = v.real();
                     gt[2 * ((size_t)gg * g.B + k) + 1] = v.imag();
                 }
@@ -719,13 +731,15 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
                 g.gtw_off = tb.add(g32.data(), g32.size() * sizeof(float));
             }
         }
-        // output units: single scales (complex output) or pairs (real output)
+        // output units: single scales (complex output, column pairs) or
+        // scale pairs (other real output)
         g.unit0 = (int32_t)p.units.size();
-        for (size_t u = 0; u < js.size(); u += per_unit) {
+        const bool scale_pairs = p.pair_real && !g.colpair;
+        for (size_t u = 0; u < js.size(); u += scale_pairs ? 2 : 1) {
             SegUnit un{};
             un.sa = js[u];
             un.ka = koff[u];
-            if (p.pair_real && u + 1 < js.size()) {
+            if (scale_pairs && u + 1 < js.size()) {
                 un.sb = js[u + 1];
                 un.kb = koff[u + 1];
             } else {
@@ -756,6 +770,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         gd.iters = g.iters;
         gd.unit0 = g.unit0;
         gd.nunits = g.nunits;
+        gd.colpair = g.colpair;
         gd.V = g.V;
         gd.Tg = g.Tg;
         gd.klo = g.klo;
@@ -780,7 +795,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
                 for (int32_t kb = 0; kb < nkb; ++kb)
                     sl->red.push_back({gi, (int32_t)sg, kb, (int32_t)std::min(rsw, g.nseg - sg)});
         for (int64_t sg = 0; sg < g.nseg; ++sg)
-            for (int64_t r0 = 0; r0 < Q; r0 += 16) sl->inv.push_back({gi, (int32_t)sg, (int32_t)r0, 0});
+            for (int64_t r0 = 0; r0 < Q; r0 += g.colpair ? 32 : 16) sl->inv.push_back({gi, (int32_t)sg, (int32_t)r0, 0});
         p.segs.push_back(std::move(g));
     }
     p.ws_bytes = ws;
@@ -1494,9 +1509,9 @@ int cwt_plan_describe(cwt_plan_t plan, char *buf, size_t size) {
         p.method == CWT_METHOD_SPLINE ? "spline" : (p.fft_mode == CWT_FFT_WHOLE ? "fft-whole" : "fft-segmented"),
         p.precision == CWT_FP64 ? "fp64" : "fp32", p.ws_bytes, p.table_bytes);
     for (const auto &g : p.segs)
-        add("%s L=%d P=%d B=%d Tg=%lld V=%lld nseg=%lld nchunk=%d iters=%d scales=%zu\n",
+        add("%s L=%d P=%d B=%d Tg=%lld V=%lld nseg=%lld nchunk=%d iters=%d scales=%zu%s\n",
             g.kind == cwt::SegGroup::LOCAL ? "local" : "band", g.L, g.P, g.B, (long long)g.Tg, (long long)g.V,
-            (long long)g.nseg, g.nchunk, g.iters, g.scales.size());
+            (long long)g.nseg, g.nchunk, g.iters, g.scales.size(), g.colpair ? " colpair=1" : "");
     for (const auto &l : p.seg_launches)
         add("launch P=%d groups=%zu forward=%zu reduce=%zu inverse=%zu\n", l.P, l.gdev.size(), l.fwd.size(),
             l.red.size(), l.inv.size());

@@ -18,7 +18,10 @@
 //             column chunk, then seg_reduce_kernel)
 //   inverse  W[r + Q p] = DFT_P^{-1}( Y[m] w_L^{m r} )[p],  m = k mod P
 //            (seg_inverse_kernel: 16 consecutive columns r per workgroup, so
-//             the last FFT pass stores 16-element runs straight to HBM).
+//             the last FFT pass stores 16-element runs straight to HBM; 32
+//             columns as 16 adjacent pairs for real FP32 output).
+#include <type_traits>
+
 #include "cwt_internal.h"
 #include "fft_cols.h"
 
@@ -324,7 +327,15 @@ constexpr int seg_kls_elems(int rbytes, int P) {
 
 // ---------------------------------------------------------------------------
 // band-limited inverse: work item (g, seg, r0) covers columns r0..r0+15 of one
-// segment for every output unit of the group
+// segment for every output unit of the group.  Real output takes two real
+// transforms per complex one: either two scales (unit sa, sb: real and
+// imaginary part), or, in a column-pair group, the adjacent columns
+// r0 + 2c, r0 + 2c + 1 of one scale as complex column c (work item r0..r0+31).
+// Every column of a real output has a Hermitian P-point spectrum, so
+// Z_{2c} + i Z_{2c+1} inverts to W_{2c} + i W_{2c+1}; each lane then holds two
+// neighbouring outputs and stores them with one 8-byte store, 16 lanes
+// filling a whole 128-byte line (two half lines written by different
+// workgroups stream at about two thirds of the rate).
 
 template <typename R, int P, int NT, bool PAIR, bool CPLX>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void seg_inverse_kernel(
@@ -352,6 +363,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const SegWork w = cload(kd->work + rv.local);
     const SegGroupDev gd = cload(kd->groups + w.g);
     const int nunits = gd.nunits < MAXU ? gd.nunits : MAXU;
+    const bool cp = PAIR && gd.colpair;  // column pairs of one scale (uniform)
     const int64_t L = int64_t(1) << gd.lgL, Q = L >> log2_exact(P);
     const int sh = 23 - gd.lgL;
     const int tid = threadIdx.x;
@@ -406,7 +418,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             for (int j = 0; j < 8; ++j) {
                 if (u0 + j < nunits) {
                     kls[(u0 + j) * B + tid] = ka[j];
-                    if constexpr (PAIR) kls[nunits * B + (u0 + j) * B + tid] = kb[j];
+                    if constexpr (PAIR)
+                        if (!cp) kls[nunits * B + (u0 + j) * B + tid] = kb[j];
                 }
             }
         }
@@ -426,44 +439,55 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     lds_barrier();  // xs (in buf) is no longer read
     const int64_t ob = (int64_t)w.seg * gd.V - gd.Tg;
     const uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
-    for (int u = 0; u < nunits; ++u) {
-        // unit fields are uniform; say so, so that the store descriptors
-        // live in scalar registers (no waterfall loop around the stores)
-        const SegUnit su = cload(units + gd.unit0 + u);
-        const int sa = __builtin_amdgcn_readfirstlane(su.sa);
-        const int sb = __builtin_amdgcn_readfirstlane(su.sb);
-        C v[16];
+    const int64_t lo_all = gd.Tg - r0, hi_all = gd.Tg + gd.V - r0;
+    const int64_t obr = ob + r0;
+    auto units_loop = [&](auto cp_const) {
+        constexpr bool CP = decltype(cp_const)::value;
+        for (int u = 0; u < nunits; ++u) {
+            // unit fields are uniform; say so, so that the store descriptors
+            // live in scalar registers (no waterfall loop around the stores)
+            const SegUnit su = cload(units + gd.unit0 + u);
+            const int sa = __builtin_amdgcn_readfirstlane(su.sa);
+            const int sb = __builtin_amdgcn_readfirstlane(su.sb);
+            C v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const R ka = kls[u * B + fro[r]];
-            if constexpr (PAIR) {
-                const R kb = kls[nunits * B + u * B + fro[r]];
-                v[r] = cmul(xg[r], mk<C>(ka, kb));
-            } else {
-                v[r] = cscale(xg[r], ka);
+            for (int r = 0; r < 16; ++r) {
+                const R ka = kls[u * B + fro[r]];
+                if constexpr (PAIR && !CP) {
+                    const R kb = kls[nunits * B + u * B + fro[r]];
+                    v[r] = cmul(xg[r], mk<C>(ka, kb));
+                } else {
+                    v[r] = cscale(xg[r], ka);
+                }
             }
+            cols_pass0_regs<C, P, G, NT, LD, +1>(buf, v);
+            // output b = ob + r0 + o, o = cc + Q p (column pairs: 2 cc + Q p and
+            // the next one), kept when Tg <= o < Tg + V; the descriptor of each
+            // row spans exactly its N values, so b >= N is dropped.  Column
+            // pairs: o, Tg, V and N are even, so both outputs are kept or dropped.
+            const __amdgpu_buffer_rsrc_t ra =
+                make_rsrc(out + (int64_t)sa * N * (CPLX ? 2 : 1), (uint32_t)(N * eb));
+            const __amdgpu_buffer_rsrc_t rb =
+                make_rsrc(out + (int64_t)(PAIR && sb >= 0 ? sb : sa) * N, (uint32_t)(N * eb));
+            const bool has_b = PAIR && sb >= 0;
+            auto emit = [&](int cc, int p, C val) {
+                const int64_t o = (CP ? 2 * cc : cc) + Q * p;
+                const uint32_t off = (o >= lo_all && o < hi_all) ? (uint32_t)((obr + o) * (int64_t)eb) : kOOB;
+                if (CPLX || CP) bstore(val, ra, off);
+                else {
+                    bstore(val.x, ra, off);
+                    bstore(val.y, rb, has_b ? off : kOOB);
+                }
+            };
+            cols_fft_after0<C, P, G, NT, LD, +1, false>(buf, twl, emit);
+            lds_barrier();
         }
-        cols_pass0_regs<C, P, G, NT, LD, +1>(buf, v);
-        // output b = ob + r0 + cc + Q p, kept when Tg <= r0 + cc + Q p < Tg + V; the
-        // descriptor of each row spans exactly its N values, so b >= N is dropped
-        const __amdgpu_buffer_rsrc_t ra =
-            make_rsrc(out + (int64_t)sa * N * (CPLX ? 2 : 1), (uint32_t)(N * eb));
-        const __amdgpu_buffer_rsrc_t rb =
-            make_rsrc(out + (int64_t)(PAIR && sb >= 0 ? sb : sa) * N, (uint32_t)(N * eb));
-        const bool has_b = PAIR && sb >= 0;
-        const int64_t lo_all = gd.Tg - r0, hi_all = gd.Tg + gd.V - r0;
-        const int64_t obr = ob + r0;
-        auto emit = [&](int cc, int p, C val) {
-            const int64_t o = cc + Q * p;
-            const uint32_t off = (o >= lo_all && o < hi_all) ? (uint32_t)((obr + o) * (int64_t)eb) : kOOB;
-            if (CPLX) bstore(val, ra, off);
-            else {
-                bstore(val.x, ra, off);
-                bstore(val.y, rb, has_b ? off : kOOB);
-            }
-        };
-        cols_fft_after0<C, P, G, NT, LD, +1, false>(buf, twl, emit);
-        lds_barrier();
+    };
+    if constexpr (PAIR) {
+        if (cp) units_loop(std::true_type{});
+        else units_loop(std::false_type{});
+    } else {
+        units_loop(std::false_type{});
     }
 }
 

@@ -157,6 +157,24 @@ def test_segment_groups_of_the_headline_plan():
             assert nchunk == 1 or iters >= 2
 
 
+def test_column_pairs_only_for_real_fp32_output_of_even_length():
+    scales = np.geomspace(2, 2 ** 16, 128)
+
+    def band(n, wav, par, precision):
+        p = cwt.Plan(n, "zero", wav, scales, param=par, precision=precision, host_only=True)
+        return [(int(ln.split("L=")[1].split()[0]), int(ln.split("P=")[1].split()[0]), "colpair=1" in ln)
+                for ln in p.describe().splitlines() if ln.startswith("band")]
+
+    # real output, FP32, even N: every band group whose rows hold >= 32 columns
+    g = band(1 << 22, "dog", 2.0, "fp32")
+    assert g and all(cp == (L // P >= 32) for L, P, cp in g)
+    assert any(cp for _, _, cp in g) and not all(cp for _, _, cp in g)
+    # complex output, FP64 or odd N: scale pairs (or single scales) only
+    assert not any(cp for _, _, cp in band(1 << 22, "morlet", 6.0, "fp32"))
+    assert not any(cp for _, _, cp in band(1 << 20, "dog", 2.0, "fp64"))
+    assert not any(cp for _, _, cp in band((1 << 22) - 1, "dog", 2.0, "fp32"))
+
+
 def test_segment_groups_not_merged_for_fp64_or_short_signals():
     scales = np.geomspace(2, 2 ** 12, 48)
     p = cwt.Plan(1 << 20, "zero", "morlet", scales, param=6.0, precision="fp64", host_only=True)

@@ -80,6 +80,23 @@ def test_parity_mixed(torch_cuda, precision, n, bc, wav, par, scales, fft_mode):
     check_full(torch_cuda, f, bc, wav, par, scales, precision, fft_mode=fft_mode)
 
 
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+@pytest.mark.parametrize("wav,par", [("mexhat", None), ("dog", 3.0)])
+@pytest.mark.parametrize("n", [20002, 20001])
+def test_real_output_column_pairs(torch_cuda, n, wav, par, bc):
+    # Real FP32 output: band groups with rows of >= 32 columns pair adjacent
+    # columns of one scale when N is even, else pair scales; several segments
+    # per group, a ragged last segment, a single-segment group, even and odd
+    # (imaginary spectrum) wavelets.
+    import paper_2302_03909_amd as cwt
+    scales = synth.log_scales(1.5, 600.0, 12)
+    plan = cwt.Plan(n, bc, wav, scales, param=par, precision="fp32", host_only=True)
+    band = [ln for ln in plan.describe().splitlines() if ln.startswith("band")]
+    assert any("colpair=1" in ln for ln in band) == (n % 2 == 0)
+    f = np.random.default_rng(n).standard_normal(n) + 0.2
+    check_full(torch_cuda, f, bc, wav, par, scales, "fp32")
+
+
 @pytest.mark.parametrize("fft_mode", ["segmented", "whole"])
 @pytest.mark.parametrize("n", [2, 3, 17])
 @pytest.mark.parametrize("bc", ["periodic", "zero"])
