@@ -55,6 +55,7 @@ struct SegGroup {
     int64_t twl_off = -1;  // LOCAL: per-pass LDS twiddle table of size L, bytes
     int64_t gtw_off = -1;  // BAND: column factors (w_L^{m g}, or column pairs), g < 16, m in band, bytes
     int32_t colpair = 0;   // BAND, real output: complex column g holds columns 2g, 2g + 1 of one scale
+    int32_t cshift = 0;    // BAND: some unit's columns are shifted (SegUnit::dsh); complex staged samples
     size_t ws_xp_off = 0, ws_x_off = 0;
     int32_t unit0 = 0, nunits = 0;  // BAND: range in Plan::units
     int32_t key = -1;               // LOCAL: index of its KeyDesc
@@ -65,7 +66,7 @@ struct SegGroup {
 struct SegGroupDev {
     int32_t lgL, B, nchunk, iters;
     int32_t unit0, nunits;
-    int32_t colpair, pad;
+    int32_t colpair, cshift;
     int64_t V, Tg, klo, nseg;
     int64_t xp_off, x_off;  // workspace byte offsets of the partial and reduced band spectra
     int64_t gtw_off;        // byte offset of the column factors in the twiddle allocation
@@ -77,6 +78,10 @@ struct SegGroupDev {
 struct SegUnit {
     int32_t sa, sb;
     int64_t ka, kb;  // offsets of their spectrum samples in the spectrum table
+    // single-row units: the work item of first column r0 computes columns
+    // r0 - dsh .. (modulo the segment), so that the row's store runs start on
+    // 128-byte lines; its spectrum samples carry the factor w_L^{-m dsh}
+    int32_t dsh, pad;
 };
 
 // one workgroup of a fused launch: group g, segment seg, and idx = column

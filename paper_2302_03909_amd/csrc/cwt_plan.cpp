@@ -517,7 +517,7 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
 // multiple of 16 too), so the 16-column output runs of the kernels fill whole
 // cache lines instead of straddling two.  Any halo >= the largest T of the
 // group gives the same outputs.
-static int64_t align_halo(int64_t t) { return (t + 15) & ~int64_t(15); }
+static int64_t align_halo(int64_t t, int64_t a = 16) { return (t + a - 1) & ~(a - 1); }
 
 // Stream of the calling thread for plan construction and release
 // (non-blocking, default priority): plan tables are allocated, filled and
@@ -539,17 +539,21 @@ static int64_t single_segment_len(const Plan &p, int64_t T) {
     return p.boundary == CWT_ZERO ? p.N + T + 1 : p.N + 2 * align_halo(T);
 }
 
-// Frames a segment group: halo Tg, kept outputs V per segment, segment count.
-// A zero-boundary group whose segment holds the whole signal uses the
-// single-segment framing above (no left halo, V = N).
-static void frame_group(const Plan &p, SegGroup &g) {
-    if (p.boundary == CWT_ZERO && g.L >= p.N + g.Tg + 1) {
+// Frames a segment group: halo Tg, kept outputs V per segment, segment count,
+// with Tg and V multiples of a (16, or 32 for column pairs).  A zero-boundary
+// group whose segment holds the whole signal uses the single-segment framing
+// above (no left halo, V = N).
+static bool single_segment(const Plan &p, const SegGroup &g) {
+    return p.boundary == CWT_ZERO && g.L >= p.N + g.Tg + 1;
+}
+static void frame_group(const Plan &p, SegGroup &g, int64_t a = 16) {
+    if (single_segment(p, g)) {
         g.Tg = 0;
         g.V = p.N;
         g.nseg = 1;
         return;
     }
-    g.Tg = align_halo(g.Tg);
+    g.Tg = align_halo(g.Tg, a);
     g.V = g.L - 2 * g.Tg;
     if (g.V <= 0) fail(CWT_EUNSUPPORTED, "internal: segment too short for the halo");
     g.nseg = (p.N + g.V - 1) / g.V;
@@ -656,6 +660,13 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     const int kMaxUnits = 32;
     std::sort(band.begin(), band.end(), [](const Cand &a, const Cand &b) { return a.lg < b.lg || (a.lg == b.lg && a.j < b.j); });
     const int per_unit = p.pair_real ? 2 : 1;
+    // Output elements per 128-byte line: complex rows, and real FP32 rows
+    // written as column pairs.  When N is not a multiple of it, rows start
+    // inside a line, and the inverse shifts each unit's columns so that its
+    // store runs start on line boundaries; its spectrum samples are then
+    // complex (twice the staging space).
+    const int64_t line_e = 128 / ((p.cplx_out ? 2 : 1) * (fp64 ? 8 : 4));
+    const bool may_shift = (p.cplx_out || (!fp64 && p.N % 2 == 0)) && p.N % line_e != 0;
     for (size_t i = 0; i < band.size();) {
         SegGroup g;
         g.kind = SegGroup::BAND;
@@ -670,8 +681,10 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             if (!js.empty() && (P > pmax || P * 16 > g.L)) break;
             // the inverse stages all spectrum samples of a group in LDS
             int64_t kls_cap = std::max<int64_t>(2 * P, kSegKlsBytes / (fp64 ? 8 : 4));
-            // (a real-wavelet pair takes two tables even when its second scale is absent)
-            int64_t ntab = ((int64_t)js.size() + 1 + per_unit - 1) / per_unit * per_unit;
+            // (a real-wavelet pair takes two tables even when its second scale
+            // is absent; a shifted unit's complex samples take two)
+            int64_t ntab = may_shift ? 2 * ((int64_t)js.size() + 1)
+                                     : ((int64_t)js.size() + 1 + per_unit - 1) / per_unit * per_unit;
             if (!js.empty() && ntab * (nhi - nlo + 1) > kls_cap) break;
             klo = nlo;
             khi = nhi;
@@ -682,23 +695,21 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         g.klo = klo;
         g.B = (int32_t)(khi - klo + 1);
         g.P = (int32_t)std::max<int64_t>(64, next_pow2(g.B));
-        {
-            int64_t ntab = ((int64_t)js.size() + per_unit - 1) / per_unit * per_unit;
-            if (ntab * g.B > std::max<int64_t>(2 * g.P, kSegKlsBytes / (fp64 ? 8 : 4)))
-                fail(CWT_EUNSUPPORTED, "internal: band group tables exceed the staging area");
-        }
         for (int j : js) g.Tg = std::max(g.Tg, p.T[j]);
-        frame_group(p, g);
         const int64_t Q = g.L / g.P;
         const int64_t iters_total = Q / 16;
         // Real FP32 output with rows of at least 32 columns: the inverse packs
         // adjacent columns 2g, 2g + 1 of one scale into one complex column
         // (each column's output is real), so that every lane stores two
         // neighbouring outputs and a 16-lane run fills a 128-byte line.  Needs
-        // even output offsets (N even; V and Tg are multiples of 16 or V = N)
-        // and one unit per scale.  (FP64 runs of 16 columns fill whole lines
+        // even output offsets (N even; V and Tg multiples of 32, or V = N) and
+        // one unit per scale.  (FP64 runs of 16 columns fill whole lines
         // already.)
-        g.colpair = p.pair_real && !fp64 && Q >= 32 && p.N % 2 == 0 && (int)js.size() <= kMaxUnits ? 1 : 0;
+        g.colpair = p.pair_real && !fp64 && Q >= 32 && p.N % 2 == 0 && (int)js.size() <= kMaxUnits &&
+                            (single_segment(p, g) || g.L > 2 * align_halo(g.Tg, 32))
+                        ? 1
+                        : 0;
+        frame_group(p, g, g.colpair ? 32 : 16);
         // column chunks of the forward: enough workgroups to fill the device,
         // at most 256 partial sums per bin.  A chunk keeps at least two
         // 16-column iterations: a wave reads 16 consecutive FP32 columns (half
@@ -746,9 +757,22 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
                 un.sb = -1;
                 un.kb = koff[u];
             }
+            // column shift of a single-row unit: its row starts dsh elements
+            // past a line boundary (for an output aligned to 128 bytes; the
+            // result does not depend on it).  Segment starts and first
+            // columns are multiples of the line length already.
+            if (p.cplx_out || g.colpair) {
+                un.dsh = (int32_t)(((int64_t)un.sa * p.N) % line_e);
+                if (un.dsh != 0) g.cshift = 1;
+            }
             p.units.push_back(un);
         }
         g.nunits = (int32_t)p.units.size() - g.unit0;
+        {
+            const int64_t need = g.cshift ? 2 * (int64_t)g.nunits : (scale_pairs ? 2 : 1) * (int64_t)g.nunits;
+            if (need * g.B > std::max<int64_t>(2 * g.P, kSegKlsBytes / (fp64 ? 8 : 4)))
+                fail(CWT_EUNSUPPORTED, "internal: band group tables exceed the staging area");
+        }
         g.ws_xp_off = ws_take((size_t)g.nseg * g.nchunk * g.B * 16);
         // one column chunk: the partial sums are the band spectra (no reduce)
         g.ws_x_off = g.nchunk == 1 ? g.ws_xp_off : ws_take((size_t)g.nseg * g.B * 16);
@@ -771,6 +795,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         gd.unit0 = g.unit0;
         gd.nunits = g.nunits;
         gd.colpair = g.colpair;
+        gd.cshift = g.cshift;
         gd.V = g.V;
         gd.Tg = g.Tg;
         gd.klo = g.klo;
@@ -1509,9 +1534,10 @@ int cwt_plan_describe(cwt_plan_t plan, char *buf, size_t size) {
         p.method == CWT_METHOD_SPLINE ? "spline" : (p.fft_mode == CWT_FFT_WHOLE ? "fft-whole" : "fft-segmented"),
         p.precision == CWT_FP64 ? "fp64" : "fp32", p.ws_bytes, p.table_bytes);
     for (const auto &g : p.segs)
-        add("%s L=%d P=%d B=%d Tg=%lld V=%lld nseg=%lld nchunk=%d iters=%d scales=%zu%s\n",
+        add("%s L=%d P=%d B=%d Tg=%lld V=%lld nseg=%lld nchunk=%d iters=%d scales=%zu%s%s\n",
             g.kind == cwt::SegGroup::LOCAL ? "local" : "band", g.L, g.P, g.B, (long long)g.Tg, (long long)g.V,
-            (long long)g.nseg, g.nchunk, g.iters, g.scales.size(), g.colpair ? " colpair=1" : "");
+            (long long)g.nseg, g.nchunk, g.iters, g.scales.size(), g.colpair ? " colpair=1" : "",
+            g.cshift ? " shift=1" : "");
     for (const auto &l : p.seg_launches)
         add("launch P=%d groups=%zu forward=%zu reduce=%zu inverse=%zu\n", l.P, l.gdev.size(), l.fwd.size(),
             l.red.size(), l.inv.size());

@@ -336,6 +336,12 @@ constexpr int seg_kls_elems(int rbytes, int P) {
 // neighbouring outputs and stores them with one 8-byte store, 16 lanes
 // filling a whole 128-byte line (two half lines written by different
 // workgroups stream at about two thirds of the rate).
+// A row that starts inside a line (N not a multiple of the line length) is
+// shifted: for that unit the work item computes columns r0 - dsh .. instead
+// (dsh = the row's offset in its line), so its runs again start on lines.
+// Since W[t] = sum_k Y[k] w_L^{k t} for any t modulo L, the shift only
+// multiplies the unit's spectrum samples by w_L^{-k dsh}, and column r < 0
+// of row p is the output t = r + Q p (+ L when negative).
 
 template <typename R, int P, int NT, bool PAIR, bool CPLX>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void seg_inverse_kernel(
@@ -349,7 +355,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     static_assert(NT == P, "one pass-0 butterfly per thread");
     __shared__ C buf[G * LD];
     __shared__ C twl[twl_len(P)];
-    __shared__ R kls[KLS];  // spectrum samples of the group's units (and pair partners)
+    // spectrum samples of the group's units (and pair partners); complex
+    // (shifted units) or real
+    __shared__ C klsc[(KLS + 1) / 2];
+    R *const kls = reinterpret_cast<R *>(klsc);
     const Resolved rv = resolve(a);
     const KeyDesc *kd = &rv.kd;
     const char *__restrict__ ws = rv.bi.ws;
@@ -363,7 +372,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const SegWork w = cload(kd->work + rv.local);
     const SegGroupDev gd = cload(kd->groups + w.g);
     const int nunits = gd.nunits < MAXU ? gd.nunits : MAXU;
-    const bool cp = PAIR && gd.colpair;  // column pairs of one scale (uniform)
+    const bool cp = PAIR && gd.colpair;              // column pairs of one scale (uniform)
+    const bool shf = gd.cshift && (CPLX || cp);      // shifted single-row units (uniform)
     const int64_t L = int64_t(1) << gd.lgL, Q = L >> log2_exact(P);
     const int sh = 23 - gd.lgL;
     const int tid = threadIdx.x;
@@ -399,8 +409,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     }
     load_twl<C, P, NT>(twl, static_cast<const C *>(kd->twl));
     // spectrum samples of every unit of the group (and pair partners),
-    // staged in LDS once, eight units per batch of loads
-    if (tid < B) {
+    // staged in LDS once, eight units per batch of loads; a shifted unit's
+    // samples times w_L^{-m dsh} (complex)
+    if (tid < B && shf) {
+        const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, 0x7ffffff0u);
+        const int64_t mm = gd.klo + tid;
+        for (int u = 0; u < nunits; ++u) {
+            const SegUnit su = cload(units + gd.unit0 + u);
+            const double ka = (double)bload(ktab, kr, (uint32_t)((uni(su.ka) + tid) * (int64_t)sizeof(R)));
+            const double2 ph = w23(whi, wlo, ((-mm * __builtin_amdgcn_readfirstlane(su.dsh)) & (L - 1)) << sh);
+            klsc[u * B + tid] = to_c<C>(make_double2(ph.x * ka, ph.y * ka));
+        }
+    } else if (tid < B) {
         const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, 0x7ffffff0u);
         for (int u0 = 0; u0 < nunits; u0 += 8) {
             R ka[8], kb[8];
@@ -437,42 +457,52 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
         xg[r] = mul_i_pow(cmul(xs[fro[r]], gv[r]), cph);
     }
     lds_barrier();  // xs (in buf) is no longer read
+    // 32-bit position arithmetic: t < L <= 2^23, and byte offsets are taken
+    // modulo 2^32 (every kept one is below the 2 GiB of a row descriptor)
     const int64_t ob = (int64_t)w.seg * gd.V - gd.Tg;
     const uint32_t eb = (uint32_t)(CPLX ? sizeof(C) : sizeof(R));
-    const int64_t lo_all = gd.Tg - r0, hi_all = gd.Tg + gd.V - r0;
-    const int64_t obr = ob + r0;
-    auto units_loop = [&](auto cp_const) {
+    const uint32_t obe = (uint32_t)ob * eb;
+    const int32_t tlo = (int32_t)gd.Tg, thi = (int32_t)(gd.Tg + gd.V);
+    const int32_t Li = (int32_t)L, Qi = (int32_t)Q;
+    auto units_loop = [&](auto cp_const, auto sh_const) {
         constexpr bool CP = decltype(cp_const)::value;
+        constexpr bool SH = decltype(sh_const)::value;
         for (int u = 0; u < nunits; ++u) {
             // unit fields are uniform; say so, so that the store descriptors
             // live in scalar registers (no waterfall loop around the stores)
             const SegUnit su = cload(units + gd.unit0 + u);
             const int sa = __builtin_amdgcn_readfirstlane(su.sa);
             const int sb = __builtin_amdgcn_readfirstlane(su.sb);
+            const int dl = SH ? __builtin_amdgcn_readfirstlane(su.dsh) : 0;
             C v[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const R ka = kls[u * B + fro[r]];
-                if constexpr (PAIR && !CP) {
+                if constexpr (SH) {
+                    v[r] = cmul(xg[r], klsc[u * B + fro[r]]);
+                } else if constexpr (PAIR && !CP) {
+                    const R ka = kls[u * B + fro[r]];
                     const R kb = kls[nunits * B + u * B + fro[r]];
                     v[r] = cmul(xg[r], mk<C>(ka, kb));
                 } else {
-                    v[r] = cscale(xg[r], ka);
+                    v[r] = cscale(xg[r], kls[u * B + fro[r]]);
                 }
             }
             cols_pass0_regs<C, P, G, NT, LD, +1>(buf, v);
-            // output b = ob + r0 + o, o = cc + Q p (column pairs: 2 cc + Q p and
-            // the next one), kept when Tg <= o < Tg + V; the descriptor of each
-            // row spans exactly its N values, so b >= N is dropped.  Column
-            // pairs: o, Tg, V and N are even, so both outputs are kept or dropped.
+            // output b = ob + t, t = r0 - dsh + col + Q p modulo L (col = cc,
+            // or 2 cc and the next one for column pairs); only t < 0 wraps.
+            // Kept when Tg <= t < Tg + V; the descriptor of each row spans
+            // exactly its N values, so b >= N is dropped.  Column pairs: t,
+            // Tg, V and N are even, so both outputs are kept or dropped.
             const __amdgpu_buffer_rsrc_t ra =
                 make_rsrc(out + (int64_t)sa * N * (CPLX ? 2 : 1), (uint32_t)(N * eb));
             const __amdgpu_buffer_rsrc_t rb =
                 make_rsrc(out + (int64_t)(PAIR && sb >= 0 ? sb : sa) * N, (uint32_t)(N * eb));
             const bool has_b = PAIR && sb >= 0;
+            const int32_t t0 = (int32_t)r0 - dl;
             auto emit = [&](int cc, int p, C val) {
-                const int64_t o = (CP ? 2 * cc : cc) + Q * p;
-                const uint32_t off = (o >= lo_all && o < hi_all) ? (uint32_t)((obr + o) * (int64_t)eb) : kOOB;
+                int32_t t = t0 + (CP ? 2 * cc : cc) + Qi * p;
+                if constexpr (SH) t += t < 0 ? Li : 0;
+                const uint32_t off = (t >= tlo && t < thi) ? obe + (uint32_t)t * eb : kOOB;
                 if (CPLX || CP) bstore(val, ra, off);
                 else {
                     bstore(val.x, ra, off);
@@ -483,11 +513,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             lds_barrier();
         }
     };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
     if constexpr (PAIR) {
-        if (cp) units_loop(std::true_type{});
-        else units_loop(std::false_type{});
+        if (!cp) units_loop(F_{}, F_{});
+        else if (shf) units_loop(T_{}, T_{});
+        else units_loop(T_{}, F_{});
     } else {
-        units_loop(std::false_type{});
+        if (shf) units_loop(F_{}, T_{});
+        else units_loop(F_{}, F_{});
     }
 }
 

@@ -175,6 +175,28 @@ def test_column_pairs_only_for_real_fp32_output_of_even_length():
     assert not any(cp for _, _, cp in band((1 << 22) - 1, "dog", 2.0, "fp32"))
 
 
+def test_shifted_units_only_where_rows_start_inside_a_line():
+    scales = np.geomspace(2, 2 ** 16, 128)
+
+    def flags(n, wav, par, precision):
+        p = cwt.Plan(n, "zero", wav, scales, param=par, precision=precision, host_only=True)
+        return [("colpair=1" in ln, "shift=1" in ln) for ln in p.describe().splitlines() if ln.startswith("band")]
+
+    # rows of 2^22 elements start on lines: no shift
+    assert not any(sh for _, sh in flags(1 << 22, "morlet", 6.0, "fp32"))
+    assert not any(sh for _, sh in flags(1 << 22, "dog", 2.0, "fp32"))
+    # complex rows off the line grid: band groups with shifted units (a group
+    # whose rows all start on lines has none)
+    g = flags((1 << 22) - 3, "morlet", 6.0, "fp32")
+    assert sum(sh for _, sh in g) >= len(g) - 2
+    assert any(sh for _, sh in flags((1 << 20) - 4, "morlet", 6.0, "fp64"))
+    # real output: column-pair groups shift (N even, not a multiple of 32);
+    # scale-pair groups never do
+    g = flags((1 << 22) - 2, "dog", 2.0, "fp32")
+    assert all(sh == cp for cp, sh in g) and any(cp for cp, _ in g)
+    assert not any(sh for _, sh in flags((1 << 22) - 1, "dog", 2.0, "fp32"))
+
+
 def test_segment_groups_not_merged_for_fp64_or_short_signals():
     scales = np.geomspace(2, 2 ** 12, 48)
     p = cwt.Plan(1 << 20, "zero", "morlet", scales, param=6.0, precision="fp64", host_only=True)

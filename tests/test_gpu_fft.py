@@ -97,6 +97,23 @@ def test_real_output_column_pairs(torch_cuda, n, wav, par, bc):
     check_full(torch_cuda, f, bc, wav, par, scales, "fp32")
 
 
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("n", [20005, 20480])
+def test_complex_rows_shifted_to_lines(torch_cuda, n, precision, bc):
+    # Complex output whose rows start inside a 128-byte line (N not a multiple
+    # of the line length): band units compute their columns shifted by the
+    # row's offset in its line, with the wrapped first columns; N = 20480
+    # needs no shift.
+    import paper_2302_03909_amd as cwt
+    scales = synth.log_scales(1.5, 600.0, 12)
+    plan = cwt.Plan(n, bc, "morlet", scales, param=6.0, precision=precision, host_only=True)
+    band = [ln for ln in plan.describe().splitlines() if ln.startswith("band")]
+    assert band and any("shift=1" in ln for ln in band) == (n % 16 != 0)
+    f = np.random.default_rng(n + 1).standard_normal(n) - 0.1
+    check_full(torch_cuda, f, bc, "morlet", 6.0, scales, precision)
+
+
 @pytest.mark.parametrize("fft_mode", ["segmented", "whole"])
 @pytest.mark.parametrize("n", [2, 3, 17])
 @pytest.mark.parametrize("bc", ["periodic", "zero"])
