@@ -166,6 +166,8 @@ size_t cwt_footprint_bytes(cwt_plan_t plan);
  *   signal:    device, N values, double (CWT_FP64) or float (CWT_FP32).
  *   out:       device, [S][N] row-major; complex values interleaved
  *              (re, im) for Morlet; element type double or float as above.
+ *              Stores are laid out for an output that starts on a 128-byte
+ *              boundary (any element-aligned output gives the same result).
  *   workspace: device, at least cwt_workspace_bytes(plan) bytes, 256-byte
  *              aligned; may be NULL when that size is 0.
  * Errors: CWT_EINVAL for a NULL plan/signal/out, a NULL workspace when one is
