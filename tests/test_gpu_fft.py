@@ -183,3 +183,15 @@ def test_full_size_fp32_4m(torch_cuda, wav, par, bc, fft_mode):
     plan, err = sampled_check(torch_cuda, f, bc, wav, par, scales, "fp32", npos=40, fft_mode=fft_mode)
     print(f"fp32 4M {wav} {bc} {fft_mode} max err", err.max(), "median", np.median(err))
     assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("n,wav,par", [((1 << 22) - 3, "morlet", 6.0), ((1 << 22) - 2, "dog", 2.0)])
+def test_full_size_fp32_rows_off_the_line_grid(torch_cuda, n, wav, par):
+    # the full-size workload with rows that start inside 128-byte lines:
+    # shifted units (complex rows; column pairs), sampled outputs
+    f = synth.lognormal_field(n, seed=synth.SEED_FIELD_4M)
+    scales = synth.log_scales(2.0, 2.0 ** 16, 128)
+    plan, err = sampled_check(torch_cuda, f, "zero", wav, par, scales, "fp32", npos=40)
+    assert "shift=1" in plan.describe()
+    print(f"fp32 N={n} {wav} max err", err.max())
+    assert err.max() <= 1e-5
