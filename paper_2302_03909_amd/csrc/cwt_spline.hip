@@ -285,8 +285,12 @@ __device__ __forceinline__ int stile_idx(int m, int R, int r) { return R * (m + 
 
 // LDS: the S tile (stile doubles), then the tile's taps d' (ntap double2).
 // The launch passes the largest such size over the plan's scales.
+// Registers are budgeted for three waves per SIMD (three workgroups per CU
+// where the S tile allows): stated explicitly, the real form keeps its tap
+// window in fewer registers and both forms schedule their row loads better
+// (about 2 % faster); four would need spills in the tap loop and run slower.
 template <typename OUT, bool CPLX>
-__global__ __launch_bounds__(256) void spl_tap_kernel(int64_t N, int64_t E, const SplineScaleDev *__restrict__ scl,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void spl_tap_kernel(int64_t N, int64_t E, const SplineScaleDev *__restrict__ scl,
                                                       const SplineWork *__restrict__ work,
                                                       const u128 *__restrict__ H, const double2 *__restrict__ dtab,
                                                       const int *__restrict__ fx, OUT *__restrict__ out) {
