@@ -334,8 +334,9 @@ constexpr int seg_kls_elems(int rbytes, int P) {
 // Every column of a real output has a Hermitian P-point spectrum, so
 // Z_{2c} + i Z_{2c+1} inverts to W_{2c} + i W_{2c+1}; each lane then holds two
 // neighbouring outputs and stores them with one 8-byte store, 16 lanes
-// filling a whole 128-byte line (two half lines written by different
-// workgroups stream at about two thirds of the rate).
+// filling a whole 128-byte line (a line written as two 64-byte halves, by two
+// stores of one wave or of two workgroups, streams at about two thirds of the
+// rate).
 // A row that starts inside a line (N not a multiple of the line length) is
 // shifted: for that unit the work item computes columns r0 - dsh .. instead
 // (dsh = the row's offset in its line), so its runs again start on lines.
