@@ -127,7 +127,7 @@ static double cached_h_star(const Wavelet &w, double chi) {
     return h;
 }
 
-static const int kSplineBlock = 1024;  // elements per block of the running sums and the max|f| reduction
+static const int kSplineBlock = 2048;  // elements per block of the running sums and the max|f| reduction (= kSB of the kernels)
 
 void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
     const double chi14 = spline_chi(w, 1e-14);  // truncation used for h* (Table 2 keeps |psi| near 1e-14)
