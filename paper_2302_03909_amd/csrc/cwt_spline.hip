@@ -233,43 +233,35 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
     }
 }
 
-// exclusive scan of the block states: carry[b] = running sums just before block b
-constexpr int kCNT = 1024;
+// exclusive scan of the block states: carry[b] = running sums just before
+// block b.  One wave: each lane combines a contiguous run of states, the
+// lanes' totals are scanned across the wave with shuffles (no barriers), and
+// each lane then writes the carries of its run.
+constexpr int kCNT = 64;
+__device__ __forceinline__ u128 shfl_up_u128(u128 v, int d) {
+    const uint64_t lo = __shfl_up((unsigned long long)(uint64_t)v, d, kCNT);
+    const uint64_t hi = __shfl_up((unsigned long long)(uint64_t)(v >> 64), d, kCNT);
+    return ((u128)hi << 64) | lo;
+}
 __global__ __launch_bounds__(kCNT) void spl_carry_kernel(const Sums *__restrict__ state, int nblk,
                                                          Sums *__restrict__ carry) {
-    __shared__ Sums sc[kCNT];
-    __shared__ int64_t ln[kCNT];
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     const int per = (nblk + kCNT - 1) / kCNT;
-    const int b0 = tid * per, b1 = min(nblk, b0 + per);
+    const int b0 = min(nblk, lane * per), b1 = min(nblk, b0 + per);
     Sums acc = {0, 0, 0, 0};
-    int64_t len = 0;
-    for (int b = b0; b < b1; ++b) {
-        acc = sums_then(acc, state[b], (uint64_t)kSB);
-        len += kSB;
-    }
-    sc[tid] = acc;
-    ln[tid] = len;
-    lds_barrier();
+    for (int b = b0; b < b1; ++b) acc = sums_then(acc, state[b], (uint64_t)kSB);
+    int64_t len = (int64_t)(b1 - b0) * kSB;  // positions acc covers
     for (int d = 1; d < kCNT; d <<= 1) {
-        Sums left;
-        int64_t llen = 0;
-        const bool has = tid >= d;
-        if (has) {
-            left = sc[tid - d];
-            llen = ln[tid - d];
-        }
-        lds_barrier();
-        if (has) {
+        const Sums left = {shfl_up_u128(acc.y1, d), shfl_up_u128(acc.y2, d), shfl_up_u128(acc.y3, d),
+                           shfl_up_u128(acc.y4, d)};
+        const int64_t llen = __shfl_up((long long)len, d, kCNT);
+        if (lane >= d) {
             acc = sums_then(left, acc, (uint64_t)len);
             len += llen;
         }
-        sc[tid] = acc;
-        ln[tid] = len;
-        lds_barrier();
     }
-    Sums st = {0, 0, 0, 0};
-    if (tid > 0) st = sc[tid - 1];
+    Sums st = {shfl_up_u128(acc.y1, 1), shfl_up_u128(acc.y2, 1), shfl_up_u128(acc.y3, 1), shfl_up_u128(acc.y4, 1)};
+    if (lane == 0) st = {0, 0, 0, 0};
     for (int b = b0; b < b1; ++b) {
         carry[b] = st;
         st = sums_then(st, state[b], (uint64_t)kSB);
