@@ -158,6 +158,16 @@ struct ZPow {
 };
 __constant__ ZPow kZ = ZPow();
 
+// lane i gets v of lane i - d of its wave (its own v when i < d)
+__device__ __forceinline__ u128 shfl_up_u128(u128 v, int d) {
+    const uint64_t lo = __shfl_up((unsigned long long)(uint64_t)v, d, 64);
+    const uint64_t hi = __shfl_up((unsigned long long)(uint64_t)(v >> 64), d, 64);
+    return ((u128)hi << 64) | lo;
+}
+__device__ __forceinline__ Sums shfl_up_sums(const Sums &a, int d) {
+    return {shfl_up_u128(a.y1, d), shfl_up_u128(a.y2, d), shfl_up_u128(a.y3, d), shfl_up_u128(a.y4, d)};
+}
+
 // Block b covers array indices [b kSB, (b + 1) kSB), position x = index - E.
 // FINAL = 0: writes the block's running-sum state (from zero) to state[b].
 // FINAL = 1: adds the carry-in carry[b] and writes H[index] (fourth sum).
@@ -170,7 +180,7 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
     constexpr int QS = kSB + 6;             // q on [x0 - 3, x0 + kSB + 3)
     __shared__ double fs[FS];
     __shared__ long long qs[QS];
-    __shared__ Sums scan[kSNT];
+    __shared__ Sums wtot[kSNT / 64];
     const int tid = threadIdx.x;
     const int F = fx[0], bad = fx[1];
     const int64_t l0 = (int64_t)blockIdx.x * kSB;
@@ -202,26 +212,28 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
         loc.y3 += loc.y2;
         loc.y4 += loc.y3;
     }
-    // inclusive scan of the thread states (each covers kSPT positions)
+    // inclusive scan of the thread states (each covers kSPT positions): within
+    // each wave with shuffles, then the totals of the earlier waves in front
+    const int lane = tid & 63, wv = tid >> 6;
     Sums inc = loc;
-    scan[tid] = inc;
-    lds_barrier();
-    for (int d = 1; d < kSNT; d <<= 1) {
-        Sums left;
-        const bool has = tid >= d;
-        if (has) left = scan[tid - d];
-        lds_barrier();
-        if (has) inc = sums_then(left, inc, (uint64_t)(d * kSPT));
-        scan[tid] = inc;
-        lds_barrier();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const Sums left = shfl_up_sums(inc, d);
+        if (lane >= d) inc = sums_then(left, inc, (uint64_t)(d * kSPT));
     }
+    if (lane == 63) wtot[wv] = inc;
+    lds_barrier();
+    Sums pre = {0, 0, 0, 0};  // waves before this one
+    for (int v = 0; v < wv; ++v) pre = sums_then(pre, wtot[v], (uint64_t)(64 * kSPT));
     if (!FINAL) {
-        if (tid == kSNT - 1) state[blockIdx.x] = inc;
+        if (tid == kSNT - 1) state[blockIdx.x] = sums_then(pre, inc, (uint64_t)(64 * kSPT));
         return;
     }
-    // absolute state before this thread's first position
-    Sums st = carry[blockIdx.x];
-    if (tid > 0) st = sums_then(st, scan[tid - 1], (uint64_t)(tid * kSPT));
+    // absolute state before this thread's first position: carry-in, earlier
+    // waves, earlier lanes of this wave
+    const Sums excl = shfl_up_sums(inc, 1);
+    Sums st = sums_then(carry[blockIdx.x], pre, (uint64_t)(wv * 64 * kSPT));
+    if (lane > 0) st = sums_then(st, excl, (uint64_t)(lane * kSPT));
 #pragma unroll
     for (int e = 0; e < kSPT; ++e) {
         st.y1 += (u128)q7v[e];
@@ -238,11 +250,6 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
 // lanes' totals are scanned across the wave with shuffles (no barriers), and
 // each lane then writes the carries of its run.
 constexpr int kCNT = 64;
-__device__ __forceinline__ u128 shfl_up_u128(u128 v, int d) {
-    const uint64_t lo = __shfl_up((unsigned long long)(uint64_t)v, d, kCNT);
-    const uint64_t hi = __shfl_up((unsigned long long)(uint64_t)(v >> 64), d, kCNT);
-    return ((u128)hi << 64) | lo;
-}
 __global__ __launch_bounds__(kCNT) void spl_carry_kernel(const Sums *__restrict__ state, int nblk,
                                                          Sums *__restrict__ carry) {
     const int lane = threadIdx.x;
@@ -252,15 +259,14 @@ __global__ __launch_bounds__(kCNT) void spl_carry_kernel(const Sums *__restrict_
     for (int b = b0; b < b1; ++b) acc = sums_then(acc, state[b], (uint64_t)kSB);
     int64_t len = (int64_t)(b1 - b0) * kSB;  // positions acc covers
     for (int d = 1; d < kCNT; d <<= 1) {
-        const Sums left = {shfl_up_u128(acc.y1, d), shfl_up_u128(acc.y2, d), shfl_up_u128(acc.y3, d),
-                           shfl_up_u128(acc.y4, d)};
+        const Sums left = shfl_up_sums(acc, d);
         const int64_t llen = __shfl_up((long long)len, d, kCNT);
         if (lane >= d) {
             acc = sums_then(left, acc, (uint64_t)len);
             len += llen;
         }
     }
-    Sums st = {shfl_up_u128(acc.y1, 1), shfl_up_u128(acc.y2, 1), shfl_up_u128(acc.y3, 1), shfl_up_u128(acc.y4, 1)};
+    Sums st = shfl_up_sums(acc, 1);
     if (lane == 0) st = {0, 0, 0, 0};
     for (int b = b0; b < b1; ++b) {
         carry[b] = st;
