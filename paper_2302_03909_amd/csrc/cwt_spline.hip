@@ -317,8 +317,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     if (active) {
         // rows in batches of BR: S rows m0..m0+BR-1 need H rows i - 2 .. i + 2,
         // i.e. the BR + 4 rows starting at i0 - nd + m0 - 2, loaded together
-        // (one memory latency per batch)
-        constexpr int BR = 16;
+        // (one memory latency per batch; batches as large as the register
+        // budget of each form allows measured best: 20 rows complex, 24 real)
+        constexpr int BR = CPLX ? 20 : 24;
         const int ch = BR * ((rowsS + BR * ngrp - 1) / (BR * ngrp));
         const int mb = g * ch, me = min(rowsS, mb + ch);
         // H row rho of this column: H[E + r0 + r - 2 + rho delta], read with
