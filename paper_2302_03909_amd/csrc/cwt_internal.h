@@ -56,6 +56,7 @@ struct SegGroup {
     int64_t gtw_off = -1;  // BAND: column factors (w_L^{m g}, or column pairs), g < 16, m in band, bytes
     int32_t colpair = 0;   // BAND, real output: complex column g holds columns 2g, 2g + 1 of one scale
     int32_t cshift = 0;    // BAND: some unit's columns are shifted (SegUnit::dsh); complex staged samples
+    int32_t colodd = 0;    // BAND, column pairs of an odd-length signal: pairs may straddle a row or window edge
     size_t ws_xp_off = 0, ws_x_off = 0;
     int32_t unit0 = 0, nunits = 0;  // BAND: range in Plan::units
     int32_t key = -1;               // LOCAL: index of its KeyDesc
@@ -67,6 +68,7 @@ struct SegGroupDev {
     int32_t lgL, B, nchunk, iters;
     int32_t unit0, nunits;
     int32_t colpair, cshift;
+    int32_t colodd, pad;
     int64_t V, Tg, klo, nseg;
     int64_t xp_off, x_off;  // workspace byte offsets of the partial and reduced band spectra
     int64_t gtw_off;        // byte offset of the column factors in the twiddle allocation

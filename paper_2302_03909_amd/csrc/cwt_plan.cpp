@@ -666,7 +666,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     // store runs start on line boundaries; its spectrum samples are then
     // complex (twice the staging space).
     const int64_t line_e = 128 / ((p.cplx_out ? 2 : 1) * (fp64 ? 8 : 4));
-    const bool may_shift = (p.cplx_out || (!fp64 && p.N % 2 == 0)) && p.N % line_e != 0;
+    const bool may_shift = (p.cplx_out || !fp64) && p.N % line_e != 0;
     for (size_t i = 0; i < band.size();) {
         SegGroup g;
         g.kind = SegGroup::BAND;
@@ -701,14 +701,17 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         // Real FP32 output with rows of at least 32 columns: the inverse packs
         // adjacent columns 2g, 2g + 1 of one scale into one complex column
         // (each column's output is real), so that every lane stores two
-        // neighbouring outputs and a 16-lane run fills a 128-byte line.  Needs
-        // even output offsets (N even; V and Tg multiples of 32, or V = N) and
-        // one unit per scale.  (FP64 runs of 16 columns fill whole lines
-        // already.)
-        g.colpair = p.pair_real && !fp64 && Q >= 32 && p.N % 2 == 0 && (int)js.size() <= kMaxUnits &&
+        // neighbouring outputs and a 16-lane run fills a 128-byte line.  With
+        // the column shift below every pair starts on an even element; for an
+        // odd N a pair can straddle the row end or a window edge, and the
+        // inverse then stores its two outputs separately.  Needs one unit per
+        // scale and V, Tg multiples of 32 (or V = N).  (FP64 runs of 16 columns
+        // fill whole lines already.)
+        g.colpair = p.pair_real && !fp64 && Q >= 32 && (int)js.size() <= kMaxUnits &&
                             (single_segment(p, g) || g.L > 2 * align_halo(g.Tg, 32))
                         ? 1
                         : 0;
+        g.colodd = g.colpair && p.N % 2 != 0 ? 1 : 0;
         frame_group(p, g, g.colpair ? 32 : 16);
         // column chunks of the forward: enough workgroups to fill the device,
         // at most 256 partial sums per bin.  A chunk keeps at least two
@@ -768,6 +771,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             p.units.push_back(un);
         }
         g.nunits = (int32_t)p.units.size() - g.unit0;
+        if (g.colodd) g.cshift = 1;  // the odd-length path reads complex staged samples
         {
             const int64_t need = g.cshift ? 2 * (int64_t)g.nunits : (scale_pairs ? 2 : 1) * (int64_t)g.nunits;
             if (need * g.B > std::max<int64_t>(2 * g.P, kSegKlsBytes / (fp64 ? 8 : 4)))
@@ -796,6 +800,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         gd.nunits = g.nunits;
         gd.colpair = g.colpair;
         gd.cshift = g.cshift;
+        gd.colodd = g.colodd;
         gd.V = g.V;
         gd.Tg = g.Tg;
         gd.klo = g.klo;

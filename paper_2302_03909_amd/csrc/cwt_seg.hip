@@ -375,6 +375,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const int nunits = gd.nunits < MAXU ? gd.nunits : MAXU;
     const bool cp = PAIR && gd.colpair;              // column pairs of one scale (uniform)
     const bool shf = gd.cshift && (CPLX || cp);      // shifted single-row units (uniform)
+    const bool codd = cp && gd.colodd;               // column pairs of an odd-length signal (uniform)
     const int64_t L = int64_t(1) << gd.lgL, Q = L >> log2_exact(P);
     const int sh = 23 - gd.lgL;
     const int tid = threadIdx.x;
@@ -465,9 +466,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const uint32_t obe = (uint32_t)ob * eb;
     const int32_t tlo = (int32_t)gd.Tg, thi = (int32_t)(gd.Tg + gd.V);
     const int32_t Li = (int32_t)L, Qi = (int32_t)Q;
-    auto units_loop = [&](auto cp_const, auto sh_const) {
+    auto units_loop = [&](auto cp_const, auto sh_const, auto odd_const) {
         constexpr bool CP = decltype(cp_const)::value;
         constexpr bool SH = decltype(sh_const)::value;
+        constexpr bool ODD = decltype(odd_const)::value;
         for (int u = 0; u < nunits; ++u) {
             // unit fields are uniform; say so, so that the store descriptors
             // live in scalar registers (no waterfall loop around the stores)
@@ -492,8 +494,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             // output b = ob + t, t = r0 - dsh + col + Q p modulo L (col = cc,
             // or 2 cc and the next one for column pairs); only t < 0 wraps.
             // Kept when Tg <= t < Tg + V; the descriptor of each row spans
-            // exactly its N values, so b >= N is dropped.  Column pairs: t,
-            // Tg, V and N are even, so both outputs are kept or dropped.
+            // exactly its N values, so b >= N is dropped.  Column pairs of an
+            // even N: t, Tg, V and N are even, so both outputs are kept or
+            // dropped.  Odd N (ODD): a pair can straddle the row end or a
+            // window edge, or wrap (t = -1, 0); such a pair is stored as two
+            // single outputs, each kept or dropped on its own.
             const __amdgpu_buffer_rsrc_t ra =
                 make_rsrc(out + (int64_t)sa * N * (CPLX ? 2 : 1), (uint32_t)(N * eb));
             const __amdgpu_buffer_rsrc_t rb =
@@ -502,6 +507,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             const int32_t t0 = (int32_t)r0 - dl;
             auto emit = [&](int cc, int p, C val) {
                 int32_t t = t0 + (CP ? 2 * cc : cc) + Qi * p;
+                if constexpr (ODD) {
+                    int32_t ty = t + 1;
+                    if constexpr (SH) {
+                        t += t < 0 ? Li : 0;
+                        ty += ty < 0 ? Li : 0;
+                    }
+                    const bool kx = t >= tlo && t < thi, ky = ty >= tlo && ty < thi;
+                    // b + 1 < N: the pair lies inside the row
+                    if (kx && ky && ty == t + 1 && (int64_t)ob + ty < N) {
+                        bstore(val, ra, obe + (uint32_t)t * eb);
+                    } else {
+                        bstore(val.x, ra, kx ? obe + (uint32_t)t * eb : kOOB);
+                        bstore(val.y, ra, ky ? obe + (uint32_t)ty * eb : kOOB);
+                    }
+                    return;
+                }
                 if constexpr (SH) t += t < 0 ? Li : 0;
                 const uint32_t off = (t >= tlo && t < thi) ? obe + (uint32_t)t * eb : kOOB;
                 if (CPLX || CP) bstore(val, ra, off);
@@ -517,12 +538,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     using T_ = std::true_type;
     using F_ = std::false_type;
     if constexpr (PAIR) {
-        if (!cp) units_loop(F_{}, F_{});
-        else if (shf) units_loop(T_{}, T_{});
-        else units_loop(T_{}, F_{});
+        if (!cp) units_loop(F_{}, F_{}, F_{});
+        else if (codd) units_loop(T_{}, T_{}, T_{});  // odd N: rows start on odd elements, shifted
+        else if (shf) units_loop(T_{}, T_{}, F_{});
+        else units_loop(T_{}, F_{}, F_{});
     } else {
-        if (shf) units_loop(F_{}, T_{});
-        else units_loop(F_{}, F_{});
+        if (shf) units_loop(F_{}, T_{}, F_{});
+        else units_loop(F_{}, F_{}, F_{});
     }
 }
 

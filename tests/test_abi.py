@@ -157,7 +157,7 @@ def test_segment_groups_of_the_headline_plan():
             assert nchunk == 1 or iters >= 2
 
 
-def test_column_pairs_only_for_real_fp32_output_of_even_length():
+def test_column_pairs_only_for_real_fp32_output():
     scales = np.geomspace(2, 2 ** 16, 128)
 
     def band(n, wav, par, precision):
@@ -169,10 +169,12 @@ def test_column_pairs_only_for_real_fp32_output_of_even_length():
     g = band(1 << 22, "dog", 2.0, "fp32")
     assert g and all(cp == (L // P >= 32) for L, P, cp in g)
     assert any(cp for _, _, cp in g) and not all(cp for _, _, cp in g)
-    # complex output, FP64 or odd N: scale pairs (or single scales) only
+    # odd N: the same groups as the even N next to it (pairs that straddle a
+    # row or window edge are stored as two single outputs)
+    assert band((1 << 22) - 1, "dog", 2.0, "fp32") == band((1 << 22) - 2, "dog", 2.0, "fp32")
+    # complex output or FP64: scale pairs (or single scales) only
     assert not any(cp for _, _, cp in band(1 << 22, "morlet", 6.0, "fp32"))
     assert not any(cp for _, _, cp in band(1 << 20, "dog", 2.0, "fp64"))
-    assert not any(cp for _, _, cp in band((1 << 22) - 1, "dog", 2.0, "fp32"))
 
 
 def test_shifted_units_only_where_rows_start_inside_a_line():
@@ -190,11 +192,11 @@ def test_shifted_units_only_where_rows_start_inside_a_line():
     g = flags((1 << 22) - 3, "morlet", 6.0, "fp32")
     assert sum(sh for _, sh in g) >= len(g) - 2
     assert any(sh for _, sh in flags((1 << 20) - 4, "morlet", 6.0, "fp64"))
-    # real output: column-pair groups shift (N even, not a multiple of 32);
-    # scale-pair groups never do
-    g = flags((1 << 22) - 2, "dog", 2.0, "fp32")
-    assert all(sh == cp for cp, sh in g) and any(cp for cp, _ in g)
-    assert not any(sh for _, sh in flags((1 << 22) - 1, "dog", 2.0, "fp32"))
+    # real output: column-pair groups shift (N not a multiple of 32, odd N
+    # included); scale-pair groups never do
+    for n in ((1 << 22) - 2, (1 << 22) - 1):
+        g = flags(n, "dog", 2.0, "fp32")
+        assert all(sh == cp for cp, sh in g) and any(cp for cp, _ in g)
 
 
 def test_segment_groups_not_merged_for_fp64_or_short_signals():

@@ -85,14 +85,15 @@ def test_parity_mixed(torch_cuda, precision, n, bc, wav, par, scales, fft_mode):
 @pytest.mark.parametrize("n", [20002, 20001])
 def test_real_output_column_pairs(torch_cuda, n, wav, par, bc):
     # Real FP32 output: band groups with rows of >= 32 columns pair adjacent
-    # columns of one scale when N is even, else pair scales; several segments
+    # columns of one scale, for odd N with pairs that straddle the row end,
+    # segment edges and the wrap stored as single outputs; several segments
     # per group, a ragged last segment, a single-segment group, even and odd
     # (imaginary spectrum) wavelets.
     import paper_2302_03909_amd as cwt
     scales = synth.log_scales(1.5, 600.0, 12)
     plan = cwt.Plan(n, bc, wav, scales, param=par, precision="fp32", host_only=True)
     band = [ln for ln in plan.describe().splitlines() if ln.startswith("band")]
-    assert any("colpair=1" in ln for ln in band) == (n % 2 == 0)
+    assert any("colpair=1" in ln for ln in band)
     f = np.random.default_rng(n).standard_normal(n) + 0.2
     check_full(torch_cuda, f, bc, wav, par, scales, "fp32")
 
@@ -185,7 +186,8 @@ def test_full_size_fp32_4m(torch_cuda, wav, par, bc, fft_mode):
     assert err.max() <= 1e-5
 
 
-@pytest.mark.parametrize("n,wav,par", [((1 << 22) - 3, "morlet", 6.0), ((1 << 22) - 2, "dog", 2.0)])
+@pytest.mark.parametrize("n,wav,par", [((1 << 22) - 3, "morlet", 6.0), ((1 << 22) - 2, "dog", 2.0),
+                                       ((1 << 22) - 1, "dog", 2.0)])
 def test_full_size_fp32_rows_off_the_line_grid(torch_cuda, n, wav, par):
     # the full-size workload with rows that start inside 128-byte lines:
     # shifted units (complex rows; column pairs), sampled outputs
