@@ -539,7 +539,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     using F_ = std::false_type;
     if constexpr (PAIR) {
         if (!cp) units_loop(F_{}, F_{}, F_{});
-        else if (codd) units_loop(T_{}, T_{}, T_{});  // odd N: rows start on odd elements, shifted
+        else if (codd) units_loop(T_{}, T_{}, T_{});  // odd N: pairs may straddle edges; always shifted
         else if (shf) units_loop(T_{}, T_{}, F_{});
         else units_loop(T_{}, F_{}, F_{});
     } else {
