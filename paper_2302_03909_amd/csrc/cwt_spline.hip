@@ -305,7 +305,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     const int rowsS = I + ntap;
     double *S = lds;
     double2 *dl = reinterpret_cast<double2 *>(lds + R * (rowsS + rowsS / 16 + 1));
-    for (int k = tid; k < ntap; k += 256) dl[k] = dtab[p.d_off + k];
+    // first 256 taps: loaded now, written to LDS after the S rows (their
+    // latency overlaps the H row loads)
+    const double2 d0 = tid < ntap ? dtab[p.d_off + tid] : make_double2(0.0, 0.0);
     const int64_t nrows = (N + delta - 1) / delta;
     // S rows that some output of the tile uses with a nonzero tap; the H
     // rows of later S rows are clamped (their finite values meet zero taps or
@@ -348,6 +350,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
                 if (m0 + k < me) S[stile_idx(m0 + k, R, r)] = i128_to_double(h[k]);
         }
     }
+    if (tid < ntap) dl[tid] = d0;
+    for (int k = tid + 256; k < ntap; k += 256) dl[k] = dtab[p.d_off + k];
     lds_barrier();
     if (!active) return;
     const int u0 = g * 16;
