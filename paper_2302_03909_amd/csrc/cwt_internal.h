@@ -55,7 +55,7 @@ struct SegGroup {
     int64_t twl_off = -1;  // LOCAL: per-pass LDS twiddle table of size L, bytes
     int64_t gtw_off = -1;  // BAND: column factors (w_L^{m g}, or column pairs), g < 16, m in band, bytes
     int32_t colpair = 0;   // BAND, real output: complex column g holds columns 2g, 2g + 1 of one scale
-    int32_t cshift = 0;    // BAND: some unit's columns are shifted (SegUnit::dsh); complex staged samples
+    int32_t cshift = 0;    // BAND: some unit's columns are shifted (SegUnit::dsh)
     int32_t colodd = 0;    // BAND, column pairs of an odd-length signal: pairs may straddle a row or window edge
     size_t ws_xp_off = 0, ws_x_off = 0;
     int32_t unit0 = 0, nunits = 0;  // BAND: range in Plan::units
@@ -82,7 +82,7 @@ struct SegUnit {
     int64_t ka, kb;  // offsets of their spectrum samples in the spectrum table
     // single-row units: the work item of first column r0 computes columns
     // r0 - dsh .. (modulo the segment), so that the row's store runs start on
-    // 128-byte lines; its spectrum samples carry the factor w_L^{-m dsh}
+    // 128-byte lines; its spectrum samples take the factor w_L^{-m dsh}
     int32_t dsh, pad;
 };
 

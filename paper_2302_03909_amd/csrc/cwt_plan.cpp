@@ -663,10 +663,8 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     // Output elements per 128-byte line: complex rows, and real FP32 rows
     // written as column pairs.  When N is not a multiple of it, rows start
     // inside a line, and the inverse shifts each unit's columns so that its
-    // store runs start on line boundaries; its spectrum samples are then
-    // complex (twice the staging space).
+    // store runs start on line boundaries (a phase applied in registers).
     const int64_t line_e = 128 / ((p.cplx_out ? 2 : 1) * (fp64 ? 8 : 4));
-    const bool may_shift = (p.cplx_out || !fp64) && p.N % line_e != 0;
     for (size_t i = 0; i < band.size();) {
         SegGroup g;
         g.kind = SegGroup::BAND;
@@ -681,10 +679,8 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             if (!js.empty() && (P > pmax || P * 16 > g.L)) break;
             // the inverse stages all spectrum samples of a group in LDS
             int64_t kls_cap = std::max<int64_t>(2 * P, kSegKlsBytes / (fp64 ? 8 : 4));
-            // (a real-wavelet pair takes two tables even when its second scale
-            // is absent; a shifted unit's complex samples take two)
-            int64_t ntab = may_shift ? 2 * ((int64_t)js.size() + 1)
-                                     : ((int64_t)js.size() + 1 + per_unit - 1) / per_unit * per_unit;
+            // (a real-wavelet pair takes two tables even when its second scale is absent)
+            int64_t ntab = ((int64_t)js.size() + 1 + per_unit - 1) / per_unit * per_unit;
             if (!js.empty() && ntab * (nhi - nlo + 1) > kls_cap) break;
             klo = nlo;
             khi = nhi;
@@ -771,9 +767,9 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             p.units.push_back(un);
         }
         g.nunits = (int32_t)p.units.size() - g.unit0;
-        if (g.colodd) g.cshift = 1;  // the odd-length path reads complex staged samples
+        if (g.colodd) g.cshift = 1;  // the odd-length path is a shifted one
         {
-            const int64_t need = g.cshift ? 2 * (int64_t)g.nunits : (scale_pairs ? 2 : 1) * (int64_t)g.nunits;
+            const int64_t need = (scale_pairs ? 2 : 1) * (int64_t)g.nunits;
             if (need * g.B > std::max<int64_t>(2 * g.P, kSegKlsBytes / (fp64 ? 8 : 4)))
                 fail(CWT_EUNSUPPORTED, "internal: band group tables exceed the staging area");
         }

@@ -341,8 +341,9 @@ constexpr int seg_kls_elems(int rbytes, int P) {
 // shifted: for that unit the work item computes columns r0 - dsh .. instead
 // (dsh = the row's offset in its line), so its runs again start on lines.
 // Since W[t] = sum_k Y[k] w_L^{k t} for any t modulo L, the shift only
-// multiplies the unit's spectrum samples by w_L^{-k dsh}, and column r < 0
-// of row p is the output t = r + Q p (+ L when negative).
+// multiplies the unit's spectrum samples by w_L^{-k dsh} (applied in
+// registers, so the staged samples stay real), and column r < 0 of row p is
+// the output t = r + Q p (+ L when negative).
 
 template <typename R, int P, int NT, bool PAIR, bool CPLX>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void seg_inverse_kernel(
@@ -356,10 +357,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     static_assert(NT == P, "one pass-0 butterfly per thread");
     __shared__ C buf[G * LD];
     __shared__ C twl[twl_len(P)];
-    // spectrum samples of the group's units (and pair partners); complex
-    // (shifted units) or real
-    __shared__ C klsc[(KLS + 1) / 2];
-    R *const kls = reinterpret_cast<R *>(klsc);
+    __shared__ R kls[KLS];  // spectrum samples of the group's units (and pair partners)
     const Resolved rv = resolve(a);
     const KeyDesc *kd = &rv.kd;
     const char *__restrict__ ws = rv.bi.ws;
@@ -411,18 +409,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     }
     load_twl<C, P, NT>(twl, static_cast<const C *>(kd->twl));
     // spectrum samples of every unit of the group (and pair partners),
-    // staged in LDS once, eight units per batch of loads; a shifted unit's
-    // samples times w_L^{-m dsh} (complex)
-    if (tid < B && shf) {
-        const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, 0x7ffffff0u);
-        const int64_t mm = gd.klo + tid;
-        for (int u = 0; u < nunits; ++u) {
-            const SegUnit su = cload(units + gd.unit0 + u);
-            const double ka = (double)bload(ktab, kr, (uint32_t)((uni(su.ka) + tid) * (int64_t)sizeof(R)));
-            const double2 ph = w23(whi, wlo, ((-mm * __builtin_amdgcn_readfirstlane(su.dsh)) & (L - 1)) << sh);
-            klsc[u * B + tid] = to_c<C>(make_double2(ph.x * ka, ph.y * ka));
-        }
-    } else if (tid < B) {
+    // staged in LDS once, eight units per batch of loads
+    if (tid < B) {
         const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, 0x7ffffff0u);
         for (int u0 = 0; u0 < nunits; u0 += 8) {
             R ka[8], kb[8];
@@ -470,6 +458,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
         constexpr bool CP = decltype(cp_const)::value;
         constexpr bool SH = decltype(sh_const)::value;
         constexpr bool ODD = decltype(odd_const)::value;
+        // shifted units: the phase w_L^{-m dsh} of the thread's bins
+        // m_r = klo + fro[r], from w_L^{-m_0 dsh} (m_0 = klo + f0, looked up one
+        // unit ahead) by steps w_L^{-NB dsh}, and w_L^{(P - NB) dsh} at the step
+        // where fro wraps past P
+        const int64_t m0 = gd.klo + f0;
+        const int rw = (P - f0 + NB - 1) / NB;  // first r with f0 + r NB >= P
+        // the three phases of unit uu (first bin, step, wrapped step)
+        struct Phases {
+            C first, step, wrap;
+        };
+        auto phases = [&](int uu) {
+            const int d = __builtin_amdgcn_readfirstlane(cload(units + gd.unit0 + uu).dsh);
+            return Phases{to_c<C>(w23(whi, wlo, ((-m0 * d) & (L - 1)) << sh)),
+                          to_c<C>(w23(whi, wlo, ((-(int64_t)NB * d) & (L - 1)) << sh)),
+                          to_c<C>(w23(whi, wlo, (((int64_t)(P - NB) * d) & (L - 1)) << sh))};
+        };
+        Phases ph_next{};
+        if constexpr (SH) ph_next = phases(0);
         for (int u = 0; u < nunits; ++u) {
             // unit fields are uniform; say so, so that the store descriptors
             // live in scalar registers (no waterfall loop around the stores)
@@ -478,16 +484,28 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             const int sb = __builtin_amdgcn_readfirstlane(su.sb);
             const int dl = SH ? __builtin_amdgcn_readfirstlane(su.dsh) : 0;
             C v[16];
+            if constexpr (SH) {
+                // this unit's phases, looked up during the previous unit
+                const Phases cur = ph_next;
+                if (u + 1 < nunits) ph_next = phases(u + 1);
+                C ph = cur.first;
+                const C step = cur.step, wrap = cur.wrap;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                if constexpr (SH) {
-                    v[r] = cmul(xg[r], klsc[u * B + fro[r]]);
-                } else if constexpr (PAIR && !CP) {
-                    const R ka = kls[u * B + fro[r]];
-                    const R kb = kls[nunits * B + u * B + fro[r]];
-                    v[r] = cmul(xg[r], mk<C>(ka, kb));
-                } else {
-                    v[r] = cscale(xg[r], kls[u * B + fro[r]]);
+                for (int r = 0; r < 16; ++r) {
+                    v[r] = cmul(xg[r], cscale(ph, kls[u * B + fro[r]]));
+                    ph = cmul(ph, r + 1 == rw ? wrap : step);
+                }
+            }
+            if constexpr (!SH) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    if constexpr (PAIR && !CP) {
+                        const R ka = kls[u * B + fro[r]];
+                        const R kb = kls[nunits * B + u * B + fro[r]];
+                        v[r] = cmul(xg[r], mk<C>(ka, kb));
+                    } else {
+                        v[r] = cscale(xg[r], kls[u * B + fro[r]]);
+                    }
                 }
             }
             cols_pass0_regs<C, P, G, NT, LD, +1>(buf, v);
