@@ -16,16 +16,19 @@ Contents
   signal, Eq. interp_coeffs, by a banded solve or an FFT division -- not by
   the recursive filter of App. C), ``wavelet_spline_coeffs`` (d of Eq.
   beta3_wavelet_approx_m02), ``ae_m`` (Eq. m02cwt_error), ``h_star`` (the
-  step where AE_M = 5e-4, Sec. 4.4), ``spline_delta`` and
-  ``spline_target`` (the exact CWT of the spline interpolant with the
-  spline wavelet, by Gauss-Legendre quadrature).
+  step where AE_M = 5e-4, Sec. 3.6), ``spline_delta`` and
+  ``spline_step`` (the reading of the step per scale),
+  ``spline_target`` / ``spline_target_h`` / ``spline_target_scale`` (the
+  exact CWT of the spline interpolant with the spline wavelet, by
+  Gauss-Legendre quadrature over the merged knots of both splines).
 
 Readings of the paper that this oracle takes (each is repeated in the
 design notes): scales and positions are in samples; the canonical result is
 the 1/s correlation with conj(psi) as a unit-step sum; chi is the radius
 where |psi| falls below ``rel`` times its maximum; the spline step is
-h_s = delta_s / s with delta_s = max(1, floor(h* s)) so that every knot is
-an integer.
+h_s = delta_s / s with delta_s = floor(h* s) whenever h* s >= 1 (every knot
+of the wavelet spline on a sample), and h* itself below that (knots between
+samples, as the paper keeps h fixed at every scale).
 
 Parity pins: every function above is pinned in ``tests/test_oracle_*.py``
 against closed forms, printed constants of Tables 2 and 3, brute force and
@@ -79,6 +82,9 @@ def _load():
         lib.oracle_spline_target.argtypes = [dp, ctypes.c_long, ctypes.c_long, dp, dp,
                                              ctypes.c_long, ctypes.c_long, ctypes.c_double,
                                              lp, ctypes.c_long, dp, dp, ctypes.c_int]
+        lib.oracle_spline_target_step.argtypes = [dp, ctypes.c_long, ctypes.c_long, dp, dp,
+                                                  ctypes.c_long, ctypes.c_double, ctypes.c_double,
+                                                  lp, ctypes.c_long, dp, dp, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -272,8 +278,19 @@ def spline_h_star(wavelet: str, param: float | None = None) -> float:
 
 
 def spline_delta(hstar: float, s: float) -> int:
-    """Integer sample spacing of the wavelet knots at scale s."""
-    return max(1, int(np.floor(hstar * s)))
+    """Knot spacing of the spline wavelet at scale s in whole samples:
+    delta = floor(h* s) when h* s >= 1 (step h_s = delta / s <= h*), and 0
+    below that, where the step is h* itself and the knots s h* k fall
+    between samples."""
+    return int(np.floor(hstar * s)) if hstar * s >= 1.0 else 0
+
+
+def spline_step(hstar: float, s: float) -> float:
+    """Step h_s of the spline wavelet at scale s: delta / s with delta =
+    floor(h* s) >= 1, else h*.  Either way h_s <= h*, so the wavelet's
+    approximation error AE_M (Eq. m02cwt_error) stays at or below 5e-4."""
+    d = spline_delta(hstar, s)
+    return d / s if d >= 1 else float(hstar)
 
 
 def spline_target(f, boundary: str, wavelet: str, s: float, delta: int, x,
@@ -286,6 +303,60 @@ def spline_target(f, boundary: str, wavelet: str, s: float, delta: int, x,
     d = wavelet_spline_coeffs(wavelet, param, h, nd)
     w = spline_target_d(f, boundary, d, delta, s, x, nthreads)
     return w if is_complex(wavelet) else w.real
+
+
+def spline_target_h(f, boundary: str, wavelet: str, s: float, h: float, x,
+                    param: float | None = None, nthreads: int = 0) -> np.ndarray:
+    """Exact CWT of the spline interpolant f_c with the spline wavelet
+    psi_h at any step h (knots of psi_h((u - x)/s) every s h samples, not
+    necessarily integers), at integer positions x."""
+    ch = chi(wavelet, param, 1e-17)
+    nd = int(np.ceil(ch / h - 2.0)) + 2
+    d = wavelet_spline_coeffs(wavelet, param, h, nd)
+    w = spline_target_step_d(f, boundary, d, s * h, s, x, nthreads)
+    return w if is_complex(wavelet) else w.real
+
+
+def spline_target_scale(f, boundary: str, wavelet: str, s: float, hstar: float, x,
+                        param: float | None = None, nthreads: int = 0) -> np.ndarray:
+    """The spline method's target at scale s for a wavelet of step h*: the
+    step h_s of ``spline_step`` (whole-sample knots above s = 1/h*, step h*
+    below)."""
+    d = spline_delta(hstar, s)
+    if d >= 1:
+        return spline_target(f, boundary, wavelet, s, d, x, param=param, nthreads=nthreads)
+    return spline_target_h(f, boundary, wavelet, s, hstar, x, param=param, nthreads=nthreads)
+
+
+def _spline_ext(f, boundary: str, half: float):
+    """Spline coefficients of f extended over `half` samples beyond each
+    end: (c, c0) with c[i] the coefficient of sample c0 + i."""
+    n = f.size
+    if boundary == "periodic":
+        c, _ = spline_coeffs(f, "periodic")
+        reps = int(np.ceil(half / n)) + 1
+        return np.ascontiguousarray(np.tile(c, 2 * reps + 1)), -reps * n
+    cext, c0 = spline_coeffs(f, "zero", pad=max(48, int(np.ceil(half)) + 8))
+    return np.ascontiguousarray(cext, dtype=np.float64), c0
+
+
+def spline_target_step_d(f, boundary: str, d, step: float, s: float, x,
+                         nthreads: int = 0) -> np.ndarray:
+    """Same as ``spline_target_h`` with explicit wavelet coefficients d[k],
+    k in [-nd, nd], and the knot step s h given in samples (complex128)."""
+    f = np.asarray(f, dtype=np.float64)
+    d = np.asarray(d, dtype=np.complex128)
+    nd = (d.size - 1) // 2
+    cext, c0 = _spline_ext(f, boundary, (nd + 2) * step + 4)
+    dr = np.ascontiguousarray(d.real)
+    di = np.ascontiguousarray(d.imag)
+    xs = np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+    re = np.empty(xs.size)
+    im = np.empty(xs.size)
+    _load().oracle_spline_target_step(_dp(cext), c0, cext.size, _dp(dr), _dp(di), nd, float(step),
+                                      float(s), xs.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                                      xs.size, _dp(re), _dp(im), nthreads)
+    return re + 1j * im
 
 
 def spline_target_d(f, boundary: str, d, delta: int, s: float, x,

@@ -24,11 +24,14 @@
  *     and beta3_wavelet_approx_m02): with f_c = sum_n c[n] beta3(u-n) the
  *     cubic-spline interpolant of the signal and
  *     psi_h(y) = sum_k d[k] beta3(y/h - k) the spline approximation of the
- *     wavelet at step h = delta/s (delta a positive integer),
+ *     wavelet at step h,
  *         W_spl(s,x) = (1/s) * integral f_c(u) conj(psi_h((u-x)/s)) du.
- *     All knots of both factors are integers, so the integrand is a
- *     polynomial of degree 6 on every unit interval and 4-point
- *     Gauss-Legendre quadrature on each interval is exact.
+ *     The knots of f_c are the integers and those of psi_h((u-x)/s) are
+ *     x + s h k, k integer.  Between two consecutive knots of the merged set
+ *     the integrand is a polynomial of degree 6, so 4-point Gauss-Legendre
+ *     quadrature on each such piece is exact.  oracle_spline_target takes
+ *     an integer knot step s h = delta (every knot an integer, one piece per
+ *     unit interval); oracle_spline_target_step takes any real step s h.
  *
  * Wavelets (unit L2 norm; FT convention psi^(w) = int psi(x) e^{-iwx} dx):
  *   kind 0  Morlet(w0): C (e^{i w0 x} - e^{-w0^2/2}) e^{-x^2/2},
@@ -307,6 +310,83 @@ int oracle_spline_target(const double *c, long c0, long nc,
                     ti[cnt] = -w * fc * pi;
                     ++cnt;
                 }
+            }
+            out_re[i] = pw_sum(tr, cnt);
+            out_im[i] = pw_sum(ti, cnt);
+        }
+        free(tr);
+        free(ti);
+    }
+    return 0;
+}
+
+/*
+ * W_spl(s, x) for a real knot step `step` = s h of the wavelet spline (any
+ * step > 0, in samples).  Arguments as for oracle_spline_target.  For each
+ * output the integration range |u - x| <= (Nd + 2) step is cut at the
+ * integers and at the points x + step k; every piece gets 4-point
+ * Gauss-Legendre nodes, and the two cubic splines are evaluated there from
+ * the knot interval that holds the piece's midpoint.
+ */
+int oracle_spline_target_step(const double *c, long c0, long nc,
+                              const double *d_re, const double *d_im, long Nd,
+                              double step, double s, const long *x, long nx,
+                              double *out_re, double *out_im, int nthreads) {
+    static const double gx[4] = {-0.8611363115940526, -0.3399810435848563,
+                                 0.3399810435848563, 0.8611363115940526};
+    static const double gw[4] = {0.3478548451374538, 0.6521451548625461,
+                                 0.6521451548625461, 0.3478548451374538};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    const double half = (double)(Nd + 2) * step; /* support radius */
+    const long maxpieces = 2 * (long)ceil(half) + 2 * (Nd + 2) + 8;
+#pragma omp parallel
+    {
+        double *tr = (double *)malloc(sizeof(double) * maxpieces * 4);
+        double *ti = (double *)malloc(sizeof(double) * maxpieces * 4);
+#pragma omp for schedule(dynamic, 8)
+        for (long i = 0; i < nx; ++i) {
+            const double xi = (double)x[i];
+            const double lo = xi - half, hi = xi + half;
+            /* two sorted knot sequences: integers in (lo, hi), and
+             * xi + step k for k = -(Nd+2)..Nd+2 (the first and last are lo
+             * and hi themselves) */
+            long nint = (long)floor(lo) + 1; /* next integer above lo */
+            long k = -(Nd + 2) + 1;
+            double a = lo;
+            long cnt = 0;
+            while (a < hi) {
+                double bi = (double)nint;
+                double bk = (k <= Nd + 2) ? xi + step * (double)k : hi;
+                double b = bi < bk ? bi : bk;
+                if (b > hi) b = hi;
+                if (bi <= b) ++nint;
+                if (bk <= b) ++k;
+                if (b > a) {
+                    const double mid = 0.5 * (a + b), hw = 0.5 * (b - a);
+                    const long nf = (long)floor(mid);
+                    const long kf = (long)floor((mid - xi) / step);
+                    for (int q = 0; q < 4; ++q) {
+                        const double u = mid + hw * gx[q];
+                        double fc = 0.0;
+                        for (long np = nf - 1; np <= nf + 2; ++np)
+                            fc += coef(c, c0, nc, np) * beta3(u - (double)np);
+                        const double y = (u - xi) / step;
+                        double pr = 0.0, pi = 0.0;
+                        for (long kk = kf - 1; kk <= kf + 2; ++kk) {
+                            if (kk < -Nd || kk > Nd) continue;
+                            const double bb = beta3(y - (double)kk);
+                            pr += d_re[kk + Nd] * bb;
+                            pi += d_im[kk + Nd] * bb;
+                        }
+                        const double wq = hw * gw[q] / s;
+                        tr[cnt] = wq * fc * pr;
+                        ti[cnt] = -wq * fc * pi;
+                        ++cnt;
+                    }
+                }
+                a = b;
             }
             out_re[i] = pw_sum(tr, cnt);
             out_im[i] = pw_sum(ti, cnt);

@@ -7,13 +7,13 @@ path and the CPU oracle consume what it returns.
 Workloads (all seeded with numpy's PCG64):
 
 * ``tones_noise`` -- a periodic three-tone signal plus white noise.  The
-  paper's own accuracy tests use a periodic sum of tones (Sec. 5, Eq.
+  paper's own accuracy tests use a periodic sum of tones (Sec. 4, Eq.
   signal_f1); the tone frequencies here are 40, 300 and 900 cycles per 4096
   samples, scaled with the length.
 * ``lognormal_field`` -- a non-periodic 1D density-like field
   delta = exp(g - sigma^2/2) - 1 with g a Gaussian random field of power
   spectrum P(k) ~ k^-1.5 exp(-(k/k_c)^2).  It stands in for the 1D density
-  fields of Sec. 6 (Eq. nonlinear_dens), which are also synthetic; the
+  fields of Sec. 5 (Eq. nonlinear_dens), which are also synthetic; the
   paper's own field parameters are not given in the text.
 * ``log_scales`` -- scales a * (b/a)^(j/(S-1)), j = 0..S-1, both ends
   included (the paper discretises scales evenly in log, Sec. 3.1).

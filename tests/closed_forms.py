@@ -135,3 +135,36 @@ def numeric_ft(psi_fn, w, half=14.0, step=1.0 / 512):
         ww = w[i0:i0 + 256]
         out[i0:i0 + 256] = (np.exp(-1j * np.outer(ww, x)) @ px) * step
     return out
+
+
+def bspline3_hat(nu):
+    """Fourier transform of the cubic B-spline: (sin(nu/2) / (nu/2))^4."""
+    nu = np.asarray(nu, dtype=np.float64)
+    return np.sinc(nu / (2 * np.pi)) ** 4
+
+
+def spline_tone_target(d, h, s, n, k, x):
+    """Spline-method target for the periodic tone f[t] = e^{2 pi i k t/n}:
+    W(x) = (1/s) int f_c(u) conj(psi_h((u - x)/s)) du in the Fourier domain.
+
+    The periodic spline coefficients are c[t] = f[t] / B(w), B(w) =
+    (4 + 2 cos w)/6 the sampled cubic B-spline's symbol, w = 2 pi k/n; by
+    Poisson summation f_c(u) = sum_q A_q e^{i nu_q u} with nu_q = w + 2 pi q,
+    A_q = bhat(nu_q) / B(w), bhat the B-spline's transform.  The spline
+    wavelet psi_h(y) = sum_j d[j] beta3(y/h - j) has the transform
+    h D(nu h) bhat(nu h), D(theta) = sum_j d[j] e^{-i j theta}.  Hence
+    W(x) = sum_q A_q e^{i nu_q x} conj(h D(s h nu_q) bhat(s h nu_q)).
+    The terms fall off like q^-8; |q| <= 600 is kept."""
+    d = np.asarray(d, dtype=np.complex128)
+    nd = (d.size - 1) // 2
+    j = np.arange(-nd, nd + 1)
+    w = 2 * np.pi * k / n
+    q = np.arange(-600, 601)
+    nu = w + 2 * np.pi * q
+    amp = bspline3_hat(nu) / ((4.0 + 2.0 * math.cos(w)) / 6.0)
+    th = s * h * nu
+    dsym = np.exp(-1j * np.outer(th, j)) @ d
+    hat = h * dsym * bspline3_hat(th)
+    coef = amp * np.conj(hat)
+    x = np.asarray(x, dtype=np.float64)
+    return np.exp(1j * np.outer(x, nu)) @ coef

@@ -12,7 +12,7 @@ def per_scale_rel_l2(got, ref, floor=1e-3):
 
 
 def error_spectrum_percent(got, ref):
-    """ES of Sec. 5.1 (Eq. error_spectrum): per-scale L1 error relative to the
+    """ES of Sec. 4.1 (Eq. error_spectrum): per-scale L1 error relative to the
     reference, in percent."""
     got = np.asarray(got)
     ref = np.asarray(ref)

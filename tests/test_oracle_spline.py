@@ -82,7 +82,7 @@ def test_h_star_table3(golden):
 
 def test_cbsw_exact_target_identity():
     # CBSW = C (2 beta3(x) - beta3(x+1) - beta3(x-1)) (Table 2) is its own spline
-    # approximation at h = 1 (Sec. 4.4): at s = 1, delta = 1 the target is
+    # approximation at h = 1 (Sec. 3.6): at s = 1, delta = 1 the target is
     # sum_n c[n] sum_k d[k] beta7(x + k - n) (App. B, Eq. two_betas).
     rng = np.random.default_rng(9)
     n = 64
@@ -197,3 +197,114 @@ def test_box_identity_exact(delta):
     for _ in range(4):
         e = [sum(e[i - j] for j in range(delta) if i - j >= 0) for i in range(n)]
     assert g == e
+
+
+_HSTAR = {}
+
+
+def _hstar(wav, par):
+    key = (wav, par)
+    if key not in _HSTAR:
+        _HSTAR[key] = oracle.spline_h_star(wav, par)
+    return _HSTAR[key]
+
+
+@pytest.mark.parametrize("wav,par,scales", [
+    ("morlet", 6.0, [0.6, 2.0, 5.5, 8.0, 30.0]),
+    ("mexhat", None, [0.5, 1.7, 2.6, 9.0]),
+    ("dog", 4.0, [0.8, 3.1, 12.0]),
+])
+def test_spline_target_tone_closed_form(wav, par, scales):
+    # Periodic tones against the Fourier-domain form of the spline target
+    # (tests/closed_forms.spline_tone_target): pins the quadrature over the
+    # merged knots at steps s h between samples (h* s < 1, knot step h*) and
+    # on whole samples (h* s >= 1), including the periodic extension of c.
+    n = 256
+    hs = _hstar(wav, par)
+    x = np.arange(n)
+    for s in scales:
+        h = oracle.spline_step(hs, s)
+        nd = int(math.ceil(oracle.chi(wav, par) / h - 2.0)) + 2
+        d = oracle.wavelet_spline_coeffs(wav, par, h, nd)
+        for k in (3, 40, 101):
+            f = np.cos(2 * np.pi * k * x / n)
+            got = oracle.spline_target_scale(f, "periodic", wav, s, hs, x, param=par)
+            ref = 0.5 * (cf.spline_tone_target(d, h, s, n, k, x) + cf.spline_tone_target(d, h, s, n, -k, x))
+            if not oracle.is_complex(wav):
+                assert np.max(np.abs(ref.imag)) < 1e-13
+                ref = ref.real
+            # |f| <= 1 and int |psi_h(y)| dy is of order one: errors are
+            # measured against max(|W|, 1), as for the direct sum's tones
+            scale = max(np.max(np.abs(ref)), 1.0)
+            assert np.max(np.abs(got - ref)) / scale < 1e-12, (s, k, np.max(np.abs(got - ref)) / scale)
+
+
+@pytest.mark.parametrize("wav,par,s", [("mexhat", None, 1.9), ("morlet", 6.0, 2.3), ("dog", 4.0, 0.7)])
+def test_spline_target_fractional_knots_brute_force(wav, par, s):
+    # h* s < 1: the knots of psi_h((u - x)/s) sit every s h* samples, between
+    # the integers.  Adaptive quadrature over every piece between consecutive
+    # knots of the merged set, on a tiny zero-boundary signal.
+    rng = np.random.default_rng(14)
+    n = 10
+    f = rng.standard_normal(n)
+    h = _hstar(wav, par)
+    assert h * s < 1.0
+    step = s * h
+    nd = int(math.ceil(oracle.chi(wav, par) / h - 2.0)) + 2
+    d = oracle.wavelet_spline_coeffs(wav, par, h, nd)
+    c, c0 = oracle.spline_coeffs(f, "zero")
+
+    def fc(u):
+        m0 = int(math.floor(u))
+        return sum(c[m - c0] * cf.beta_n(3, u - m) for m in range(m0 - 1, m0 + 3) if 0 <= m - c0 < c.size)
+
+    xs = [0, 4, 9]
+    got = oracle.spline_target_h(f, "zero", wav, s, h, xs, param=par)
+    for i, x in enumerate(xs):
+        half = (nd + 2) * step
+        knots = sorted(set([x - half, x + half] + list(range(math.floor(x - half) + 1, math.ceil(x + half)))
+                           + [x + step * kk for kk in range(-nd - 2, nd + 3)]))
+        knots = [v for v in knots if x - half <= v <= x + half]
+
+        def g(u, part):
+            v = fc(u) * np.conj(oracle.spline_approx(d, 1.0, np.array([(u - x) / step]))[0])
+            return v.real if part == 0 else v.imag
+        vr = sum(integrate.quad(g, a, b, args=(0,), epsabs=1e-16, epsrel=1e-13)[0]
+                 for a, b in zip(knots[:-1], knots[1:])) / s
+        if oracle.is_complex(wav):
+            vi = sum(integrate.quad(g, a, b, args=(1,), epsabs=1e-16, epsrel=1e-13)[0]
+                     for a, b in zip(knots[:-1], knots[1:])) / s
+            ref = vr + 1j * vi
+        else:
+            ref = vr
+        assert abs(got[i] - ref) < 1e-13 * max(1.0, abs(ref)), (x, got[i], ref)
+
+
+@pytest.mark.parametrize("wav,par", [("morlet", 6.0), ("mexhat", None), ("dog", 4.0)])
+def test_spline_step_keeps_ae_m_at_most_5e4(wav, par):
+    # Eq. m02cwt_error: the step of every scale is at most h*, so the
+    # wavelet's approximation error stays within the 5e-4 that fixes h*
+    # (Sec. 3.6, Table 3), also below s = 1/h* where the knots leave the
+    # sample grid.
+    hs = _hstar(wav, par)
+    ch = oracle.chi(wav, par, oracle.SPLINE_CHI_REL)
+
+    def fn(x):
+        return oracle.psi(wav, par, x)
+    for s in (0.3, 0.99 / hs, 1.0 / hs, 1.01 / hs, 2.5 / hs, 7.2 / hs, 40.0 / hs):
+        h = oracle.spline_step(hs, s)
+        assert 0.5 * hs < h <= hs
+        assert oracle.ae_m(fn, ch, h) <= 5e-4 * (1 + 1e-6), (s, h)
+
+
+def test_spline_target_step_equals_integer_knots():
+    # The merged-knot quadrature with an integer step reduces to the
+    # unit-interval quadrature of oracle_spline_target (same integrand, the
+    # pieces coincide).
+    rng = np.random.default_rng(21)
+    f = rng.standard_normal(300)
+    for wav, par, s, delta in (("morlet", 6.0, 20.0, 2), ("mexhat", None, 11.0, 4)):
+        x = np.arange(0, 300, 7)
+        a = oracle.spline_target(f, "zero", wav, s, delta, x, param=par)
+        b = oracle.spline_target_h(f, "zero", wav, s, delta / s, x, param=par)
+        assert np.max(np.abs(a - b)) <= 1e-14 * max(1.0, np.max(np.abs(a)))
