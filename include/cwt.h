@@ -24,17 +24,23 @@
  *                        beta3_wavelet_approx_m02, beta3_signal, m02_cwt,
  *                        cumsum4_coeffs): the exact CWT of the cubic-spline
  *                        interpolant of the samples with the cubic-spline
- *                        approximation of the wavelet at step h_s = delta_s/s,
- *                        delta_s = max(1, floor(h* s)), h* the step where the
- *                        approximation error of Eq. m02cwt_error is 5e-4
- *                        (the wavelet's truncation radius taken where |psi|
- *                        falls below 1e-14 of its maximum).  Its coefficients
- *                        d_s interpolate psi(h_s k), |k| <= N_d with N_d =
- *                        ceil(chi / h_s - 2) + 2, chi at 1e-17.  The running
- *                        sums of Eq. cumsum4_coeffs are exact (128-bit
- *                        fixed point), so the result matches that exact
- *                        spline CWT to FP64 rounding at any N; the output is
- *                        FP64 or FP32 (precision), the arithmetic FP64.
+ *                        approximation of the wavelet at step h_s <= h*, h*
+ *                        the step where the approximation error of Eq.
+ *                        m02cwt_error is 5e-4 (Sec. 3.6, Table 3; the
+ *                        wavelet's truncation radius taken where |psi| falls
+ *                        below 1e-14 of its maximum).  Where h* s >= 1,
+ *                        h_s = delta_s / s with the whole-sample knot
+ *                        spacing delta_s = floor(h* s), and the tap sum runs
+ *                        on the running sums of Eq. cumsum4_coeffs, taken
+ *                        exactly (128-bit fixed point); where h* s < 1,
+ *                        h_s = h* (knots between samples) and the output is
+ *                        a sum of exact taps over the interpolant's
+ *                        coefficients.  The wavelet coefficients d_s
+ *                        interpolate psi(h_s k), |k| <= N_d with N_d =
+ *                        ceil(chi / h_s - 2) + 2, chi at 1e-17.  The result
+ *                        matches that exact spline CWT to FP64 rounding at
+ *                        any N; the output is FP64 or FP32 (precision), the
+ *                        arithmetic FP64.
  *
  * Wavelets (unit L2 norm, psi^(w) = int psi(x) e^{-iwx} dx):
  *   CWT_MORLET(w0): C (e^{i w0 x} - e^{-w0^2/2}) e^{-x^2/2} (complex output;
@@ -126,23 +132,33 @@ typedef struct {
  * cwt_plan -- build a plan for signals of N samples and the S scales in
  * `scales` (host array of S doubles, copied).  Output row j belongs to
  * scales[j].  `opts` may be NULL (FP64, FFT method).
+ * What is planned: Sec. 3.1 (FFTCWT: the signal transform of Eq. FT_signal
+ * and, per scale, the product and inverse of Eq. discrete_CWT_conv, with
+ * the wavelet spectrum evaluated once here) or Sec. 3.3 (M02CWT: h*, the
+ * per-scale steps and the coefficients d_s of Eq.
+ * beta3_wavelet_approx_m02, chosen by Eq. m02cwt_error as in Sec. 3.6).
  * Errors: CWT_EINVAL for N < 2, S < 1, a scale that is not finite and > 0,
  * omega0 <= 0 or not finite, a DOG order that is not an integer in [1, 16],
  * an unknown kind/boundary/precision/method, out == NULL or scales == NULL;
  * CWT_EUNSUPPORTED for N > 2^26, S > 65536, an fft_len that is too short or
  * not of the supported form, or (spline method) a knot spacing delta_s
  * above about 2^18.4 (the 128-bit running sums then keep fewer than 40
- * fixed-point bits), more
- * than 3601 wavelet coefficients at one scale, or N + 2 (N_d + 3) delta_s
- * above 2^31;
+ * fixed-point bits), more than 3601 wavelet coefficients at one scale, or
+ * N + 2 E above 2^27 with E = max over the scales of (N_d + 3) delta_s + 16
+ * (the tap kernel addresses the running sums with 32-bit byte offsets);
  * CWT_ENOMEM / CWT_EDEVICE on allocation or HIP failures.
  * On failure *out is set to NULL.
  */
 int cwt_plan(cwt_plan_t *out, int64_t N, int32_t boundary, cwt_wavelet wavelet,
              const double *scales, int32_t S, const cwt_opts *opts);
 
-/* Destroys a plan (NULL is accepted).  The caller must ensure no stream is
- * still using it. */
+/* Destroys a plan (NULL is accepted).  Work of the plan that is still
+ * queued is not disturbed: the plan's device tables are released in stream
+ * order after the last cwt_exec / cwt_exec_batch call enqueued with the
+ * plan on each stream (tables allocated outside the stream-ordered arena
+ * are released after a host wait for those calls).  Calls captured into a
+ * HIP graph are not tracked: keep the plan alive while such a graph may be
+ * launched. */
 int cwt_destroy(cwt_plan_t plan);
 
 /* 1 if the output is complex (Morlet), 0 if real; negative on error. */
@@ -162,7 +178,11 @@ size_t cwt_workspace_bytes(cwt_plan_t plan);
 size_t cwt_footprint_bytes(cwt_plan_t plan);
 
 /*
- * cwt_exec -- enqueue the transform on `stream`.
+ * cwt_exec -- enqueue the transform on `stream`: the signal's spectrum, the
+ * per-scale spectral products and their inverses (Sec. 3.1, Eqs. FT_signal
+ * and discrete_CWT_conv, in overlap-save segments or on the whole signal),
+ * or the spline method's prefilter (Eq. interp_coeffs), running sums (Eq.
+ * cumsum4_coeffs) and tap sums (Eq. m02_cwt) (Sec. 3.3).
  *   signal:    device, N values, double (CWT_FP64) or float (CWT_FP32).
  *   out:       device, [S][N] row-major; complex values interleaved
  *              (re, im) for Morlet; element type double or float as above.
@@ -175,11 +195,14 @@ size_t cwt_footprint_bytes(cwt_plan_t plan);
  * launch fails.  NaN/Inf in the signal propagate; they are not checked.
  * The call only enqueues kernels and event dependencies (no allocation, no
  * host copy), so it may be captured into a HIP graph.  Part of the work may
- * run on a second stream of the calling thread, forked from `stream` and
- * joined back into it before the call returns; that stream and its two
- * events are created on the thread's first call, so run one call before
+ * run on a second stream paired with `stream` (one per calling thread,
+ * device and caller stream), forked from `stream` and joined back into it
+ * before the call returns; that stream and its two events are created on
+ * the first call with that caller stream, so run one call before
  * capturing.  The plan is only read, so calls on different streams with
- * different workspaces may overlap.
+ * different workspaces may overlap entirely.  Outside graph capture the
+ * call also records an event on `stream` that orders the plan's release
+ * (cwt_destroy).
  */
 int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace,
              void *stream);
@@ -202,15 +225,20 @@ int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals,
  *   cwt_plan_fft_len:      length of the whole-signal FFT (0 if the plan
  *                          never needs it).
  *   cwt_plan_spline_delta: fills delta[j] (S entries) with the integer knot
- *                          spacing delta_j of the spline method (0 for plans
- *                          of the FFT method).
- *   cwt_plan_spline_taps:  fills taps[j] with 2 N_d + 1, the number of
- *                          wavelet coefficients d_s of scale j (0 for the
- *                          FFT method).
+ *                          spacing delta_j of the spline method, 0 where the
+ *                          knots fall between samples (h* s < 1) and for
+ *                          plans of the FFT method.
+ *   cwt_plan_spline_taps:  fills taps[j] with the taps per output of scale
+ *                          j: 2 N_d + 1 wavelet coefficients d_s on the
+ *                          running sums, or 2 T + 1 exact taps on the
+ *                          interpolant's coefficients, T = ceil((N_d + 2)
+ *                          s h*) + 2 (0 for the FFT method).
  *   cwt_plan_spline_hstar: h* of the plan's wavelet (0 for the FFT method).
  *   cwt_plan_scale_path:   fills path[j] with how scale j is computed:
  *                          0 = segmented FFT (overlap-save), 1 = band-limited
- *                          inverse of the whole-signal spectrum, 2 = spline.
+ *                          inverse of the whole-signal spectrum, 2 = spline
+ *                          on the running sums, 3 = spline with exact taps
+ *                          (h* s < 1).
  */
 int64_t cwt_plan_fft_len(cwt_plan_t plan);
 int cwt_plan_spline_delta(cwt_plan_t plan, int32_t *delta);
@@ -222,7 +250,8 @@ int cwt_plan_scale_path(cwt_plan_t plan, int32_t *path);
  * cwt_plan_describe -- a text summary of the plan (one line per segment
  * group: local or band, segment length L, band transform size P, band bins
  * B, halo, outputs per segment, segments, column chunks, scales; one line
- * per band launch with its work item counts).  Writes at most size bytes
+ * per band launch with its work item counts; for the spline method one line
+ * per scale: knot spacing, tile columns R and rows I, taps, exact taps).  Writes at most size bytes
  * including the terminating NUL into buf (host memory, owned by the
  * caller); returns the full length of the text, or CWT_EINVAL for a NULL
  * plan or a NULL buf with size > 0.

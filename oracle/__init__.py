@@ -10,6 +10,9 @@ Contents
 * ``cwt`` / ``cwt_points`` -- the direct O(N * chi * s) sum (Sec. 3,
   Eq. discreteCWT with the 1/s correlation normalisation), in plain C with
   OpenMP (``cwt_oracle.c``).
+* ``cwt_spectral_rows`` -- the same sum row by row as an FFT circular
+  convolution with the sampled wavelet (scipy.fft as a library primitive),
+  for full-length references at sizes the direct sum cannot reach.
 * ``psi`` / ``chi`` -- the mother wavelets in the time domain.
 * Spline method (Sec. 3.3, App. B, App. C):
   ``spline_coeffs`` (cubic-spline interpolation coefficients c of the
@@ -153,6 +156,46 @@ def cwt_points(f, boundary: str, wavelet: str, scales, scale_idx, pos,
                               ps.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), si.size,
                               _dp(re), _dp(im) if im is not None else None, nthreads)
     return re + 1j * im if im is not None else re
+
+
+def cwt_spectral_rows(f, boundary: str, wavelet: str, scales, param: float | None = None,
+                      rel: float = 1e-17, workers: int = -1, rows=None):
+    """The same transform as ``cwt`` (the unit-step sum of Sec. 3, Eq.
+    discreteCWT), one row at a time, as a circular convolution done with
+    FFTs: W_j = f_ext (*) r_j with r_j[-t] = conj(psi(t / s_j)) / s_j for
+    |t| <= floor(chi s_j) (time-domain samples, wrapped onto the period N for
+    a periodic signal; zero-padded to a length M >= N + T_max + 1 for a zero
+    boundary, where the circular convolution equals the linear one on
+    [0, N)).  Yields (j, row) for the requested rows (all by default).  For
+    full-length checks where the direct sum is too slow; pinned against
+    ``cwt`` in the tests."""
+    import scipy.fft as sf
+    kind, p = _wavelet(wavelet, param)
+    f = np.asarray(f, dtype=np.float64)
+    n = f.size
+    sc = np.asarray(scales, dtype=np.float64)
+    ch = chi(wavelet, param, rel)
+    rows = range(sc.size) if rows is None else rows
+    tmax = max(int(np.floor(ch * sc[j])) for j in rows)
+    if boundary == "periodic":
+        m = n
+    else:
+        m = sf.next_fast_len(n + tmax + 1)
+    fp = np.zeros(m)
+    fp[:n] = f
+    cplx = kind == MORLET
+    ff = sf.fft(fp, workers=workers) if cplx else sf.rfft(fp, workers=workers)
+    for j in rows:
+        s = float(sc[j])
+        t = np.arange(-int(np.floor(ch * s)), int(np.floor(ch * s)) + 1)
+        k = np.conj(psi(wavelet, param, t / s)) / s
+        r = np.zeros(m, dtype=np.complex128 if cplx else np.float64)
+        np.add.at(r, (-t) % m, k)       # images wrap onto the period
+        if cplx:
+            w = sf.ifft(ff * sf.fft(r, workers=workers), workers=workers)[:n]
+        else:
+            w = sf.irfft(ff * sf.rfft(r, workers=workers), n=m, workers=workers)[:n]
+        yield j, w
 
 
 # --------------------------------------------------------------------------

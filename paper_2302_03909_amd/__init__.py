@@ -25,7 +25,7 @@ CWT_MORLET, CWT_MEXHAT, CWT_DOG = 0, 1, 2
 CWT_FP64, CWT_FP32 = 0, 1
 CWT_METHOD_FFT, CWT_METHOD_SPLINE = 0, 1
 CWT_OK, CWT_EINVAL, CWT_EUNSUPPORTED, CWT_ENOMEM, CWT_EDEVICE = 0, -1, -2, -3, -4
-PATH_LOCAL, PATH_COLUMN, PATH_SPLINE = 0, 1, 2
+PATH_LOCAL, PATH_COLUMN, PATH_SPLINE, PATH_SPLINE_DIRECT = 0, 1, 2, 3
 
 
 class CwtError(RuntimeError):

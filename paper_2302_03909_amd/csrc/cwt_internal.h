@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace cwt {
@@ -16,7 +19,7 @@ enum LoadMode : int32_t {
                         // n >= M - T, 0 between (periodic, FFT length != N)
 };
 
-enum ScalePath : int32_t { PATH_LOCAL = 0, PATH_COLUMN = 1, PATH_SPLINE = 2 };
+enum ScalePath : int32_t { PATH_LOCAL = 0, PATH_COLUMN = 1, PATH_SPLINE = 2, PATH_SPLINE_DIRECT = 3 };
 
 // One overlap-save group: scales that share the segment FFT length L and the
 // halo Tg; V = L - 2 Tg outputs per segment.
@@ -182,12 +185,16 @@ struct ColumnLaunch {
 // workgroups per compute unit.
 constexpr int kSegKlsBytes = 14336;
 
-// Spline method (Sec. 3.3 with integer knot spacing, see cwt_spline.hip).
-// Per scale: knot spacing delta, wavelet coefficients d'[n] = conj(d[n - nd]) /
-// (5040 s delta^3), n < ntap (2 nd + 1 taps, zero-padded to a multiple of 8),
-// and the tile shape: R columns (consecutive positions) x I rows (stride delta).
+// Spline method (Sec. 3.3, see cwt_spline.hip).  Per scale, a tap sum
+// W[x] = sum_n d'[n] S[x + (n - nd) delta] with the tile shape R columns
+// (consecutive positions) x I rows (stride delta):
+//   mode 0 (integer knot spacing delta): S the exact box sums of the running
+//     sums, d'[n] = conj(d[n - nd]) / (5040 s delta^3), 2 nd + 1 taps;
+//   mode 1 (knots between samples, delta = 1): S = c, the spline
+//     coefficients, d'[n] = Omega_s(n - nd), the exact taps, 2 nd + 1 taps.
+// Taps are zero-padded to ntap, a multiple of 8.
 struct SplineScaleDev {
-    int32_t delta, nd, ntap, R, I, pad;
+    int32_t delta, nd, ntap, R, I, mode;
     int64_t d_off;  // complex FP64 elements into the plan's coefficient table
 };
 
@@ -196,6 +203,19 @@ struct SplineScaleDev {
 struct SplineWork {
     int32_t j, r0, R, pad;
     int64_t i0;
+};
+
+// an event owned by every plan whose last call on a stream it follows
+struct UseEvent {
+    hipEvent_t ev = nullptr;
+    UseEvent() {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+    }
+    ~UseEvent() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+    UseEvent(const UseEvent &) = delete;
+    UseEvent &operator=(const UseEvent &) = delete;
 };
 
 struct Plan {
@@ -233,7 +253,9 @@ struct Plan {
     double hstar = 0.0;
     std::vector<SplineScaleDev> spl;
     std::vector<SplineWork> spl_work;
-    std::vector<int32_t> spl_delta;
+    std::vector<int32_t> spl_delta;  // delta per scale, 0 where the knots fall between samples
+    std::vector<int32_t> spl_ntaps;  // taps per output per scale (2 N_d + 1, or the exact-tap count)
+    bool spl_direct = false;         // some scale runs exact taps on c (workspace holds c)
     int64_t spl_E = 0;      // the running sums cover positions [-E, N + E)
     int64_t spl_len = 0;    // N + 2E
     int32_t spl_qbits = 0;  // bits of the fixed-point coefficients
@@ -242,7 +264,7 @@ struct Plan {
     int64_t spl_lds_bytes = 0;  // LDS of the tap-sum launch (largest tile plus its taps)
     SplineScaleDev *d_spl = nullptr;
     SplineWork *d_spl_work = nullptr;
-    size_t ws_maxp_off = 0, ws_fx_off = 0, ws_state_off = 0, ws_carry_off = 0, ws_H_off = 0;
+    size_t ws_maxp_off = 0, ws_fx_off = 0, ws_state_off = 0, ws_carry_off = 0, ws_H_off = 0, ws_C_off = 0;
 
     // device tables (owned).  Segmented plans keep all of them in one
     // allocation, d_arena; the pointers below then point into it.
@@ -266,6 +288,12 @@ struct Plan {
     bool timing = false;
     std::vector<TimingRec> timing_recs;
     std::vector<hipEvent_t> event_pool;
+
+    // release ordering: per stream, an event recorded after the plan's last
+    // call enqueued on it (calls under graph capture are not recorded); one
+    // batched call shares one event among all its plans
+    std::mutex use_mu;
+    std::vector<std::pair<hipStream_t, std::shared_ptr<UseEvent>>> last_use;
 
     size_t ws_bytes = 0;
     size_t ws_F_off = 0, ws_Y_off = 0;  // workspace layout (FFT method)

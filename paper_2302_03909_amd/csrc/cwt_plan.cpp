@@ -522,7 +522,8 @@ static int64_t align_halo(int64_t t, int64_t a = 16) { return (t + a - 1) & ~(a 
 // Stream of the calling thread for plan construction and release
 // (non-blocking, default priority): plan tables are allocated, filled and
 // freed in its order, so building or destroying a plan never waits for the
-// work other streams are running.
+// work other streams are running (release waits for the plan's own calls
+// only, through the events of note_use).
 static hipStream_t plan_stream() {
     static thread_local hipStream_t st = nullptr;
     if (!st) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -954,16 +955,54 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     HIPCHK(hipStreamSynchronize(pst));
 }
 
+static hipStream_t plan_stream();
+
+// Records, on `st`, that the plan's work enqueued so far on that stream must
+// finish before its tables are released.  Skipped while `st` is capturing a
+// graph: a graph keeps no claim on the plan, so the caller keeps the plan
+// alive while the graph may still be launched.
+static bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+static std::shared_ptr<UseEvent> record_use(hipStream_t st) {
+    auto e = std::make_shared<UseEvent>();
+    if (!e->ev) fail(CWT_EDEVICE, "hipEventCreateWithFlags failed");
+    HIPCHK(hipEventRecord(e->ev, st));
+    return e;
+}
+static void note_use(Plan &p, hipStream_t st, const std::shared_ptr<UseEvent> &e) {
+    std::lock_guard<std::mutex> g(p.use_mu);
+    for (auto &u : p.last_use)
+        if (u.first == st) {
+            u.second = e;
+            return;
+        }
+    if (p.last_use.size() >= 16) {
+        // bound the list: the oldest stream's last call is waited for here
+        HIPCHK(hipEventSynchronize(p.last_use.front().second->ev));
+        p.last_use.erase(p.last_use.begin());
+    }
+    p.last_use.push_back({st, e});
+}
+static void note_use(Plan &p, hipStream_t st) {
+    if (!capturing(st)) note_use(p, st, record_use(st));
+}
+
 static void free_plan(Plan *p) {
     if (!p) return;
     if (p->d_arena) {
-        // every table of a segmented plan sits in the arena (stream-ordered
-        // release: the caller guarantees no stream still uses the plan)
+        // every table of a segmented plan sits in the arena; its stream-ordered
+        // release waits for the plan's last call on every stream that used it
         try {
-            (void)hipFreeAsync(p->d_arena, plan_stream());
+            hipStream_t pst = plan_stream();
+            for (auto &e : p->last_use) (void)hipStreamWaitEvent(pst, e.second->ev, 0);
+            (void)hipFreeAsync(p->d_arena, pst);
         } catch (...) {
+            for (auto &e : p->last_use) (void)hipEventSynchronize(e.second->ev);
             (void)hipFree(p->d_arena);
         }
+        p->last_use.clear();
         for (void *x : p->d_extra)
             if (x) (void)hipFree(x);
         for (auto &r : p->timing_recs) {
@@ -974,6 +1013,9 @@ static void free_plan(Plan *p) {
         delete p;
         return;
     }
+    // separately allocated tables: wait for the plan's last calls first
+    for (auto &e : p->last_use) (void)hipEventSynchronize(e.second->ev);
+    p->last_use.clear();
     if (p->d_tab) (void)hipFree(p->d_tab);
     if (p->d_tw_all) (void)hipFree(p->d_tw_all);
     if (p->d_dtab) (void)hipFree(p->d_dtab);
@@ -1101,22 +1143,24 @@ static void for_each_seg_launch(const Plan &p, F &&fn) {
     }
 }
 
-// Second stream of the calling thread on the current device (non-blocking,
-// default priority) with a fork/join event pair.  The local-group kernels of
-// a call run on it while the band kernels (forward, reduce, inverse, which
-// depend on each other) run on the caller's stream: the two chains write
-// disjoint output rows and only read the signal, and running them side by
-// side lets one chain's latency-bound phases (segment loads and transforms,
-// launch tails) overlap the other's output stores.
+// Second stream paired with the caller's stream (one per calling thread,
+// device and caller stream; non-blocking, default priority) with a
+// fork/join event pair.  The local-group kernels of a call run on it while
+// the band kernels (forward, reduce, inverse, which depend on each other) run
+// on the caller's stream: the two chains write disjoint output rows and only
+// read the signal, and running them side by side lets one chain's
+// latency-bound phases (segment loads and transforms, launch tails) overlap
+// the other's output stores.  Calls on different caller streams get
+// different side streams, so nothing orders them against each other.
 struct SideStream {
     hipStream_t st = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
 };
-static SideStream &side_stream() {
-    static thread_local std::map<int, SideStream> m;
+static SideStream &side_stream(hipStream_t caller) {
+    static thread_local std::map<std::pair<int, hipStream_t>, SideStream> m;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    SideStream &s = m[dev];
+    SideStream &s = m[std::make_pair(dev, caller)];
     if (!s.st) {
         HIPCHK(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
@@ -1135,7 +1179,7 @@ struct SegStreams {
     SideStream *ss = nullptr;
     SegStreams(hipStream_t st, bool split) : main(st), side(st) {
         if (!split) return;
-        ss = &side_stream();
+        ss = &side_stream(st);
         side = ss->st;
         HIPCHK(hipEventRecord(ss->fork, main));
         HIPCHK(hipStreamWaitEvent(side, ss->fork, 0));
@@ -1270,6 +1314,7 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, vo
                        [&] { return cwt::launch_spline(p, signal, out, workspace, st, 0); });
             cwt::timed(p, st, cwt::spline_kernel_name(p, 1), nn * p.S * eb, "spline taps launch",
                        [&] { return cwt::launch_spline(p, signal, out, workspace, st, 1); });
+            cwt::note_use(p, st);
             return CWT_OK;
         }
         const double fb = p.precision == CWT_FP64 ? 16.0 : 8.0;
@@ -1308,6 +1353,7 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, vo
             cwt::timed(p, st, cwt::column_kernel_name(p, c), band + nn * rows * eb, "column launch",
                        [&] { return cwt::launch_column(p, c, workspace, out, st); });
         }
+        cwt::note_use(p, st);
         return CWT_OK;
     });
 }
@@ -1494,6 +1540,13 @@ int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals, void *co
                            [&] { return cwt::launch_seg_kernel(m.id, a, m.blocks, ks); });
             }
             ss.end();
+            // one event after the merged launches orders the release of every
+            // segmented plan of the batch
+            if (!cwt::capturing(st)) {
+                const auto ev = cwt::record_use(st);
+                for (int32_t i = 0; i < n; ++i)
+                    if (cwt::seg_plan(*plans[i]->p)) cwt::note_use(*plans[i]->p, st, ev);
+            }
         }
         for (int32_t i = 0; i < n; ++i) {
             if (cwt::seg_plan(*plans[i]->p)) continue;
@@ -1516,7 +1569,7 @@ int cwt_plan_spline_delta(cwt_plan_t plan, int32_t *delta) {
 int cwt_plan_spline_taps(cwt_plan_t plan, int32_t *taps) {
     if (!plan || !taps) return CWT_EINVAL;
     const Plan &p = *plan->p;
-    for (int j = 0; j < p.S; ++j) taps[j] = p.method == CWT_METHOD_SPLINE ? 2 * p.spl[j].nd + 1 : 0;
+    for (int j = 0; j < p.S; ++j) taps[j] = p.method == CWT_METHOD_SPLINE ? p.spl_ntaps[j] : 0;
     return CWT_OK;
 }
 
@@ -1542,8 +1595,12 @@ int cwt_plan_describe(cwt_plan_t plan, char *buf, size_t size) {
     for (const auto &l : p.seg_launches)
         add("launch P=%d groups=%zu forward=%zu reduce=%zu inverse=%zu\n", l.P, l.gdev.size(), l.fwd.size(),
             l.red.size(), l.inv.size());
-    if (p.method == CWT_METHOD_SPLINE)
+    if (p.method == CWT_METHOD_SPLINE) {
         add("spline h*=%.6f E=%lld tiles=%zu\n", p.hstar, (long long)p.spl_E, p.spl_work.size());
+        for (int j = 0; j < p.S; ++j)
+            add("spline scale=%d delta=%d R=%d I=%d taps=%d exact=%d\n", j, p.spl[j].delta, p.spl[j].R, p.spl[j].I,
+                p.spl_ntaps[j], p.spl[j].mode);
+    }
     if (size) {
         const size_t n = std::min(size - 1, s.size());
         std::memcpy(buf, s.data(), n);

@@ -1,4 +1,10 @@
-// cwt_spline.hip -- spline method (Sec. 3.3), integer knot spacing.
+// cwt_spline.hip -- spline method (Sec. 3.3).
+//
+// Scales with h* s >= 1 use an integer knot spacing delta (below); scales
+// with h* s < 1 keep the step h* and sum exact taps over the spline
+// coefficients c themselves, W[x] = sum_t Omega_s(t) c[x + t] (the taps are
+// built with the plan), in the same tap kernel with delta = 1 and c read in
+// place of the box sums.
 //
 // With psi_h(y) = sum_n d[n] beta3(y/h - n) (Eq. beta3_wavelet_approx_m02) and
 // f_c = sum_k c[k] beta3(u - k) (Eq. beta3_signal), the transform
@@ -26,7 +32,7 @@
 //   spl_maxabs   partial max |f| per block of 1024 samples
 //   spl_exponent F = qbits - e, 3 max|f| = m 2^e, 0.5 <= m < 1  (|c| <= 3 max|f|)
 //   spl_sums<0>  per block: c (61-tap FIR, Eq. interp_coeffs), q, q7, local
-//                running-sum state
+//                running-sum state; c 2^F stored when a scale sums exact taps
 //   spl_carry    exclusive scan of the block states
 //   spl_sums<1>  per block: the fourth running sum H of q7, stored (16 B each)
 //   spl_tap      per (scale, tile): S from H (5 loads, exact), FP64 taps
@@ -171,11 +177,12 @@ __device__ __forceinline__ Sums shfl_up_sums(const Sums &a, int d) {
 // Block b covers array indices [b kSB, (b + 1) kSB), position x = index - E.
 // FINAL = 0: writes the block's running-sum state (from zero) to state[b].
 // FINAL = 1: adds the carry-in carry[b] and writes H[index] (fourth sum).
+// C (FINAL = 0, may be null): c 2^F at every index of the block.
 template <typename R, int FINAL>
 __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f, int64_t N, int periodic, int64_t E,
                                                         int64_t len, const int *__restrict__ fx,
                                                         Sums *__restrict__ state, const Sums *__restrict__ carry,
-                                                        u128 *__restrict__ H) {
+                                                        u128 *__restrict__ H, double *__restrict__ C) {
     constexpr int FS = kSB + 6 + 2 * kFIR;  // samples on [x0 - 3 - kFIR, x0 + kSB + 3 + kFIR)
     constexpr int QS = kSB + 6;             // q on [x0 - 3, x0 + kSB + 3)
     __shared__ double fs[FS];
@@ -195,7 +202,9 @@ __global__ __launch_bounds__(kSNT) void spl_sums_kernel(const R *__restrict__ f,
 #pragma unroll
         for (int t = 1; t <= kFIR; ++t) c = fma(kZ.v[t], fc[-t] + fc[t], c);
         c *= 1.7320508075688772935;
-        qs[k] = bad ? 0ll : (long long)rint(ldexp(c, F));
+        const double cf = bad ? 0.0 : ldexp(c, F);
+        qs[k] = (long long)rint(cf);
+        if (!FINAL && C != nullptr && k >= 3 && k < kSB + 3 && l0 + k - 3 < len) C[l0 + k - 3] = cf;
     }
     lds_barrier();
     // 5040 beta7 * q at this thread's positions, local running sums
@@ -290,7 +299,8 @@ __device__ __forceinline__ int stile_idx(int m, int R, int r) { return R * (m + 
 template <typename OUT, bool CPLX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void spl_tap_kernel(int64_t N, int64_t E, const SplineScaleDev *__restrict__ scl,
                                                       const SplineWork *__restrict__ work,
-                                                      const u128 *__restrict__ H, const double2 *__restrict__ dtab,
+                                                      const u128 *__restrict__ H, const double *__restrict__ C,
+                                                      const double2 *__restrict__ dtab,
                                                       const int *__restrict__ fx, OUT *__restrict__ out) {
     extern __shared__ double lds[];
     const SplineWork w = work[blockIdx.x];
@@ -316,7 +326,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     const int64_t rho_max = w.i0 - nd + mvalid + 1;
     const int F = fx[0];
     const int bad = fx[1];
-    if (active) {
+    if (active && p.mode == 1) {
+        // exact taps on c: S row m is c 2^F at position i0 - nd + m (R = 1,
+        // delta = 1, every thread active); rows past the last one some
+        // output uses are clamped
+        const double *cp = C + (E + w.i0 - nd);
+        for (int m = tid; m < rowsS; m += 256) S[stile_idx(m, 1, 0)] = cp[min(m, mvalid - 1)];
+    } else if (active) {
         // rows in batches of BR: S rows m0..m0+BR-1 need H rows i - 2 .. i + 2,
         // i.e. the BR + 4 rows starting at i0 - nd + m0 - 2, loaded together
         // (one memory latency per batch; batches as large as the register
@@ -450,14 +466,15 @@ static hipError_t spline_sums(const Plan &p, const R *f, char *ws, hipStream_t s
     Sums *state = reinterpret_cast<Sums *>(ws + p.ws_state_off);
     Sums *carry = reinterpret_cast<Sums *>(ws + p.ws_carry_off);
     u128 *H = reinterpret_cast<u128 *>(ws + p.ws_H_off);
+    double *C = p.spl_direct ? reinterpret_cast<double *>(ws + p.ws_C_off) : nullptr;
     const int periodic = p.boundary == CWT_PERIODIC;
     hipLaunchKernelGGL(spl_maxabs_kernel<R>, dim3(p.spl_nb0), dim3(kSNT), 0, st, f, p.N, part);
     hipLaunchKernelGGL(spl_exponent_kernel, dim3(1), dim3(kSNT), 0, st, part, p.spl_nb0, p.spl_qbits, fx);
     hipLaunchKernelGGL((spl_sums_kernel<R, 0>), dim3(p.spl_nblk), dim3(kSNT), 0, st, f, p.N, periodic, p.spl_E,
-                       p.spl_len, fx, state, carry, H);
+                       p.spl_len, fx, state, carry, H, C);
     hipLaunchKernelGGL(spl_carry_kernel, dim3(1), dim3(kCNT), 0, st, state, p.spl_nblk, carry);
     hipLaunchKernelGGL((spl_sums_kernel<R, 1>), dim3(p.spl_nblk), dim3(kSNT), 0, st, f, p.N, periodic, p.spl_E,
-                       p.spl_len, fx, state, carry, H);
+                       p.spl_len, fx, state, carry, H, nullptr);
     return hipGetLastError();
 }
 
@@ -465,15 +482,16 @@ template <typename OUT>
 static hipError_t spline_taps(const Plan &p, char *ws, void *out, hipStream_t st) {
     const int *fx = reinterpret_cast<const int *>(ws + p.ws_fx_off);
     const u128 *H = reinterpret_cast<const u128 *>(ws + p.ws_H_off);
+    const double *C = p.spl_direct ? reinterpret_cast<const double *>(ws + p.ws_C_off) : nullptr;
     const double2 *dt = reinterpret_cast<const double2 *>(p.d_dtab);
     const dim3 grid((unsigned)p.spl_work.size());
     const size_t lds = (size_t)p.spl_lds_bytes;
     if (p.cplx_out)
         hipLaunchKernelGGL((spl_tap_kernel<OUT, true>), grid, dim3(256), lds, st, p.N, p.spl_E, p.d_spl, p.d_spl_work,
-                           H, dt, fx, reinterpret_cast<OUT *>(out));
+                           H, C, dt, fx, reinterpret_cast<OUT *>(out));
     else
         hipLaunchKernelGGL((spl_tap_kernel<OUT, false>), grid, dim3(256), lds, st, p.N, p.spl_E, p.d_spl, p.d_spl_work,
-                           H, dt, fx, reinterpret_cast<OUT *>(out));
+                           H, C, dt, fx, reinterpret_cast<OUT *>(out));
     return hipGetLastError();
 }
 

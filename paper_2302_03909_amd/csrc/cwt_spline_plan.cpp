@@ -1,12 +1,22 @@
 // cwt_spline_plan.cpp -- host side of the spline method (Sec. 3.3, App. B,
-// App. C, Eq. m02cwt_error).
+// App. C, Sec. 3.6 Eq. m02cwt_error).
 //
 // Per plan: h*, the largest knot step whose spline wavelet reaches the
-// accuracy AE_M = 5e-4 (Eq. m02cwt_error, Table 3).  Per scale s: the integer
-// knot spacing delta = max(1, floor(h* s)) in samples, h_s = delta / s, the
-// wavelet coefficients d_s (Eq. beta3_wavelet_approx_m02, computed as Eq.
-// interp_coeffs on the samples psi(h_s k)), N_d = ceil(chi / h_s - 2) + 2
-// taps on each side, and the tiling of the tap-sum launch.
+// accuracy AE_M = 5e-4 (Eq. m02cwt_error, Table 3).  Per scale s, the step
+// h_s of the wavelet spline psi_h (Eq. beta3_wavelet_approx_m02, its
+// coefficients d_s computed as Eq. interp_coeffs on the samples psi(h_s k),
+// N_d = ceil(chi / h_s - 2) + 2 on each side):
+//   h* s >= 1: h_s = delta / s with the integer knot spacing
+//              delta = floor(h* s) in samples (h_s in (h*/2, h*]); the tap
+//              sum runs on the exact box sums of the running sums;
+//   h* s <  1: h_s = h*, the paper's fixed step, whose knots s h* k fall
+//              between samples.  W[x] = sum_t c[x + t] Omega_s(t) with the
+//              exact taps Omega_s(t) = (1/s) int beta3(v - t)
+//              conj(psi_h(v / s)) dv on the spline coefficients c (Eq.
+//              beta3_signal), evaluated here by Gauss-Legendre quadrature
+//              over the merged knots; |t| <= (N_d + 2) s h* + 2.
+// Either way h_s <= h*, so AE_M <= 5e-4 at every scale.  Also the tiling of
+// the tap-sum launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -127,6 +137,41 @@ static double cached_h_star(const Wavelet &w, double chi) {
     return h;
 }
 
+// Omega_s(t) = (1/s) int beta3(v - t) conj(psi_h(v / s)) dv for |t| <= Tt:
+// both factors are cubic between consecutive points of the merged knot set
+// (the integers and s h k), so 4-point Gauss-Legendre on each piece is exact.
+static std::vector<cd> exact_taps(const std::vector<cd> &d, int K, int nd, double h, double s, int Tt) {
+    static const double gx[4] = {-0.86113631159405257522, -0.33998104358485626480, 0.33998104358485626480,
+                                 0.86113631159405257522};
+    static const double gw[4] = {0.34785484513745385737, 0.65214515486254614263, 0.65214515486254614263,
+                                 0.34785484513745385737};
+    // the spline with its coefficients truncated to |k| <= nd
+    std::vector<cd> dt(d.size(), cd(0.0));
+    for (int k = -nd; k <= nd; ++k) dt[(size_t)(k + K)] = d[(size_t)(k + K)];
+    const double step = s * h;
+    std::vector<cd> om(2 * (size_t)Tt + 1);
+    for (int t = -Tt; t <= Tt; ++t) {
+        const double lo = t - 2.0, hi = t + 2.0;
+        std::vector<double> cut;
+        for (int i = t - 2; i <= t + 2; ++i) cut.push_back((double)i);
+        for (long k = (long)std::ceil(lo / step); (double)k * step < hi; ++k)
+            if ((double)k * step > lo) cut.push_back((double)k * step);
+        std::sort(cut.begin(), cut.end());
+        cd acc = 0.0;
+        for (size_t i = 0; i + 1 < cut.size(); ++i) {
+            const double a = cut[i], b = cut[i + 1];
+            if (!(b > a)) continue;
+            const double mid = 0.5 * (a + b), hw = 0.5 * (b - a);
+            for (int q = 0; q < 4; ++q) {
+                const double v = mid + hw * gx[q];
+                acc += hw * gw[q] * bspline3(v - (double)t) * std::conj(spline_eval(dt, K, h, v / s));
+            }
+        }
+        om[(size_t)(t + Tt)] = acc / s;
+    }
+    return om;
+}
+
 static const int kSplineBlock = 2048;  // elements per block of the running sums and the max|f| reduction (= kSB of the kernels)
 
 void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
@@ -141,25 +186,46 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
 
     std::vector<cd> dtab;
     int64_t delta_max = 1, E = 16;
+    p.spl_ntaps.assign(p.S, 0);
+    p.spl_direct = false;
     for (int j = 0; j < p.S; ++j) {
         const double s = p.scales[j];
         const double fl = std::floor(p.hstar * s);
         if (fl > 1e9) fail(CWT_EUNSUPPORTED, "spline method: scale too large");
-        const int64_t delta = std::max<int64_t>(1, (int64_t)fl);
-        const double h = (double)delta / s;
+        const bool direct = fl < 1.0;  // knots between samples: exact taps on c
+        const int64_t delta = direct ? 1 : (int64_t)fl;
+        const double h = direct ? p.hstar : (double)delta / s;
         const int nd = (int)std::ceil(chi17 / h - 2.0) + 2;
         if (nd > 1800) fail(CWT_EUNSUPPORTED, "spline method: more than 3601 wavelet coefficients at this scale");
         const int K = std::max(nd, (int)std::ceil(chi17 / h)) + 40;
         const std::vector<cd> dk = wavelet_coeffs(w, h, K);
-        const int ntap = (2 * nd + 1 + 7) / 8 * 8;
         SplineScaleDev &sc = p.spl[j];
-        sc.delta = (int32_t)delta;
-        sc.nd = nd;
-        sc.ntap = ntap;
         sc.d_off = (int64_t)dtab.size();
-        const double kscale = 1.0 / (5040.0 * s * (double)delta * (double)delta * (double)delta);
-        for (int n = 0; n < ntap; ++n)
-            dtab.push_back(n <= 2 * nd ? std::conj(dk[(size_t)(K - nd + n)]) * kscale : cd(0.0));
+        int ntap;
+        if (direct) {
+            // W[x] = sum_{|t| <= Tt} Omega_s(t) c[x + t], run as a tap sum of
+            // spacing 1 over c itself (tap n <-> t = n - Tt)
+            const int Tt = (int)std::ceil((double)(nd + 2) * h * s) + 2;
+            const std::vector<cd> om = exact_taps(dk, K, nd, h, s, Tt);
+            ntap = (2 * Tt + 1 + 7) / 8 * 8;
+            sc.delta = 1;
+            sc.nd = Tt;
+            sc.mode = 1;
+            for (int n = 0; n < ntap; ++n) dtab.push_back(n <= 2 * Tt ? om[(size_t)n] : cd(0.0));
+            p.spl_ntaps[j] = 2 * Tt + 1;
+            p.spl_direct = true;
+            E = std::max<int64_t>(E, (int64_t)Tt + 16);
+        } else {
+            ntap = (2 * nd + 1 + 7) / 8 * 8;
+            sc.delta = (int32_t)delta;
+            sc.nd = nd;
+            sc.mode = 0;
+            const double kscale = 1.0 / (5040.0 * s * (double)delta * (double)delta * (double)delta);
+            for (int n = 0; n < ntap; ++n)
+                dtab.push_back(n <= 2 * nd ? std::conj(dk[(size_t)(K - nd + n)]) * kscale : cd(0.0));
+            p.spl_ntaps[j] = 2 * nd + 1;
+        }
+        sc.ntap = ntap;
         // tile: R <= 16 columns x I = 16 floor(256 / R) rows; the S tile holds
         // R (I + ntap) values plus one spare row per 16, and the taps follow it
         auto tile_fits = [&](int r) {
@@ -173,7 +239,6 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
         const int R = (int)((delta + nck - 1) / nck);
         sc.R = R;
         sc.I = 16 * (256 / R);
-        sc.pad = 0;
         {
             const int64_t rows_s = sc.I + ntap;
             const int64_t lds = 8 * (int64_t)R * (rows_s + rows_s / 16 + 1) + 16 * (int64_t)ntap;
@@ -192,6 +257,11 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
                 wk.i0 = i0;
                 p.spl_work.push_back(wk);
             }
+        if (direct) {
+            p.spl_delta[j] = 0;
+            p.path[j] = PATH_SPLINE_DIRECT;
+            continue;
+        }
         p.spl_delta[j] = (int32_t)delta;
         delta_max = std::max(delta_max, delta);
         E = std::max<int64_t>(E, (int64_t)(nd + 3) * delta + 16);
@@ -224,6 +294,7 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
     p.ws_state_off = take((size_t)p.spl_nblk * 64);
     p.ws_carry_off = take((size_t)p.spl_nblk * 64);
     p.ws_H_off = take((size_t)p.spl_len * 16);
+    p.ws_C_off = p.spl_direct ? take((size_t)p.spl_len * 8) : 0;
     p.ws_bytes = ws;
     if (p.host_only) return;
 

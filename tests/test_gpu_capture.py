@@ -30,7 +30,7 @@ def test_exec_graph_replays_match_eager(torch_cuda, wavelet, param):
     assert paths == {cwt.PATH_LOCAL, cwt.PATH_COLUMN}, "the plan must take both kernel chains"
     f = torch.as_tensor(synth.lognormal_field(n, seed=11).astype(np.float32), device="cuda")
     ws = plan.empty_workspace()
-    ref = plan(f, plan.empty_output(), ws)  # eager (also creates the second stream before capture)
+    ref = plan(f, plan.empty_output(), ws)  # eager
     torch.cuda.synchronize()
     # another plan's eager work between replays
     other = cwt.Plan(5000, "periodic", "mexhat", [2.0, 17.0, 90.0], precision="fp32")
@@ -38,6 +38,10 @@ def test_exec_graph_replays_match_eager(torch_cuda, wavelet, param):
     g_out = other.empty_output()
     out = plan.empty_output()
     side = torch.cuda.Stream()
+    # one eager call on the capture stream creates its paired second stream
+    with torch.cuda.stream(side):
+        plan(f, out, ws)
+    torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=side):
         plan(f, out, ws)

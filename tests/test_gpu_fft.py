@@ -2,8 +2,10 @@
 
 Bars (per-scale relative L2 with a floor, see tests/helpers.py): 1e-10 for
 FP64 plans, 1e-5 for FP32 plans.  FP32 references use the FP32-rounded input
-promoted to FP64.  Small cases compare every output; the full-size workloads
-compare sampled outputs the oracle computes one by one."""
+promoted to FP64.  Small cases compare every output with the direct sum; the
+full-size segmented workloads compare every output with the oracle's FFT form
+of the same sum (certified against the direct sum at sampled outputs), and
+the whole-signal mode at sampled outputs the oracle computes one by one."""
 import math
 
 import numpy as np
@@ -164,36 +166,101 @@ def sampled_check(torch, f, bc, wav, par, scales, precision, npos=48, seed=0, ff
     return plan, err
 
 
-@pytest.mark.parametrize("fft_mode", ["segmented", "whole"])
-def test_full_size_fp64_mexhat_1m(torch_cuda, fft_mode):
-    # N = 2^20 zero-boundary lognormal field, Mexican hat, 64 log scales 2..2^14, FP64
+def full_rows_check(torch, f, bc, wav, par, scales, precision):
+    """Every output of every scale against the oracle's FFT form of the sum
+    (``cwt_spectral_rows``), itself checked against the direct sum at the
+    first, last and 6 random positions of every 16th scale."""
+    import os
+    plan, w = gpu_cwt(torch, f, bc, wav, par, scales, precision)
+    fr = ref_input(f, precision)
+    n = f.size
+    workers = min(16, os.cpu_count() or 1)
+    nrm = np.empty(len(scales))
+    dif = np.empty(len(scales))
+    cert_rows = list(range(0, len(scales), 16)) + [len(scales) - 1]
+    rng = np.random.default_rng(5)
+    cert_pos = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 6)]))
+    cert = {}
+    for j, row in oracle.cwt_spectral_rows(fr, bc, wav, scales, param=par, workers=workers):
+        got = w[j].cpu().numpy().astype(row.dtype)
+        nrm[j] = np.linalg.norm(row)
+        dif[j] = np.linalg.norm(got - row)
+        if j in cert_rows:
+            cert[j] = row[cert_pos]
+    del w
+    torch.cuda.empty_cache()
+    err = dif / np.maximum(nrm, 1e-3 * nrm.max())
+    si = np.repeat(cert_rows, cert_pos.size)
+    ps = np.tile(cert_pos, len(cert_rows))
+    direct = oracle.cwt_points(fr, bc, wav, scales, si, ps, param=par, nthreads=workers)
+    spec = np.concatenate([cert[j] for j in cert_rows])
+    assert np.max(np.abs(direct - spec)) <= 1e-12 * np.max(nrm / math.sqrt(n)) * 10
+    return plan, err
+
+
+def print_table(tag, scales, err):
+    print(f"{tag}: per-scale rel L2, max {err.max():.3e} median {np.median(err):.3e}")
+    for j0 in range(0, len(scales), 8):
+        print("  " + " ".join(f"s={scales[j]:.4g}:{err[j]:.1e}" for j in range(j0, min(j0 + 8, len(scales)))))
+
+
+def test_full_size_fp64_mexhat_1m_all_outputs(torch_cuda):
+    # N = 2^20 zero-boundary lognormal field, Mexican hat, 64 log scales
+    # 2..2^14, FP64, segmented: every output
     f = synth.lognormal_field(1 << 20, seed=synth.SEED_FIELD_1M)
     scales = synth.log_scales(2.0, 2.0 ** 14, 64)
-    plan, err = sampled_check(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", fft_mode=fft_mode)
-    print("fp64 1M max err", err.max(), "M", plan.fft_len)
+    plan, err = full_rows_check(torch_cuda, f, "zero", "mexhat", None, scales, "fp64")
+    print_table("fp64 1M mexhat zero", scales, err)
     assert err.max() <= 1e-10
 
 
-@pytest.mark.parametrize("fft_mode", ["segmented", "whole"])
+def test_full_size_fp64_mexhat_1m_whole(torch_cuda):
+    f = synth.lognormal_field(1 << 20, seed=synth.SEED_FIELD_1M)
+    scales = synth.log_scales(2.0, 2.0 ** 14, 64)
+    plan, err = sampled_check(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", fft_mode="whole")
+    print("fp64 1M whole max err", err.max(), "M", plan.fft_len)
+    assert err.max() <= 1e-10
+
+
 @pytest.mark.parametrize("bc", ["zero", "periodic"])
 @pytest.mark.parametrize("wav,par", [("morlet", 6.0), ("dog", 2.0)])
-def test_full_size_fp32_4m(torch_cuda, wav, par, bc, fft_mode):
-    # N = 2^22 lognormal field, 128 log scales 2..2^16, FP32 form
+def test_full_size_fp32_4m_all_outputs(torch_cuda, wav, par, bc):
+    # N = 2^22 lognormal field, 128 log scales 2..2^16, FP32 form, segmented
+    # (the benchmarked plan): every output of every scale
     f = synth.lognormal_field(1 << 22, seed=synth.SEED_FIELD_4M)
     scales = synth.log_scales(2.0, 2.0 ** 16, 128)
-    plan, err = sampled_check(torch_cuda, f, bc, wav, par, scales, "fp32", npos=40, fft_mode=fft_mode)
-    print(f"fp32 4M {wav} {bc} {fft_mode} max err", err.max(), "median", np.median(err))
+    plan, err = full_rows_check(torch_cuda, f, bc, wav, par, scales, "fp32")
+    print_table(f"fp32 4M {wav} {bc}", scales, err)
     assert err.max() <= 1e-5
 
 
-@pytest.mark.parametrize("n,wav,par", [((1 << 22) - 3, "morlet", 6.0), ((1 << 22) - 2, "dog", 2.0),
-                                       ((1 << 22) - 1, "dog", 2.0)])
-def test_full_size_fp32_rows_off_the_line_grid(torch_cuda, n, wav, par):
+@pytest.mark.parametrize("bc", ["zero", "periodic"])
+@pytest.mark.parametrize("wav,par", [("morlet", 6.0), ("dog", 2.0)])
+def test_full_size_fp32_4m_whole(torch_cuda, wav, par, bc):
+    f = synth.lognormal_field(1 << 22, seed=synth.SEED_FIELD_4M)
+    scales = synth.log_scales(2.0, 2.0 ** 16, 128)
+    plan, err = sampled_check(torch_cuda, f, bc, wav, par, scales, "fp32", npos=40, fft_mode="whole")
+    print(f"fp32 4M {wav} {bc} whole max err", err.max(), "median", np.median(err))
+    assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("n,wav,par", [((1 << 22) - 3, "morlet", 6.0), ((1 << 22) - 1, "dog", 2.0)])
+def test_full_size_fp32_rows_off_the_line_grid_all_outputs(torch_cuda, n, wav, par):
     # the full-size workload with rows that start inside 128-byte lines:
-    # shifted units (complex rows; column pairs), sampled outputs
+    # shifted units (complex rows; column pairs of odd length): every output
     f = synth.lognormal_field(n, seed=synth.SEED_FIELD_4M)
     scales = synth.log_scales(2.0, 2.0 ** 16, 128)
-    plan, err = sampled_check(torch_cuda, f, "zero", wav, par, scales, "fp32", npos=40)
+    plan, err = full_rows_check(torch_cuda, f, "zero", wav, par, scales, "fp32")
     assert "shift=1" in plan.describe()
-    print(f"fp32 N={n} {wav} max err", err.max())
+    print_table(f"fp32 N={n} {wav} zero", scales, err)
+    assert err.max() <= 1e-5
+
+
+def test_full_size_fp32_rows_off_the_line_grid_sampled(torch_cuda):
+    n = (1 << 22) - 2
+    f = synth.lognormal_field(n, seed=synth.SEED_FIELD_4M)
+    scales = synth.log_scales(2.0, 2.0 ** 16, 128)
+    plan, err = sampled_check(torch_cuda, f, "zero", "dog", 2.0, scales, "fp32", npos=40)
+    assert "shift=1" in plan.describe()
+    print(f"fp32 N={n} dog2 max err", err.max())
     assert err.max() <= 1e-5

@@ -1,10 +1,13 @@
 """Served form on the GPU: requests of mixed shapes go through the
 continuous-batching and plain-batching schedulers; every output must equal
-the same request transformed alone, bit for bit."""
+the same request transformed alone, bit for bit, and match the FP64 oracle
+(Sec. 3, Eq. discreteCWT) within the FP32 bar at sampled positions."""
 import numpy as np
 import pytest
 
+import oracle
 import synth
+from tests.helpers import per_scale_rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -48,3 +51,19 @@ def test_served_outputs_equal_alone(torch_cuda, mode):
         alone = cwt.Plan(r.n, r.boundary, r.wavelet, r.scales, param=r.param, precision="fp32")(r.signal)
         torch_cuda.cuda.synchronize()
         assert torch_cuda.equal(r.output, alone), r.rid
+    # and every served output matches the FP64 oracle (on the FP32 input) at
+    # sampled positions of every scale: the first and last two and 12 more
+    worst = 0.0
+    for r in done:
+        rng = np.random.default_rng(r.rid)
+        pos = np.unique(np.concatenate([[0, 1, r.n - 2, r.n - 1], rng.integers(0, r.n, 12)]))
+        s = np.asarray(r.scales)
+        si = np.repeat(np.arange(s.size), pos.size)
+        pi = np.tile(pos, s.size)
+        f64 = r.signal.double().cpu().numpy()
+        ref = oracle.cwt_points(f64, r.boundary, r.wavelet, s, si, pi, param=r.param).reshape(s.size, pos.size)
+        got = r.output[:, torch_cuda.as_tensor(pos, device="cuda")].cpu().numpy().astype(ref.dtype)
+        err = per_scale_rel_l2(got, ref)
+        worst = max(worst, float(err.max()))
+        assert err.max() <= 1e-5, (r.rid, r.n, r.wavelet, float(err.max()))
+    print("served outputs vs oracle: max sampled per-scale rel L2", worst)

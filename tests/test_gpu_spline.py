@@ -1,7 +1,9 @@
 """GPU parity of the spline method against the oracle's exact spline target
 (the CWT of the cubic-spline interpolant of the samples with the spline
-wavelet psi_h, integrated exactly; Sec. 3.3).  The oracle gets the plan's
-knot spacings, checked separately against the oracle's own rule.
+wavelet psi_h, integrated exactly; Sec. 3.3).  The oracle gets the plan's h*
+(checked separately against the oracle's own search) and applies its own
+rule for the step of every scale: whole-sample knots delta / s where
+h* s >= 1, the step h* itself (knots between samples) below.
 
 Bars (per-scale relative L2 with a floor, tests/helpers.py): 1e-10 for FP64
 output, 1e-5 for FP32 output (FP32-rounded input, FP64 reference)."""
@@ -38,19 +40,20 @@ def ref_input(f, precision):
     return f.astype(np.float32).astype(np.float64) if precision == "fp32" else f
 
 
-def ref_rows(f, bc, wav, par, scales, deltas, x):
-    return np.stack([oracle.spline_target(f, bc, wav, s, int(d), x, param=par, nthreads=8)
-                     for s, d in zip(scales, deltas)])
+def ref_rows(f, bc, wav, par, scales, hstar, x):
+    import os
+    th = min(16, os.cpu_count() or 1)
+    return np.stack([oracle.spline_target_scale(f, bc, wav, s, hstar, x, param=par, nthreads=th)
+                     for s in scales])
 
 
 def check_full(torch, f, bc, wav, par, scales, precision):
     print(f"spline case N={f.size} bc={bc} wav={wav}({par}) S={len(scales)} {precision}", flush=True)
     plan, w = gpu_spline(torch, f, bc, wav, par, scales, precision)
     got = w.cpu().numpy()
-    deltas = plan.spline_delta()
-    hs = oracle.spline_h_star(wav, par)
-    assert deltas.tolist() == [oracle.spline_delta(hs, s) for s in scales]
-    ref = ref_rows(ref_input(f, precision), bc, wav, par, scales, deltas, np.arange(f.size))
+    hs = plan.spline_hstar()
+    assert plan.spline_delta().tolist() == [oracle.spline_delta(hs, s) for s in scales]
+    ref = ref_rows(ref_input(f, precision), bc, wav, par, scales, hs, np.arange(f.size))
     assert np.all(np.isfinite(got))
     err = per_scale_rel_l2(got, ref)
     assert err.max() <= TOL[precision], (err.max(), int(err.argmax()))
@@ -59,6 +62,10 @@ def check_full(torch, f, bc, wav, par, scales, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("n,bc,wav,par,scales", [
+    # below s = 1/h* (Morlet(6) 8.57, Mexican hat 2.69, DOG(4) 3.32): exact taps at step h*
+    (4096, "periodic", "morlet", 6.0, [0.7, 1.3, 2.0, 3.5, 5.0, 8.0, 8.6, 12.0]),
+    (3001, "zero", "mexhat", None, [0.5, 0.9, 1.6, 2.2, 2.68, 2.7, 4.0]),
+    (2500, "zero", "dog", 4.0, [0.6, 3.3, 3.4]),
     (4096, "periodic", "morlet", 6.0, [0.7, 2.0, 9.0, 40.0, 300.0, 1500.0]),
     (3001, "zero", "mexhat", None, [1.5, 2.0, 9.0, 40.0, 150.0, 700.0]),
     (5000, "periodic", "dog", 4.0, [2.0, 30.0, 400.0, 2500.0]),
@@ -81,18 +88,33 @@ def test_spline_degenerate_lengths(torch_cuda, n, bc):
 
 def test_spline_paper_signal_and_gap(torch_cuda):
     # N = 4096 periodic tones + noise, Morlet(6), 32 log scales 2..512: parity
-    # with the spline target, and the gap to the sampled-sum transform.  The
-    # gap is the spline approximations' own error: near Nyquist (s < 8 for
-    # Morlet(6), whose passband w0/s approaches pi) the cubic interpolant of a
-    # broadband signal departs from its samples and the gap reaches tens of
-    # percent; above that it is of the order of AE_M.
+    # with the spline target, and the gap to the sampled-sum transform split
+    # into its two parts:
+    #  - signal: the CWT of the cubic interpolant f_c with the wavelet itself
+    #    (step h_s / 8, wavelet error 4096x smaller) against the sampled sum.
+    #    Near Nyquist (s < 8 for Morlet(6), whose passband w0/s approaches pi)
+    #    the interpolant of a broadband signal departs from its samples and
+    #    this part reaches tens of percent;
+    #  - wavelet: the transform against that interpolant transform, i.e. the
+    #    spline wavelet's own error.  With h_s <= h* at every scale it stays at
+    #    the level of AE_M (5e-4) everywhere.
     f = synth.tones_noise(4096)
     scales = synth.log_scales(2.0, 512.0, 32)
     check_full(torch_cuda, f, "periodic", "morlet", 6.0, scales, "fp64")
-    _, w = gpu_spline(torch_cuda, f, "periodic", "morlet", 6.0, scales, "fp64")
+    plan, w = gpu_spline(torch_cuda, f, "periodic", "morlet", 6.0, scales, "fp64")
+    got = w.cpu().numpy()
+    hs = plan.spline_hstar()
     canon = oracle.cwt(f, "periodic", "morlet", scales, param=6.0)
-    gap = per_scale_rel_l2(w.cpu().numpy(), canon)
+    x = np.arange(0, f.size, 4)
+    fine = np.stack([oracle.spline_target_h(f, "periodic", "morlet", s, oracle.spline_step(hs, s) / 8.0, x,
+                                            param=6.0, nthreads=16) for s in scales])
+    gap = per_scale_rel_l2(got, canon)
+    signal_part = per_scale_rel_l2(fine, canon[:, x])
+    wavelet_part = per_scale_rel_l2(got[:, x], fine)
     print("gap to the sampled sum, per scale:", np.array2string(gap, precision=2))
+    print("  signal interpolation part:      ", np.array2string(signal_part, precision=2))
+    print("  wavelet approximation part:     ", np.array2string(wavelet_part, precision=2))
+    assert wavelet_part.max() < 2e-3
     assert gap[np.asarray(scales) >= 8.0].max() < 1e-2
 
 
@@ -113,24 +135,46 @@ def test_spline_deterministic(torch_cuda):
     assert torch_cuda.equal(a, b)
 
 
+def tile_edges(plan, n):
+    """Positions at the edges of the tap kernel's tiles of every scale (from
+    the plan's description): a tile covers I rows of positions spaced delta
+    apart, starting at a multiple of I delta, and R consecutive columns;
+    the first and last outputs of the first, a middle and the last tile,
+    and the first and last columns, are taken."""
+    import re
+    out = set()
+    for m in re.finditer(r"spline scale=(\d+) delta=(\d+) R=(\d+) I=(\d+)", plan.describe()):
+        d, r, rows = int(m.group(2)), int(m.group(3)), int(m.group(4))
+        span = rows * d
+        ntile = (n + span - 1) // span
+        for t in sorted({0, ntile // 2, ntile - 1}):
+            for off in {0, 1, r - 1, r, d - 1, span - d, span - d + r - 1, span - 1}:
+                x = t * span + off
+                if 0 <= x < n:
+                    out.add(x)
+    assert out
+    return np.array(sorted(out))
+
+
 def sampled(torch, f, bc, wav, par, scales, precision, npos, seed):
     plan, w = gpu_spline(torch, f, bc, wav, par, scales, precision)
     n = f.size
     rng = np.random.default_rng(seed)
-    pos = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.integers(0, n, npos - 5)]))
+    pos = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.integers(0, n, npos - 5),
+                                    tile_edges(plan, n)]))
     got = w[:, torch.as_tensor(pos, device="cuda")].cpu().numpy()
     del w
     torch.cuda.empty_cache()
-    ref = ref_rows(ref_input(f, precision), bc, wav, par, scales, plan.spline_delta(), pos)
+    ref = ref_rows(ref_input(f, precision), bc, wav, par, scales, plan.spline_hstar(), pos)
     return per_scale_rel_l2(got, ref)
 
 
 def test_spline_full_size_fp64_mexhat_1m(torch_cuda):
     # N = 2^20 zero-boundary lognormal field, Mexican hat, 64 log scales
-    # 2..2^14, FP64, sampled positions
+    # 2..2^14, FP64: every scale at sampled positions and tile edges
     f = synth.lognormal_field(1 << 20, seed=synth.SEED_FIELD_1M)
     scales = synth.log_scales(2.0, 2.0 ** 14, 64)
-    err = sampled(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", 24, 1)
+    err = sampled(torch_cuda, f, "zero", "mexhat", None, scales, "fp64", 12, 1)
     print("spline fp64 1M max err", err.max())
     assert err.max() <= 1e-10
 
@@ -138,20 +182,24 @@ def test_spline_full_size_fp64_mexhat_1m(torch_cuda):
 @pytest.mark.parametrize("bc", ["zero", "periodic"])
 def test_spline_full_size_fp32_morlet_4m(torch_cuda, bc):
     # N = 2^22 lognormal field, Morlet(6), 128 log scales 2..2^16, FP32
-    # output; every 8th scale is checked at sampled positions
+    # output: every scale, at the tile edges of all scales plus a few
+    # random positions (the oracle's cost grows with s: about 2 chi s
+    # quadrature pieces per output)
     f = synth.lognormal_field(1 << 22, seed=synth.SEED_FIELD_4M)
     scales = synth.log_scales(2.0, 2.0 ** 16, 128)
     import paper_2302_03909_amd as cwt
     plan = cwt.Plan(f.size, bc, "morlet", scales, param=6.0, precision="fp32", method="spline")
     w = plan(torch_cuda.as_tensor(f, dtype=torch_cuda.float32, device="cuda"))
     torch_cuda.cuda.synchronize()
-    rows = np.arange(0, 128, 8)
     n = f.size
-    pos = np.unique(np.concatenate([[0, 1, n // 2, n - 1], np.random.default_rng(2).integers(0, n, 20)]))
-    got = w[torch_cuda.as_tensor(rows, device="cuda")][:, torch_cuda.as_tensor(pos, device="cuda")].cpu().numpy()
+    edges = tile_edges(plan, n)
+    rng = np.random.default_rng(2)
+    pos = np.unique(np.concatenate([[0, 1, n // 2, n - 1], rng.integers(0, n, 4), rng.choice(edges, 12)]))
+    got = w[:, torch_cuda.as_tensor(pos, device="cuda")].cpu().numpy()
     del w
     torch_cuda.cuda.empty_cache()
-    ref = ref_rows(ref_input(f, "fp32"), bc, "morlet", 6.0, scales[rows], plan.spline_delta()[rows], pos)
+    ref = ref_rows(ref_input(f, "fp32"), bc, "morlet", 6.0, scales, plan.spline_hstar(), pos)
     err = per_scale_rel_l2(got, ref)
-    print(f"spline fp32 4M {bc} max err", err.max())
+    print(f"spline fp32 4M {bc} max err", err.max(), "exact-tap scales",
+          int((plan.spline_delta() == 0).sum()))
     assert err.max() <= 1e-5

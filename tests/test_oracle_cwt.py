@@ -149,3 +149,28 @@ def test_icwt_single_integral_reconstruction():
     k = math.sqrt(2 * math.pi) / math.sqrt(math.gamma(2.5))
     rec = f.mean() + np.trapezoid(w, u, axis=0) / k
     assert np.max(np.abs(rec - f)) < 2e-3
+
+
+@pytest.mark.parametrize("bc", ["periodic", "zero"])
+@pytest.mark.parametrize("wav,par", [("morlet", 6.0), ("mexhat", None), ("dog", 3.0)])
+def test_spectral_rows_equal_direct_sum(bc, wav, par):
+    # the FFT form of the sum (full-length references) against the direct sum,
+    # with scales whose support wraps the period several times
+    rng = np.random.default_rng(5)
+    n = 300
+    f = rng.standard_normal(n) + 0.2
+    scales = [0.8, 2.0, 9.3, 40.0, 230.0]
+    ref = oracle.cwt(f, bc, wav, scales, param=par)
+    for j, row in oracle.cwt_spectral_rows(f, bc, wav, scales, param=par):
+        scale = max(np.max(np.abs(ref[j])), 1e-3 * np.max(np.abs(ref)))
+        assert np.max(np.abs(row - ref[j])) / scale < 1e-12, (j, np.max(np.abs(row - ref[j])) / scale)
+
+
+def test_spectral_rows_tone_closed_form():
+    n = 1000
+    t = np.arange(n)
+    f = np.cos(2 * np.pi * 37 * t / n)
+    scales = [1.1, 6.0, 75.0, 400.0]
+    for j, row in oracle.cwt_spectral_rows(f, "periodic", "morlet", scales, param=6.0):
+        ref = cf.tone_cwt("morlet", 6.0, scales[j], n, 37, "cos")
+        assert np.max(np.abs(row - ref)) < 1e-13

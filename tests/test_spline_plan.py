@@ -33,8 +33,25 @@ def test_delta_rule():
     hs = p.spline_hstar()
     want = [oracle.spline_delta(hs, s) for s in scales]
     assert p.spline_delta().tolist() == want
-    assert set(p.scale_path().tolist()) == {cwt.PATH_SPLINE}
+    # below s = 1/h* the step stays h* and the scale sums exact taps on c
+    path = p.scale_path()
+    assert path.tolist() == [cwt.PATH_SPLINE_DIRECT if d == 0 else cwt.PATH_SPLINE for d in want]
+    assert {0, 1} <= set(want)
     assert p.fft_len == 0
+
+
+@pytest.mark.parametrize("wav,par", [("mexhat", None), ("morlet", 6.0)])
+def test_exact_tap_counts(wav, par):
+    # exact taps reach |t| <= (N_d + 2) s h* + 2 with N_d = ceil(chi / h* - 2) + 2
+    import math
+    scales = [0.4, 1.0, 2.2]
+    p = host_plan(1 << 12, wav, par, scales)
+    hs = p.spline_hstar()
+    nd = math.ceil(oracle.chi(wav, par) / hs - 2.0) + 2
+    for s, taps, d in zip(scales, p.spline_taps(), p.spline_delta()):
+        if d:
+            continue
+        assert taps == 2 * (math.ceil((nd + 2) * s * hs) + 2) + 1
 
 
 def test_spline_limits():
