@@ -12,17 +12,30 @@ sit in device memory (every kernel of the method, all scales).  Workloads:
 
 Prints one JSON line (fields below), with a roofline entry for the kernel
 that takes most of the step and the FP64 oracle timed on the host cores.
-K steps are timed as a caller runs them (value, ms_per_step); K more steps
-are then timed with a HIP event pair around every kernel launch, which gives
-the per-kernel durations (roofline, whole_step.kernels).  Under launch
-timing the library keeps every launch on one stream (otherwise the local
-kernels run beside the band kernels on a second stream), so each duration is
-that kernel's alone, and that region's step time is reported on its own
-(whole_step.ms_per_step_with_kernel_events).
+
+* Warm-up: W steps and at least 200 ms.
+* K steps are timed as a caller runs them (value, ms_per_step; wall clock
+  with a synchronisation on both sides), with an event on the caller's
+  stream between steps (whole_step.ms_median / ms_min).
+* FFT method: K steps of the same plan with every launch on the caller's
+  stream (whole_step.single_stream), against the default, which runs the
+  local kernels on a second stream beside the band kernels.
+* K more steps with a HIP event pair around every kernel launch give the
+  per-kernel durations (roofline, whole_step.kernels).  Under launch timing
+  every launch stays on one stream, so each duration is that kernel's alone;
+  that region's step time is reported on its own
+  (whole_step.ms_per_step_with_kernel_events).
+* roofline is the dominant kernel's (algorithmic bytes or flops per launch
+  over its mean launch time); whole_step gives the whole transform's output
+  write rate against the published 8 TB/s and against the measured copy and
+  store rates of this GPU (measured_peaks).
+* per_scale_error: the output of the last timed step against the FP64
+  oracle at sampled positions of every scale.
 
     python bench.py [--steps K] [--warmup W] [--method fft|spline]
                     [--wavelet morlet|dog2|mexhat] [--boundary zero|periodic]
-                    [--no-cpu-baseline] [--copy-calibration] [--batch COUNT]
+                    [--no-cpu-baseline] [--no-error-table] [--copy-calibration]
+                    [--batch COUNT] [--serve]
 
 --batch COUNT times cwt_exec_batch over COUNT uneven instances instead (4096
 is the batched workload).
@@ -71,6 +84,36 @@ def measured_traffic(kernel: str, workload: str):
     return e.get("hbm_bytes_per_launch")
 
 
+def host_info():
+    """Host CPU as the oracle leg sees it: the model, nproc and the cores
+    this process may run on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "allowed_cpus": allowed}
+
+
+def oracle_threads():
+    """Threads for the oracle: every core this process may use, capped by
+    OMP_NUM_THREADS when the environment sets it (the machine's CPU share)."""
+    info = host_info()
+    n = info["allowed_cpus"]
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
 def _timed_sample(run, seconds):
     count = 2000
     while True:
@@ -80,35 +123,42 @@ def _timed_sample(run, seconds):
         count = int(count * min(8.0, max(1.5, 1.2 * seconds / max(t, 1e-3))))
 
 
-def cpu_baseline_fft(f, boundary, wavelet, param, scales, seconds=10.0):
+def cpu_baseline_fft(f, boundary, wavelet, param, scales, seconds=10.0, one_core_seconds=4.0):
     """The FP64 direct-sum oracle on a uniform random sample of the
-    workload's outputs (scale, position)."""
+    workload's outputs (scale, position), on all the cores this process may
+    use, then on one core."""
     import numpy as np
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads = oracle_threads()
     n, s = f.size, len(scales)
     rng = np.random.default_rng(123)
     f64 = f.astype(np.float64)
 
-    def run(count):
-        si = rng.integers(0, s, count)
-        ps = rng.integers(0, n, count)
-        t0 = time.perf_counter()
-        oracle.cwt_points(f64, boundary, wavelet, scales, si, ps, param=param, nthreads=threads)
-        return time.perf_counter() - t0
+    def run_with(th):
+        def run(count):
+            si = rng.integers(0, s, count)
+            ps = rng.integers(0, n, count)
+            t0 = time.perf_counter()
+            oracle.cwt_points(f64, boundary, wavelet, scales, si, ps, param=param, nthreads=th)
+            return time.perf_counter() - t0
+        return run
 
-    count, t = _timed_sample(run, seconds)
+    count, t = _timed_sample(run_with(threads), seconds)
+    c1, t1 = _timed_sample(run_with(1), one_core_seconds)
+    info = host_info()
     return {"value": count / t, "unit": "coefficients/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} outputs drawn uniformly over the {s} x {n} outputs of the workload "
-                      f"(FP64 direct sum), {t:.1f} s"}
+                      f"(FP64 direct sum), {t:.1f} s on {threads} threads",
+            "one_core_value": c1 / t1, "one_core_sample": f"{c1} outputs, {t1:.1f} s on 1 thread",
+            **info}
 
 
-def cpu_baseline_spline(f, boundary, wavelet, param, scales, deltas, seconds=10.0):
+def cpu_baseline_spline(f, boundary, wavelet, param, scales, hstar, seconds=10.0):
     """The oracle's exact spline target (Gauss-Legendre over the merged
     knots) on random positions of 8 scales spread over the scale range."""
     import numpy as np
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads = oracle_threads()
     n = f.size
     rng = np.random.default_rng(321)
     pick = np.linspace(0, len(scales) - 1, 8).round().astype(int)
@@ -118,15 +168,109 @@ def cpu_baseline_spline(f, boundary, wavelet, param, scales, deltas, seconds=10.
         per = max(1, count // len(pick))
         t0 = time.perf_counter()
         for j in pick:
-            oracle.spline_target(f64, boundary, wavelet, float(scales[j]), int(deltas[j]),
-                                 rng.integers(0, n, per), param=param, nthreads=threads)
+            oracle.spline_target_scale(f64, boundary, wavelet, float(scales[j]), hstar,
+                                       rng.integers(0, n, per), param=param, nthreads=threads)
         return time.perf_counter() - t0
 
     count, t = _timed_sample(run, seconds)
     count = max(1, count // len(pick)) * len(pick)
     return {"value": count / t, "unit": "coefficients/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} outputs, equal numbers at 8 of the {len(scales)} scales (spread over the "
-                      f"range), random positions of N = {n} (exact spline target), {t:.1f} s"}
+                      f"range), random positions of N = {n} (exact spline target), {t:.1f} s",
+            **host_info()}
+
+
+def warm_up(step, count, min_ms=200.0):
+    """At least `count` steps and at least min_ms of wall time (synchronised
+    at the end).  Returns (steps, milliseconds)."""
+    import torch
+    t0 = time.perf_counter()
+    k = 0
+    while k < count or (time.perf_counter() - t0) * 1e3 < min_ms:
+        step()
+        k += 1
+        if k % 8 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return k, (time.perf_counter() - t0) * 1e3
+
+
+def timed_steps(step, steps):
+    """K steps bracketed by a synchronisation on both sides (wall clock ->
+    ms per step), with an event recorded on the caller's stream between
+    steps (per-step milliseconds)."""
+    import torch
+    st = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(st)
+    for k in range(steps):
+        step()
+        evs[k + 1].record(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
+
+
+def measured_peaks(torch, dev, gib=2):
+    """Achievable HBM rates on this GPU: a device-to-device copy of `gib` GiB
+    (reads + writes) and a fill of `gib` GiB (writes only), best of 5."""
+    nbytes = gib << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    best_copy = best_fill = 0.0
+    for _ in range(5):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        a.fill_(2.0)
+        e2.record()
+        torch.cuda.synchronize()
+        best_copy = max(best_copy, 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        best_fill = max(best_fill, nbytes / (e1.elapsed_time(e2) * 1e-3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return {"copy_gbs": round(best_copy, 1), "store_gbs": round(best_fill, 1),
+            "how": f"torch copy_ and fill_ of {gib} GiB float32, best of 5 (copy counts reads and writes)"}
+
+
+def error_table(plan, out, f, boundary, wav, par, scales, method, npos=96):
+    """Per-scale relative L2 error (floor 1e-3 of the largest row norm) of
+    the output against the FP64 oracle on the same input (FP32-rounded for
+    the FP32 form), at the first and last positions and npos - 2 random ones
+    of every scale: the direct sum for the FFT method, the exact spline
+    target for the spline method."""
+    import numpy as np
+    import torch
+    import oracle
+    n = f.size
+    rng = np.random.default_rng(77)
+    pos = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, npos - 2)]))
+    got = out[:, torch.as_tensor(pos, device=out.device)].cpu().numpy()
+    f64 = f.astype(np.float64)
+    th = oracle_threads()
+    t0 = time.perf_counter()
+    if method == "fft":
+        si = np.repeat(np.arange(len(scales)), pos.size)
+        ps = np.tile(pos, len(scales))
+        ref = oracle.cwt_points(f64, boundary, wav, scales, si, ps, param=par, nthreads=th)
+        ref = ref.reshape(len(scales), pos.size)
+        what = "FP64 direct sum"
+    else:
+        hs = plan.spline_hstar()
+        ref = np.stack([oracle.spline_target_scale(f64, boundary, wav, float(s), hs, pos, param=par, nthreads=th)
+                        for s in scales])
+        what = "exact spline target"
+    got = got.astype(ref.dtype)
+    nrm = np.linalg.norm(ref, axis=1)
+    e = np.linalg.norm(got - ref, axis=1) / np.maximum(nrm, 1e-3 * nrm.max())
+    return {"reference": f"{what} at {pos.size} positions per scale ({time.perf_counter() - t0:.1f} s)",
+            "max": float(e.max()), "median": float(np.median(e)),
+            "per_scale": [float(f"{v:.2e}") for v in e]}
 
 
 def main():
@@ -148,6 +292,7 @@ def main():
     ap.add_argument("--wavelet", default=None, choices=["morlet", "dog2", "mexhat"])
     ap.add_argument("--boundary", default="zero", choices=["zero", "periodic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error-table", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device 3 times (a plain copy "
                          "kernel of known size, for scaling HBM byte counters)")
@@ -181,40 +326,43 @@ def main():
     f = synth.lognormal_field(n, seed=seed).astype(dt)
 
     dev = torch.device("cuda", 0)
+    print(f"bench: {args.method} {wav} N={n} S={nscales} {precision}", file=sys.stderr, flush=True)
     plan = cwt.Plan(n, args.boundary, wav, scales, param=par, precision=precision, method=args.method)
     x = torch.as_tensor(f, device=dev)
     out = plan.empty_output(dev)
     ws = plan.empty_workspace(dev)
     torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
-        plan(x, out, ws)
-    torch.cuda.synchronize()
-
-    # timed region: K steps as a caller runs them (value, ms_per_step)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan(x, out, ws)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    warm = warm_up(lambda: plan(x, out, ws), args.warmup)
+    # timed region: K steps as a caller runs them (value, ms_per_step), with
+    # an event on the caller's stream between steps (median and min)
+    ms, per_step = timed_steps(lambda: plan(x, out, ws), args.steps)
+    # the same plan with every launch on the caller's stream (no second
+    # stream for the local kernels), for the choice of the default
+    alt = None
+    if args.method == "fft":
+        plan1 = cwt.Plan(n, args.boundary, wav, scales, param=par, precision=precision, single_stream=True)
+        warm_up(lambda: plan1(x, out, ws), 3)
+        ms1, per1 = timed_steps(lambda: plan1(x, out, ws), args.steps)
+        alt = {"ms_per_step": round(ms1, 4), "ms_median": round(float(np.median(per1)), 4),
+               "ms_min": round(float(np.min(per1)), 4)}
+        del plan1
     # second timed region: K more steps with a HIP event pair around every
     # kernel launch (per-kernel durations, roofline); launches then stay on
     # one stream and the events add a few microseconds each, so this step
     # time is reported on its own
     plan.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan(x, out, ws)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms_ev, _ = timed_steps(lambda: plan(x, out, ws), args.steps)
     plan.timing(False)
     kern = plan.timing_read()
-    ms_ev = (t1 - t0) * 1e3 / args.steps
     coeffs = n * nscales
     value = coeffs / (ms * 1e-3)
     out_bytes = coeffs * (4 if precision == "fp32" else 8) * (2 if plan.is_complex else 1)
+    # per-scale error of the last step's output against the FP64 oracle on
+    # the same (FP32-rounded) input, at sampled positions of every scale
+    err = None
+    if not args.no_error_table:
+        err = error_table(plan, out, f, args.boundary, wav, par, scales, args.method)
 
     wname = f"{wav}({par:g})" if par is not None else wav
     workload = (f"lognormal field N={nname} {args.boundary} boundary, {wname}, "
@@ -225,9 +373,10 @@ def main():
     # dominant kernel: largest total time over the timed region
     name, (cnt, tot_ms, bpl) = max(kern.items(), key=lambda kv: kv[1][1])
     avg_s = tot_ms / cnt * 1e-3
+    peaks = measured_peaks(torch, dev)
     if name.startswith("spl_tap"):
-        # FP64 fused multiply-adds of the tap sums: (2 N_d + 1) taps per output,
-        # one real (two for a complex d) FMA each, 2 flops per FMA
+        # FP64 fused multiply-adds of the tap sums: one per tap and output
+        # (two for complex taps), 2 flops per FMA
         taps = plan.spline_taps().astype(np.float64)
         flops = 2.0 * n * taps.sum() * (2.0 if plan.is_complex else 1.0)
         achieved = flops / avg_s / 1e12
@@ -240,9 +389,17 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
                 "kernel": name, "avg_launch_ms": round(tot_ms / cnt, 4),
-                "algorithmic_bytes_per_launch": bpl}
+                "algorithmic_bytes_per_launch": bpl,
+                "frac_of_measured_store_peak": round(achieved / peaks["store_gbs"], 4)}
+    step_gbs = out_bytes / (ms * 1e-3) / 1e9
     whole = {"output_bytes": out_bytes,
-             "hbm_frac_of_output_write": round(out_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "output_write_gbs": round(step_gbs, 1),
+             "hbm_frac_of_spec": round(step_gbs / HBM_PEAK_GBS, 4),
+             "hbm_frac_of_measured_store_peak": round(step_gbs / peaks["store_gbs"], 4),
+             "hbm_frac_of_measured_copy_peak": round(step_gbs / peaks["copy_gbs"], 4),
+             "ms_median": round(float(np.median(per_step)), 4), "ms_min": round(float(np.min(per_step)), 4),
+             "warmup_steps": warm[0], "warmup_ms": round(warm[1], 1),
+             "single_stream": alt,
              "ms_per_step_with_kernel_events": round(ms_ev, 4),
              "kernels": {k: {"launches": v[0], "ms_per_step": round(v[1] / args.steps, 4),
                              "bytes_per_launch": v[2]} for k, v in kern.items()}}
@@ -257,10 +414,11 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
         if args.method == "fft":
             cpu = cpu_baseline_fft(f, args.boundary, wav, par, scales)
         else:
-            cpu = cpu_baseline_spline(f, args.boundary, wav, par, scales, plan.spline_delta())
+            cpu = cpu_baseline_spline(f, args.boundary, wav, par, scales, plan.spline_hstar())
 
     line = {"metric": "CWT coefficients/sec (N x scales) and % HBM peak at N=2^22, 128 scales",
             "value": value, "unit": "coefficients/s", "n_gpus": 1, "steps": args.steps,
@@ -269,7 +427,8 @@ def main():
             "config": {"workload": workload, "method": args.method, "n": n, "scales": nscales,
                        "scale_range": [2, int(smax)], "boundary": args.boundary, "wavelet": wname,
                        "precision": precision},
-            "roofline": roof, "whole_step": whole, "cpu_baseline": cpu}
+            "roofline": roof, "whole_step": whole, "measured_peaks": peaks, "per_scale_error": err,
+            "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
 

@@ -125,7 +125,10 @@ typedef struct {
     int32_t fft_mode;  /* FFT method only: CWT_FFT_SEGMENTED (default) or
                           CWT_FFT_WHOLE; both give the same transform up to
                           rounding */
-    int32_t reserved[6];
+    int32_t single_stream; /* 1: every launch of a call stays on the
+                              caller's stream (no second stream for the
+                              local-group kernels); same results */
+    int32_t reserved[5];
 } cwt_opts;
 
 /*

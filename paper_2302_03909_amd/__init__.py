@@ -41,7 +41,8 @@ class _Wavelet(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("fft_len", ctypes.c_int64), ("host_only", ctypes.c_int32),
-                ("fft_mode", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("fft_mode", ctypes.c_int32), ("single_stream", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 EXPORTS = ["cwt_plan", "cwt_destroy", "cwt_out_is_complex", "cwt_out_elems", "cwt_out_elem_bytes",
@@ -123,12 +124,12 @@ class Plan:
 
     def __init__(self, n: int, boundary: str, wavelet: str, scales, param=None,
                  precision: str = "fp64", method: str = "fft", fft_len: int = 0,
-                 host_only: bool = False, fft_mode: str = "segmented"):
+                 host_only: bool = False, fft_mode: str = "segmented", single_stream: bool = False):
         lib = load()
         kind, par = _wavelet(wavelet, param)
         sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64).ravel())
         opts = _Opts(_PRECISION[precision], _METHOD[method], int(fft_len), 1 if host_only else 0,
-                     _FFT_MODE[fft_mode])
+                     _FFT_MODE[fft_mode], 1 if single_stream else 0)
         h = ctypes.c_void_p()
         _check(lib.cwt_plan(ctypes.byref(h), int(n), _BOUNDARY[boundary], _Wavelet(kind, par),
                             sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sc.size,

