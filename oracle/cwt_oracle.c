@@ -287,15 +287,17 @@ int oracle_spline_target(const double *c, long c0, long nc,
         for (long i = 0; i < nx; ++i) {
             long xi = x[i];
             long cnt = 0;
-            for (long n = xi - half; n < xi + half; ++n) {
+            /* coordinates relative to the output: v = u - x, so that no
+             * large position enters a spline argument */
+            for (long n = -half; n < half; ++n) {
                 for (int q = 0; q < 4; ++q) {
-                    double u = n + 0.5 * (1.0 + gx[q]);
-                    /* f_c(u): c[n'] with n' in [n-1, n+2] */
+                    double v = n + 0.5 * (1.0 + gx[q]);
+                    /* f_c(x + v): c[x + m] beta3(v - m), m in [n-1, n+2] */
                     double fc = 0.0;
-                    for (long np = n - 1; np <= n + 2; ++np)
-                        fc += coef(c, c0, nc, np) * beta3(u - (double)np);
-                    /* psi_h((u - x)/s) = sum_k d[k] beta3((u-x)/delta - k) */
-                    double y = (u - (double)xi) / (double)delta;
+                    for (long m = n - 1; m <= n + 2; ++m)
+                        fc += coef(c, c0, nc, xi + m) * beta3(v - (double)m);
+                    /* psi_h(v/s) = sum_k d[k] beta3(v/delta - k) */
+                    double y = v / (double)delta;
                     long k0 = (long)floor(y) - 1;
                     double pr = 0.0, pi = 0.0;
                     for (long k = k0; k <= k0 + 3; ++k) {
@@ -347,18 +349,20 @@ int oracle_spline_target_step(const double *c, long c0, long nc,
         double *ti = (double *)malloc(sizeof(double) * maxpieces * 4);
 #pragma omp for schedule(dynamic, 8)
         for (long i = 0; i < nx; ++i) {
-            const double xi = (double)x[i];
-            const double lo = xi - half, hi = xi + half;
+            /* coordinates relative to the output, v = u - x (x is an
+             * integer, so the integer knots stay integers) */
+            const long xi = x[i];
+            const double lo = -half, hi = half;
             /* two sorted knot sequences: integers in (lo, hi), and
-             * xi + step k for k = -(Nd+2)..Nd+2 (the first and last are lo
-             * and hi themselves) */
+             * step k for k = -(Nd+2)..Nd+2 (the first and last are lo and
+             * hi themselves) */
             long nint = (long)floor(lo) + 1; /* next integer above lo */
             long k = -(Nd + 2) + 1;
             double a = lo;
             long cnt = 0;
             while (a < hi) {
                 double bi = (double)nint;
-                double bk = (k <= Nd + 2) ? xi + step * (double)k : hi;
+                double bk = (k <= Nd + 2) ? step * (double)k : hi;
                 double b = bi < bk ? bi : bk;
                 if (b > hi) b = hi;
                 if (bi <= b) ++nint;
@@ -366,13 +370,13 @@ int oracle_spline_target_step(const double *c, long c0, long nc,
                 if (b > a) {
                     const double mid = 0.5 * (a + b), hw = 0.5 * (b - a);
                     const long nf = (long)floor(mid);
-                    const long kf = (long)floor((mid - xi) / step);
+                    const long kf = (long)floor(mid / step);
                     for (int q = 0; q < 4; ++q) {
-                        const double u = mid + hw * gx[q];
+                        const double v = mid + hw * gx[q];
                         double fc = 0.0;
-                        for (long np = nf - 1; np <= nf + 2; ++np)
-                            fc += coef(c, c0, nc, np) * beta3(u - (double)np);
-                        const double y = (u - xi) / step;
+                        for (long m = nf - 1; m <= nf + 2; ++m)
+                            fc += coef(c, c0, nc, xi + m) * beta3(v - (double)m);
+                        const double y = v / step;
                         double pr = 0.0, pi = 0.0;
                         for (long kk = kf - 1; kk <= kf + 2; ++kk) {
                             if (kk < -Nd || kk > Nd) continue;

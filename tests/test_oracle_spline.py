@@ -308,3 +308,22 @@ def test_spline_target_step_equals_integer_knots():
         a = oracle.spline_target(f, "zero", wav, s, delta, x, param=par)
         b = oracle.spline_target_h(f, "zero", wav, s, delta / s, x, param=par)
         assert np.max(np.abs(a - b)) <= 1e-14 * max(1.0, np.max(np.abs(a)))
+
+
+@pytest.mark.parametrize("wav,par,s", [("mexhat", None, 2.0), ("mexhat", None, 40.0), ("morlet", 6.0, 5.0),
+                                       ("morlet", 6.0, 300.0)])
+def test_spline_target_shift_invariance_at_large_positions(wav, par, s):
+    # A periodic signal of 2^20 samples that repeats every 256 samples has a
+    # transform that repeats every 256 positions: the target at x and at
+    # x + 256 q (positions near 10^6) must agree to rounding.  Evaluating the
+    # splines at absolute positions of 10^6 loses about 1e-10 of every
+    # argument; the quadrature works relative to the output position.
+    n = 1 << 20
+    pat = np.random.default_rng(8).standard_normal(256)
+    f = np.tile(pat, n // 256)
+    hs = _hstar(wav, par)
+    x = np.array([3, 100, 255])
+    far = x + 256 * 4000
+    a = oracle.spline_target_scale(f, "periodic", wav, s, hs, x, param=par)
+    b = oracle.spline_target_scale(f, "periodic", wav, s, hs, far, param=par)
+    assert np.max(np.abs(a - b)) <= 1e-14 * max(1.0, np.max(np.abs(a))), np.max(np.abs(a - b))
