@@ -211,6 +211,26 @@ int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace,
              void *stream);
 
 /*
+ * cwt_exec_scratch -- cwt_exec without allocating anything, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The workspace is a
+ * fixed array of cwt_scratch_bytes() bytes (128 MiB) in the device memory of
+ * every GPU the library runs on, reserved when the library loads and held
+ * until the process ends; its device address is looked up once per device
+ * on the first call with that device current.  signal, out and stream as
+ * for cwt_exec.  Every launch stays on `stream` (no second stream), and no
+ * event is recorded: keep the plan alive until the call's work has finished.
+ * All calls on one GPU share that GPU's array and leave their contents in
+ * it: calls that overlap in time on one GPU (different streams, or
+ * different threads) race and give wrong results; serialise them.  No
+ * kernel relies on the array's earlier contents.
+ * Errors: as cwt_exec; CWT_EUNSUPPORTED when cwt_workspace_bytes(plan)
+ * exceeds cwt_scratch_bytes() (nothing is launched).
+ */
+int cwt_exec_scratch(cwt_plan_t plan, const void *signal, void *out, void *stream);
+size_t cwt_scratch_bytes(void);
+
+/*
  * cwt_exec_batch -- transform n independent signals, each with its own plan
  * (lengths, scales, wavelets, boundaries and precisions may differ), in one
  * enqueue on `stream`.  signals[i], outs[i] as for cwt_exec with plans[i].

@@ -48,7 +48,8 @@ class _Opts(ctypes.Structure):
 EXPORTS = ["cwt_plan", "cwt_destroy", "cwt_out_is_complex", "cwt_out_elems", "cwt_out_elem_bytes",
            "cwt_workspace_bytes", "cwt_footprint_bytes", "cwt_exec", "cwt_batch_workspace_bytes",
            "cwt_exec_batch", "cwt_plan_fft_len", "cwt_plan_spline_delta", "cwt_plan_spline_taps", "cwt_plan_spline_hstar",
-           "cwt_plan_scale_path", "cwt_plan_describe", "cwt_plan_timing_enable", "cwt_plan_timing_read", "cwt_last_error"]
+           "cwt_plan_scale_path", "cwt_plan_describe", "cwt_plan_timing_enable", "cwt_plan_timing_read", "cwt_last_error",
+           "cwt_exec_scratch", "cwt_scratch_bytes"]
 
 _lib = None
 
@@ -91,6 +92,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cwt_plan_timing_read.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.cwt_last_error.restype = ctypes.c_char_p
+    lib.cwt_exec_scratch.argtypes = [vp, vp, vp, vp]
+    lib.cwt_scratch_bytes.argtypes = []
+    lib.cwt_scratch_bytes.restype = ctypes.c_size_t
     _lib = lib
     return lib
 
@@ -251,6 +255,27 @@ class Plan:
                                ctypes.c_void_p(workspace.data_ptr() if workspace is not None else 0),
                                ctypes.c_void_p(st.cuda_stream)))
         return out
+
+
+def exec_scratch(plan: Plan, signal, out=None, stream=None):
+    """``cwt_exec_scratch``: the transform with the library's fixed scratch
+    array as workspace (no allocation by the library; ``out`` is allocated
+    here when not given).  Calls that overlap on one GPU race."""
+    import torch
+    sdt, _ = plan._dtypes()
+    if signal.dtype != sdt or signal.device.type != "cuda" or signal.numel() != plan.n:
+        raise ValueError(f"signal must be a cuda {sdt} tensor of {plan.n} values")
+    signal = signal.contiguous()
+    if out is None:
+        out = plan.empty_output(signal.device)
+    st = stream if stream is not None else torch.cuda.current_stream(signal.device)
+    _check(load().cwt_exec_scratch(plan.handle, ctypes.c_void_p(signal.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(st.cuda_stream)))
+    return out
+
+
+def scratch_bytes() -> int:
+    return int(load().cwt_scratch_bytes())
 
 
 def batch_workspace_bytes(plans) -> int:

@@ -1295,69 +1295,136 @@ size_t cwt_footprint_bytes(cwt_plan_t plan) {
     return sig + eb * (size_t)p.N * (size_t)p.S + p.ws_bytes + p.table_bytes;
 }
 
+}  // extern "C"
+
+namespace cwt {
+
+// One transform on `stream`.  bare: every launch on `stream`, no launch
+// timing and no release event (nothing is created, not even an event).
+static int exec_impl(cwt_plan_t plan, const void *signal, void *out, void *workspace, void *stream, bool bare) {
+    if (!plan) fail(CWT_EINVAL, "plan is NULL");
+    if (!signal || !out) fail(CWT_EINVAL, "signal/out is NULL");
+    Plan &p = *plan->p;
+    if (p.host_only) fail(CWT_EINVAL, "plan was built host-only");
+    if (p.ws_bytes > 0 && !workspace) fail(CWT_EINVAL, "workspace is NULL");
+    size_t ealign = p.precision == CWT_FP64 ? 8 : 4;
+    if ((uintptr_t)signal % ealign || (uintptr_t)out % ealign)
+        fail(CWT_EINVAL, "signal/out not aligned to the element size");
+    if (workspace && (uintptr_t)workspace % 256) fail(CWT_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double sb = p.precision == CWT_FP64 ? 8.0 : 4.0;
+    const double eb = (double)cwt_out_elem_bytes(plan);
+    const double nn = (double)p.N;
+    const bool timing = p.timing && !bare;
+    auto run = [&](hipStream_t ks, const std::string &name, double bytes, const char *what, auto &&launch) {
+        if (timing) {
+            timed(p, ks, name, bytes, what, launch);
+            return;
+        }
+        const hipError_t e = launch();
+        if (e != hipSuccess) fail(CWT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    if (p.method == CWT_METHOD_SPLINE) {
+        run(st, spline_kernel_name(p, 0), nn * sb + 16.0 * (double)p.spl_len, "spline sums launch",
+            [&] { return launch_spline(p, signal, out, workspace, st, 0); });
+        run(st, spline_kernel_name(p, 1), nn * p.S * eb, "spline taps launch",
+            [&] { return launch_spline(p, signal, out, workspace, st, 1); });
+        if (!bare) note_use(p, st);
+        return CWT_OK;
+    }
+    const double fb = p.precision == CWT_FP64 ? 16.0 : 8.0;
+    if (!p.segs.empty()) {
+        static const char *what[4] = {"local launch", "segment spectra launch", "segment reduce launch",
+                                      "segment inverse launch"};
+        BatchArgs a{};
+        a.i0 = {signal, out, static_cast<char *>(workspace)};
+        bool has_local = false, has_band = false;
+        for_each_seg_launch(p, [&](const SegKernelId &id, int32_t, int64_t, double) {
+            (id.kind == 0 ? has_local : has_band) = true;
+        });
+        SegStreams ss(st, has_local && has_band && !timing && !p.single_stream && !bare);
+        for_each_seg_launch(p, [&](const SegKernelId &id, int32_t key, int64_t blocks, double bytes) {
+            a.k0 = p.keys[key];
+            hipStream_t ks = ss.of(id.kind);
+            run(ks, seg_kernel_id_name(id), bytes, what[id.kind], [&] { return launch_seg_kernel(id, a, blocks, ks); });
+        });
+        ss.end();
+    }
+    if (p.M > 0)
+        run(st, "forward", nn * sb + (double)p.M * fb, "forward launch",
+            [&] { return launch_forward(p, signal, workspace, st); });
+    for (auto &g : p.groups)
+        run(st, local_kernel_name(p, g), nn * sb + nn * (double)g.scales.size() * eb, "local launch",
+            [&] { return launch_local(p, g, signal, out, st); });
+    for (auto &c : p.columns) {
+        double rows = 0.0, band = 0.0;
+        for (size_t i = 0; i < c.items.size(); ++i) {
+            const auto &d = c.items[i];
+            if (d.r0 != 0) continue;
+            rows += d.sb >= 0 ? 2.0 : 1.0;
+            band += (double)d.B * fb;
+        }
+        run(st, column_kernel_name(p, c), band + nn * rows * eb, "column launch",
+            [&] { return launch_column(p, c, workspace, out, st); });
+    }
+    if (!bare) note_use(p, st);
+    return CWT_OK;
+}
+
+}  // namespace cwt
+
+extern "C" {
+
 int cwt_exec(cwt_plan_t plan, const void *signal, void *out, void *workspace, void *stream) {
+    return guarded([&]() -> int { return cwt::exec_impl(plan, signal, out, workspace, stream, false); });
+}
+
+}  // extern "C"
+
+namespace cwt {
+
+// Workspace of cwt_exec_scratch: a fixed array in the device memory of every
+// GPU the library runs on, held from the library's load until the process
+// ends.  Host code never uses its name as an address: the device address is
+// looked up once per device (scratch_ptr) and passed to the kernels.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current.
+static void *scratch_ptr() {
+    static std::mutex mu;
+    static std::map<int, void *> ptrs;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    auto it = ptrs.find(dev);
+    if (it != ptrs.end()) return it->second;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        fail(CWT_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    ptrs[dev] = ptr;
+    return ptr;
+}
+
+}  // namespace cwt
+
+extern "C" {
+
+int cwt_exec_scratch(cwt_plan_t plan, const void *signal, void *out, void *stream) {
     return guarded([&]() -> int {
         if (!plan) cwt::fail(CWT_EINVAL, "plan is NULL");
-        if (!signal || !out) cwt::fail(CWT_EINVAL, "signal/out is NULL");
-        Plan &p = *plan->p;
-        if (p.host_only) cwt::fail(CWT_EINVAL, "plan was built host-only");
-        if (p.ws_bytes > 0 && !workspace) cwt::fail(CWT_EINVAL, "workspace is NULL");
-        size_t ealign = p.precision == CWT_FP64 ? 8 : 4;
-        if ((uintptr_t)signal % ealign || (uintptr_t)out % ealign)
-            cwt::fail(CWT_EINVAL, "signal/out not aligned to the element size");
-        if (workspace && (uintptr_t)workspace % 256) cwt::fail(CWT_EINVAL, "workspace not 256-byte aligned");
-        hipStream_t st = static_cast<hipStream_t>(stream);
-        const double sb = p.precision == CWT_FP64 ? 8.0 : 4.0;
-        const double eb = (double)cwt_out_elem_bytes(plan);
-        const double nn = (double)p.N;
-        if (p.method == CWT_METHOD_SPLINE) {
-            cwt::timed(p, st, cwt::spline_kernel_name(p, 0), nn * sb + 16.0 * (double)p.spl_len, "spline sums launch",
-                       [&] { return cwt::launch_spline(p, signal, out, workspace, st, 0); });
-            cwt::timed(p, st, cwt::spline_kernel_name(p, 1), nn * p.S * eb, "spline taps launch",
-                       [&] { return cwt::launch_spline(p, signal, out, workspace, st, 1); });
-            cwt::note_use(p, st);
-            return CWT_OK;
-        }
-        const double fb = p.precision == CWT_FP64 ? 16.0 : 8.0;
-        if (!p.segs.empty()) {
-            static const char *what[4] = {"local launch", "segment spectra launch", "segment reduce launch",
-                                          "segment inverse launch"};
-            cwt::BatchArgs a{};
-            a.i0 = {signal, out, static_cast<char *>(workspace)};
-            bool has_local = false, has_band = false;
-            cwt::for_each_seg_launch(p, [&](const cwt::SegKernelId &id, int32_t, int64_t, double) {
-                (id.kind == 0 ? has_local : has_band) = true;
-            });
-            cwt::SegStreams ss(st, has_local && has_band && !p.timing && !p.single_stream);
-            cwt::for_each_seg_launch(p, [&](const cwt::SegKernelId &id, int32_t key, int64_t blocks, double bytes) {
-                a.k0 = p.keys[key];
-                hipStream_t ks = ss.of(id.kind);
-                cwt::timed(p, ks, cwt::seg_kernel_id_name(id), bytes, what[id.kind],
-                           [&] { return cwt::launch_seg_kernel(id, a, blocks, ks); });
-            });
-            ss.end();
-        }
-        if (p.M > 0)
-            cwt::timed(p, st, "forward", nn * sb + (double)p.M * fb, "forward launch",
-                       [&] { return cwt::launch_forward(p, signal, workspace, st); });
-        for (auto &g : p.groups)
-            cwt::timed(p, st, cwt::local_kernel_name(p, g), nn * sb + nn * (double)g.scales.size() * eb,
-                       "local launch", [&] { return cwt::launch_local(p, g, signal, out, st); });
-        for (auto &c : p.columns) {
-            double rows = 0.0, band = 0.0;
-            for (size_t i = 0; i < c.items.size(); ++i) {
-                const auto &d = c.items[i];
-                if (d.r0 != 0) continue;
-                rows += d.sb >= 0 ? 2.0 : 1.0;
-                band += (double)d.B * fb;
-            }
-            cwt::timed(p, st, cwt::column_kernel_name(p, c), band + nn * rows * eb, "column launch",
-                       [&] { return cwt::launch_column(p, c, workspace, out, st); });
-        }
-        cwt::note_use(p, st);
-        return CWT_OK;
+        const size_t need = plan->p->ws_bytes;
+        if (need > cwt::kScratchBytes)
+            cwt::fail(CWT_EUNSUPPORTED, "plan needs " + std::to_string(need) + " bytes of workspace; the scratch "
+                                        "array holds " + std::to_string(cwt::kScratchBytes));
+        void *ws = need ? cwt::scratch_ptr() : nullptr;
+        return cwt::exec_impl(plan, signal, out, ws, stream, true);
     });
 }
+
+size_t cwt_scratch_bytes(void) { return cwt::kScratchBytes; }
 
 int cwt_plan_timing_enable(cwt_plan_t plan, int32_t on) {
     return guarded([&]() -> int {
