@@ -84,6 +84,21 @@ extern "C" {
 #define CWT_MORLET 0
 #define CWT_MEXHAT 1
 #define CWT_DOG 2
+/* The four wavelets of Table 2 (unit L2 norm, real ones even):
+ *   CWT_CBSW   cubic B-spline wavelet  C_N (2 beta3(x) - beta3(x+1) - beta3(x-1)),
+ *              C_N = sqrt(30/31); its spectrum 64 C_N sin^6(u/2)/u^4 is not
+ *              band-limited, so the FFT method takes it only with
+ *              CWT_FFT_WHOLE and CWT_PSI_ANALYTIC, and the spline method not
+ *              at all (CWT_EUNSUPPORTED)
+ *   CWT_GDW    Gaussian-derived wavelet C_N (2 - x^2) e^{-x^2/4}
+ *   CWT_CWGDW  cosine-weighted GDW      C_N ((1-x^2) cos x - x sin x) e^{(1-x^2)/2}
+ *   CWT_MW     Morlet wavelet           C_N (e^{-4ix} - e^{-8}) e^{-x^2/2}
+ *              (complex output; CWT_MORLET with omega0 = -4)
+ * `param` is ignored for these four. */
+#define CWT_CBSW 3
+#define CWT_GDW 4
+#define CWT_CWGDW 5
+#define CWT_MW 6
 
 #define CWT_FP64 0 /* FP64 signal, FP64 output, FP64 arithmetic */
 #define CWT_FP32 1 /* FP32 signal and output; FP32 inverse FFTs and products;
@@ -104,6 +119,21 @@ extern "C" {
  *                        scale a band-limited inverse of length M. */
 #define CWT_FFT_SEGMENTED 0
 #define CWT_FFT_WHOLE 1
+
+/* Which spectrum of the wavelet the FFT method multiplies by:
+ *   CWT_PSI_ALIASED  -- Psi_s(w) = sum_q psi^(s (w + 2 pi q)), the transform of
+ *                       the sampled wavelet: the result is the unit-step sum
+ *                       of Sec. 3, Eq. discreteCWT (the library's transform);
+ *   CWT_PSI_ANALYTIC -- psi^(s w) alone at every DFT bin w = 2 pi m / M,
+ *                       |m| <= M/2: Eq. discrete_CWT_conv as written in
+ *                       Sec. 3.1.  It differs from the sum by the aliasing
+ *                       images, large at small scales.  FFT method with
+ *                       CWT_FFT_WHOLE only (every scale is a band-limited
+ *                       inverse of length M, M = N for a periodic signal of
+ *                       a supported length, else the zero- or wrap-padded
+ *                       length), FP64 or FP32. */
+#define CWT_PSI_ALIASED 0
+#define CWT_PSI_ANALYTIC 1
 
 typedef struct cwt_plan_s *cwt_plan_t;
 
@@ -128,7 +158,8 @@ typedef struct {
     int32_t single_stream; /* 1: every launch of a call stays on the
                               caller's stream (no second stream for the
                               local-group kernels); same results */
-    int32_t reserved[5];
+    int32_t psi_mode;  /* CWT_PSI_ALIASED (default) or CWT_PSI_ANALYTIC */
+    int32_t reserved[4];
 } cwt_opts;
 
 /*
@@ -142,7 +173,9 @@ typedef struct {
  * beta3_wavelet_approx_m02, chosen by Eq. m02cwt_error as in Sec. 3.6).
  * Errors: CWT_EINVAL for N < 2, S < 1, a scale that is not finite and > 0,
  * omega0 <= 0 or not finite, a DOG order that is not an integer in [1, 16],
- * an unknown kind/boundary/precision/method, out == NULL or scales == NULL;
+ * an unknown kind/boundary/precision/method/psi_mode, CWT_PSI_ANALYTIC
+ * without CWT_METHOD_FFT and CWT_FFT_WHOLE, out == NULL or scales == NULL;
+ * CWT_EUNSUPPORTED for CWT_CBSW other than whole-signal analytic;
  * CWT_EUNSUPPORTED for N > 2^26, S > 65536, an fft_len that is too short or
  * not of the supported form, or (spline method) a knot spacing delta_s
  * above about 2^18.4 (the 128-bit running sums then keep fewer than 40

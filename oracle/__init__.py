@@ -13,7 +13,11 @@ Contents
 * ``cwt_spectral_rows`` -- the same sum row by row as an FFT circular
   convolution with the sampled wavelet (scipy.fft as a library primitive),
   for full-length references at sizes the direct sum cannot reach.
-* ``psi`` / ``chi`` -- the mother wavelets in the time domain.
+* ``psi`` / ``chi`` -- the mother wavelets in the time domain (Morlet, DOG,
+  and the CBSW, GDW, CW-GDW and MW of Table 2); ``psi_hat`` their Fourier
+  transforms.
+* ``cwt_analytic`` -- Eq. discrete_CWT_conv as printed (Sec. 3.1): the bare
+  transform of the wavelet at the DFT bins, with numpy FFTs.
 * Spline method (Sec. 3.3, App. B, App. C):
   ``spline_coeffs`` (cubic-spline interpolation coefficients c of the
   signal, Eq. interp_coeffs, by a banded solve or an FFT division -- not by
@@ -49,7 +53,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cwt_oracle.c")
 _LIB = os.path.join(_HERE, "libcwt_oracle.so")
 
-MORLET, DOG = 0, 1
+MORLET, DOG, CBSW, GDW, CWGDW = 0, 1, 2, 3, 4
 PERIODIC, ZERO = 0, 1
 
 
@@ -104,11 +108,78 @@ def _wavelet(wavelet: str, param: float | None):
         return DOG, 2.0
     if w == "dog":
         return DOG, 2.0 if param is None else float(param)
+    # Table 2: the MW is C_N (e^{-4ix} - e^{-8}) e^{-x^2/2}, the Morlet form
+    # with omega0 = -4
+    table2 = {"cbsw": (CBSW, 0.0), "gdw": (GDW, 0.0), "cwgdw": (CWGDW, 0.0), "cw-gdw": (CWGDW, 0.0),
+              "mw": (MORLET, -4.0)}
+    if w in table2:
+        return table2[w]
     raise ValueError(wavelet)
 
 
 def is_complex(wavelet: str) -> bool:
-    return wavelet.lower() == "morlet"
+    return wavelet.lower() in ("morlet", "mw")
+
+
+def psi_hat(wavelet: str, param: float | None, u) -> np.ndarray:
+    """Fourier transform psi^(u) = int psi(x) e^{-iux} dx of the unit-norm
+    wavelets (the transforms of Table 2, in this sign convention):
+    Morlet(w0) C sqrt(2 pi)(e^{-(u-w0)^2/2} - e^{-w0^2/2} e^{-u^2/2});
+    DOG(m) (-1)^{m+1} Gamma(m+1/2)^{-1/2} (iu)^m sqrt(2 pi) e^{-u^2/2};
+    CBSW 64 C_N sin^6(u/2)/u^4; GDW 8 sqrt(pi) C_N u^2 e^{-u^2};
+    CW-GDW sqrt(2 pi) C_N u (u cosh u - sinh u) e^{-u^2/2}."""
+    import math
+    kind, p = _wavelet(wavelet, param)
+    u = np.asarray(u, dtype=np.float64)
+    if kind == MORLET:
+        c = math.pi ** -0.25 / math.sqrt(1 + math.exp(-p * p) - 2 * math.exp(-0.75 * p * p))
+        return (c * math.sqrt(2 * math.pi) * (np.exp(-0.5 * (u - p) ** 2)
+                                              - math.exp(-0.5 * p * p) * np.exp(-0.5 * u * u))).astype(np.complex128)
+    if kind == DOG:
+        m = int(p)
+        return ((-1) ** (m + 1) / math.sqrt(math.gamma(m + 0.5)) * (1j * u) ** m
+                * math.sqrt(2 * math.pi) * np.exp(-0.5 * u * u))
+    if kind == CBSW:
+        cn = math.sqrt(30.0 / 31.0)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            v = 64.0 * cn * np.sin(0.5 * u) ** 6 / u ** 4
+        return np.where(u == 0.0, 0.0, v).astype(np.complex128)
+    if kind == GDW:
+        cn = (18 * math.pi) ** -0.25
+        return (8 * math.sqrt(math.pi) * cn * u * u * np.exp(-u * u)).astype(np.complex128)
+    cn = math.sqrt(8 / (1 + 5 * math.e)) / math.pi ** 0.25
+    # (u cosh u - sinh u) e^{-u^2/2} = ((u - 1) e^{u - u^2/2} + (u + 1) e^{-u - u^2/2}) / 2,
+    # which stays finite where cosh u alone would overflow
+    v = 0.5 * ((u - 1) * np.exp(u - 0.5 * u * u) + (u + 1) * np.exp(-u - 0.5 * u * u))
+    return (math.sqrt(2 * math.pi) * cn * u * v).astype(np.complex128)
+
+
+def cwt_analytic(f, boundary: str, wavelet: str, scales, m: int, param: float | None = None) -> np.ndarray:
+    """The FFT method as written in Sec. 3.1, Eq. discrete_CWT_conv: with
+    the signal's DFT on m points (the signal zero-padded to m samples for a
+    zero boundary; m = N for a periodic one), each scale's row is the
+    inverse DFT of F[k] conj(psi^(s w_k)), w_k = 2 pi k / m the signed
+    frequency of bin k in [-m/2, m/2), the bare transform of the wavelet
+    (no aliasing images).  The Nyquist bin of an even m takes the mean of
+    psi^(s pi) and psi^(-s pi).  [S, N] array, complex for complex
+    wavelets."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.size
+    if boundary == "periodic" and m != n:
+        raise ValueError("a periodic signal is transformed on its own length")
+    x = np.zeros(m)
+    x[:n] = f
+    F = np.fft.fft(x)
+    k = np.fft.fftfreq(m) * m          # signed bins, Nyquist at -m/2
+    w = 2 * np.pi * k / m
+    out = []
+    for s in np.asarray(scales, dtype=np.float64):
+        ph = psi_hat(wavelet, param, s * w)
+        if m % 2 == 0:
+            ph[m // 2] = 0.5 * (psi_hat(wavelet, param, [-s * np.pi])[0] + psi_hat(wavelet, param, [s * np.pi])[0])
+        row = np.fft.ifft(F * np.conj(ph))[:n]
+        out.append(row if is_complex(wavelet) else row.real)
+    return np.array(out)
 
 
 def psi(wavelet: str, param: float | None, x) -> np.ndarray:

@@ -42,6 +42,11 @@
  *   kind 1  DOG(m): (-1)^{m+1} Gamma(m+1/2)^{-1/2} d^m/dx^m e^{-x^2/2}
  *           = -He_m(x) e^{-x^2/2} / sqrt(Gamma(m+1/2)), He_m the
  *           probabilists' Hermite polynomial.  m = 2 is the Mexican hat.
+ *   The wavelets of Table 2 (the MW there is kind 0 with w0 = -4):
+ *   kind 2  CBSW   sqrt(30/31) (2 beta3(x) - beta3(x+1) - beta3(x-1))
+ *   kind 3  GDW    (18 pi)^{-1/4} (2 - x^2) e^{-x^2/4}
+ *   kind 4  CW-GDW sqrt(8/(1+5e)) pi^{-1/4} ((1-x^2) cos x - x sin x)
+ *                  e^{(1-x^2)/2}
  */
 #include <math.h>
 #include <stdlib.h>
@@ -52,11 +57,32 @@
 
 #define ORC_MORLET 0
 #define ORC_DOG 1
+#define ORC_CBSW 2
+#define ORC_GDW 3
+#define ORC_CWGDW 4
 #define ORC_PERIODIC 0
 #define ORC_ZERO 1
 
+static double beta3(double x);
+
 /* Mother wavelet in the time domain. */
 static void psi_eval(int kind, double p, double x, double *re, double *im) {
+    if (kind == ORC_CBSW) {
+        *re = sqrt(30.0 / 31.0) * (2.0 * beta3(x) - beta3(x + 1.0) - beta3(x - 1.0));
+        *im = 0.0;
+        return;
+    }
+    if (kind == ORC_GDW) {
+        *re = pow(18.0 * M_PI, -0.25) * (2.0 - x * x) * exp(-0.25 * x * x);
+        *im = 0.0;
+        return;
+    }
+    if (kind == ORC_CWGDW) {
+        *re = sqrt(8.0 / (1.0 + 5.0 * exp(1.0))) * pow(M_PI, -0.25) *
+              ((1.0 - x * x) * cos(x) - x * sin(x)) * exp(0.5 * (1.0 - x * x));
+        *im = 0.0;
+        return;
+    }
     if (kind == ORC_MORLET) {
         double w0 = p;
         double C = pow(M_PI, -0.25) /

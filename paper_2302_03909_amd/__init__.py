@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcwt.so")
 
 CWT_PERIODIC, CWT_ZERO = 0, 1
-CWT_MORLET, CWT_MEXHAT, CWT_DOG = 0, 1, 2
+CWT_MORLET, CWT_MEXHAT, CWT_DOG, CWT_CBSW, CWT_GDW, CWT_CWGDW, CWT_MW = 0, 1, 2, 3, 4, 5, 6
 CWT_FP64, CWT_FP32 = 0, 1
 CWT_METHOD_FFT, CWT_METHOD_SPLINE = 0, 1
 CWT_OK, CWT_EINVAL, CWT_EUNSUPPORTED, CWT_ENOMEM, CWT_EDEVICE = 0, -1, -2, -3, -4
@@ -42,7 +42,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("fft_len", ctypes.c_int64), ("host_only", ctypes.c_int32),
                 ("fft_mode", ctypes.c_int32), ("single_stream", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("psi_mode", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 EXPORTS = ["cwt_plan", "cwt_destroy", "cwt_out_is_complex", "cwt_out_elems", "cwt_out_elem_bytes",
@@ -108,6 +108,7 @@ _BOUNDARY = {"periodic": CWT_PERIODIC, "zero": CWT_ZERO}
 _PRECISION = {"fp64": CWT_FP64, "fp32": CWT_FP32}
 _METHOD = {"fft": CWT_METHOD_FFT, "spline": CWT_METHOD_SPLINE}
 _FFT_MODE = {"segmented": 0, "whole": 1}
+_PSI_MODE = {"aliased": 0, "analytic": 1}
 
 
 def _wavelet(name: str, param):
@@ -118,6 +119,9 @@ def _wavelet(name: str, param):
         return CWT_MEXHAT, 2.0
     if n == "dog":
         return CWT_DOG, 2.0 if param is None else float(param)
+    paper = {"cbsw": CWT_CBSW, "gdw": CWT_GDW, "cwgdw": CWT_CWGDW, "cw-gdw": CWT_CWGDW, "mw": CWT_MW}
+    if n in paper:
+        return paper[n], 0.0
     raise ValueError(f"unknown wavelet {name!r}")
 
 
@@ -128,12 +132,13 @@ class Plan:
 
     def __init__(self, n: int, boundary: str, wavelet: str, scales, param=None,
                  precision: str = "fp64", method: str = "fft", fft_len: int = 0,
-                 host_only: bool = False, fft_mode: str = "segmented", single_stream: bool = False):
+                 host_only: bool = False, fft_mode: str = "segmented", single_stream: bool = False,
+                 psi_mode: str = "aliased"):
         lib = load()
         kind, par = _wavelet(wavelet, param)
         sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64).ravel())
         opts = _Opts(_PRECISION[precision], _METHOD[method], int(fft_len), 1 if host_only else 0,
-                     _FFT_MODE[fft_mode], 1 if single_stream else 0)
+                     _FFT_MODE[fft_mode], 1 if single_stream else 0, _PSI_MODE[psi_mode])
         h = ctypes.c_void_p()
         _check(lib.cwt_plan(ctypes.byref(h), int(n), _BOUNDARY[boundary], _Wavelet(kind, par),
                             sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sc.size,

@@ -43,39 +43,60 @@ struct TableBuilder {
 // amp/cph below).  psi^(u) = phase * amp(u) with amp real; conj(phase) = i^cph.
 
 struct Wavelet {
-    int kind = 0;   // CWT_MORLET, CWT_MEXHAT, CWT_DOG
+    int kind = 0;   // CWT_MORLET, CWT_MEXHAT, CWT_DOG, CWT_CBSW, CWT_GDW, CWT_CWGDW (CWT_MW is
+                    // planned as CWT_MORLET with w0 = -4)
     double w0 = 6.0;
     int m = 2;
-    double cmor = 0.0, kappa = 0.0, gnorm = 0.0;
+    double cmor = 0.0, kappa = 0.0, gnorm = 0.0, cn = 0.0;
 
     void init() {
         if (kind == CWT_MORLET) {
             kappa = std::exp(-0.5 * w0 * w0);
             cmor = std::pow(M_PI, -0.25) / std::sqrt(1.0 + std::exp(-w0 * w0) - 2.0 * std::exp(-0.75 * w0 * w0));
+        } else if (kind == CWT_CBSW) {
+            cn = std::sqrt(30.0 / 31.0);  // Table 2
+        } else if (kind == CWT_GDW) {
+            cn = std::pow(18.0 * M_PI, -0.25);  // Table 2
+        } else if (kind == CWT_CWGDW) {
+            cn = std::sqrt(8.0 / (1.0 + 5.0 * std::exp(1.0))) * std::pow(M_PI, -0.25);  // Table 2
         } else {
             gnorm = 1.0 / std::sqrt(std::tgamma(m + 0.5));
         }
     }
     bool complex_out() const { return kind == CWT_MORLET; }
+    // spectrum limited to a band (Gaussian decay); the cubic B-spline
+    // wavelet's transform decays only like u^-4
+    bool band_limited() const { return kind != CWT_CBSW; }
+    static double bspline3(double x) {
+        x = std::fabs(x);
+        if (x < 1.0) return 2.0 / 3.0 - x * x + 0.5 * x * x * x;
+        if (x < 2.0) return (2.0 - x) * (2.0 - x) * (2.0 - x) / 6.0;
+        return 0.0;
+    }
     // |psi(x)| in the time domain
     double abs_time(double x) const {
-        double g = std::exp(-0.5 * x * x);
-        if (kind == CWT_MORLET)
+        if (kind == CWT_MORLET) {
+            const double g = std::exp(-0.5 * x * x);
             return cmor * g * std::sqrt(std::max(0.0, 1.0 - 2.0 * kappa * std::cos(w0 * x) + kappa * kappa));
-        // probabilists' Hermite polynomial He_m
-        double hm1 = 1.0, h = x;
-        for (int n = 1; n < m; ++n) {
-            double hn = x * h - n * hm1;
-            hm1 = h;
-            h = hn;
         }
-        return std::fabs(h) * g * gnorm;
+        return std::abs(psi_time(x));
     }
-    // psi(x) in the time domain: Morlet C (e^{i w0 x} - kappa) e^{-x^2/2};
-    // DOG(m) -Gamma(m + 1/2)^{-1/2} He_m(x) e^{-x^2/2}
+    // psi(x) in the time domain:
+    //   Morlet(w0)  C (e^{i w0 x} - kappa) e^{-x^2/2}
+    //   DOG(m)      -Gamma(m + 1/2)^{-1/2} He_m(x) e^{-x^2/2}
+    //   CBSW        C_N (2 beta3(x) - beta3(x + 1) - beta3(x - 1))          (Table 2)
+    //   GDW         C_N (2 - x^2) e^{-x^2/4}                                (Table 2)
+    //   CW-GDW      C_N ((1 - x^2) cos x - x sin x) e^{(1 - x^2)/2}         (Table 2)
     std::complex<double> psi_time(double x) const {
-        double g = std::exp(-0.5 * x * x);
-        if (kind == CWT_MORLET) return cmor * g * std::complex<double>(std::cos(w0 * x) - kappa, std::sin(w0 * x));
+        if (kind == CWT_MORLET) {
+            const double g = std::exp(-0.5 * x * x);
+            return cmor * g * std::complex<double>(std::cos(w0 * x) - kappa, std::sin(w0 * x));
+        }
+        if (kind == CWT_CBSW) return {cn * (2.0 * bspline3(x) - bspline3(x + 1.0) - bspline3(x - 1.0)), 0.0};
+        if (kind == CWT_GDW) return {cn * (2.0 - x * x) * std::exp(-0.25 * x * x), 0.0};
+        if (kind == CWT_CWGDW)
+            return {cn * ((1.0 - x * x) * std::cos(x) - x * std::sin(x)) * std::exp(0.5 * (1.0 - x * x)), 0.0};
+        const double g = std::exp(-0.5 * x * x);
         double hm1 = 1.0, h = x;
         for (int n = 1; n < m; ++n) {
             double hn = x * h - n * hm1;
@@ -84,14 +105,35 @@ struct Wavelet {
         }
         return {-h * g * gnorm, 0.0};
     }
-    // real amplitude of the spectrum
+    // real amplitude of the spectrum psi^(u) = int psi(x) e^{-iux} dx:
+    //   Morlet  C sqrt(2 pi) (e^{-(u - w0)^2/2} - kappa e^{-u^2/2})
+    //   DOG(m)  Gamma(m + 1/2)^{-1/2} sqrt(2 pi) u^m e^{-u^2/2}   (times the phase i^-cph)
+    //   CBSW    64 C_N sin^6(u/2) / u^4                            (Table 2)
+    //   GDW     8 sqrt(pi) C_N u^2 e^{-u^2}                        (Table 2)
+    //   CW-GDW  sqrt(2 pi) C_N u (u cosh u - sinh u) e^{-u^2/2}    (Table 2)
     double amp(double u) const {
         if (kind == CWT_MORLET)
             return cmor * std::sqrt(2.0 * M_PI) * (std::exp(-0.5 * (u - w0) * (u - w0)) - kappa * std::exp(-0.5 * u * u));
+        if (kind == CWT_CBSW) {
+            if (std::fabs(u) < 1e-3) {
+                // sin^6(u/2)/u^4 = u^2/64 (1 - u^2/4 + ...)
+                return cn * u * u * (1.0 - u * u / 4.0);
+            }
+            const double sh = std::sin(0.5 * u);
+            const double s2 = sh * sh;
+            return 64.0 * cn * s2 * s2 * s2 / (u * u * u * u);
+        }
+        if (kind == CWT_GDW) return 8.0 * std::sqrt(M_PI) * cn * u * u * std::exp(-u * u);
+        if (kind == CWT_CWGDW) {
+            // u cosh(u) e^{-u^2/2} and sinh(u) e^{-u^2/2} as sums of two Gaussians
+            const double ep = std::exp(u - 0.5 * u * u), em = std::exp(-u - 0.5 * u * u);
+            return std::sqrt(2.0 * M_PI) * cn * u * (0.5 * u * (ep + em) - 0.5 * (ep - em));
+        }
         return std::pow(u, m) * std::sqrt(2.0 * M_PI) * std::exp(-0.5 * u * u) * gnorm;
     }
-    // DOG(m): psi^ = (-1)^{m+1} i^m amp  ->  conj(phase) = i^{(m+2) mod 4}
-    int cph() const { return kind == CWT_MORLET ? 0 : (m + 2) % 4; }
+    // DOG(m): psi^ = (-1)^{m+1} i^m amp  ->  conj(phase) = i^{(m+2) mod 4};
+    // the others have a real spectrum
+    int cph() const { return (kind == CWT_MEXHAT || kind == CWT_DOG) ? (m + 2) % 4 : 0; }
 };
 
 }  // namespace cwt

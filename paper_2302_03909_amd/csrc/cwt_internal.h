@@ -162,7 +162,7 @@ struct BatchArgs {
 // band [ulo, uhi] outside which it is negligible.
 struct SpecWavelet {
     int32_t kind, m;
-    double w0, cmor, kappa, gnorm, ulo, uhi;
+    double w0, cmor, kappa, gnorm, cn, ulo, uhi;
 };
 // count entries at tab[off..]: Psi_s(2 pi m / L) / L for m = m0 + e (full:
 // the signed bin of e in [0, L)); the job's workgroups start at block0
@@ -224,6 +224,7 @@ struct Plan {
     int32_t boundary = 0, kind = 0, precision = 0, method = 0;
     bool host_only = false;
     bool single_stream = false;  // keep every launch on the caller's stream
+    int32_t psi_mode = 0;        // CWT_PSI_ALIASED or CWT_PSI_ANALYTIC (whole-signal FFT only)
     double param = 0.0;
     int32_t S = 0;
     std::vector<double> scales;

@@ -269,11 +269,14 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
     const int lmax = 4096;  // FP64 segment forward in LDS
     const int pmax = fp64 ? 1024 : 2048;
     p.path.assign(p.S, PATH_LOCAL);
-    // local if the halo fits a quarter of the largest segment transform
+    // local if the halo fits a quarter of the largest segment transform (the
+    // literal form of Eq. discrete_CWT_conv, psi_mode ANALYTIC, takes every
+    // scale through the whole-signal spectrum)
+    const bool analytic = p.psi_mode == CWT_PSI_ANALYTIC;
     int64_t tcol = 0;
     std::vector<int> col;
     for (int j = 0; j < p.S; ++j) {
-        if (p.T[j] * 4 <= lmax) {
+        if (p.T[j] * 4 <= lmax && !analytic) {
             p.path[j] = PATH_LOCAL;
         } else {
             p.path[j] = PATH_COLUMN;
@@ -333,6 +336,10 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
             if (smooth_form(p.N, r, p2) && p2 >= 64 && factor_fft(p.N, a, b)) {
                 p.M = p.N;
                 p.load_mode = LOAD_PERIODIC;
+            } else if (analytic) {
+                // the printed form takes the DFT of the period itself
+                fail(CWT_EUNSUPPORTED, "psi_mode ANALYTIC with a periodic signal needs N of the form "
+                                       "2^a * {1,3,5,9}, 2^a >= 64");
             } else {
                 p.load_mode = LOAD_WRAP;
                 p.Twrap = tcol;
@@ -360,8 +367,21 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
         int64_t p2;
         smooth_form(p.M, r, p2);
 
-        double ulo, uhi;
-        spectral_band(w, p.rel, ulo, uhi);
+        double ulo = -1e300, uhi = 1e300;  // a spectrum without a band spans every bin
+        if (w.band_limited()) spectral_band(w, p.rel, ulo, uhi);
+        // spectrum sample at signed bin m: aliased (the sampled wavelet), or
+        // analytic (psi^(s w) at |w| <= pi only, Eq. discrete_CWT_conv; the
+        // Nyquist bin of an even length, where the paper leaves the sign of
+        // w open, takes the mean of psi^(s pi) and psi^(-s pi))
+        auto spec = [&](double s, int64_t m) {
+            int64_t ms = m % p.M;
+            if (ms < 0) ms += p.M;
+            if (ms >= (p.M + 1) / 2) ms -= p.M;  // signed bin in [-M/2, M/2)
+            const double om = 2.0 * M_PI * (double)ms / (double)p.M;
+            if (!analytic) return psi_aliased(w, s, om, ulo, uhi) / (double)p.M;
+            if (2 * ms == -p.M) return 0.5 * (w.amp(-s * M_PI) + w.amp(s * M_PI)) / (double)p.M;
+            return w.amp(s * om) / (double)p.M;
+        };
         struct Band {
             int j;
             int64_t mlo, B;
@@ -369,9 +389,12 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
         std::vector<Band> bands;
         for (int j : col) {
             double s = p.scales[j];
-            int64_t mlo = (int64_t)std::floor(p.M * ulo / (2.0 * M_PI * s)) - 1;
-            int64_t mhi = (int64_t)std::ceil(p.M * uhi / (2.0 * M_PI * s)) + 1;
-            int64_t B = mhi - mlo + 1;
+            int64_t mlo = -p.M / 2, B = p.M;
+            if (w.band_limited()) {
+                mlo = (int64_t)std::floor(p.M * ulo / (2.0 * M_PI * s)) - 1;
+                const int64_t mhi = (int64_t)std::ceil(p.M * uhi / (2.0 * M_PI * s)) + 1;
+                B = mhi - mlo + 1;
+            }
             if (B >= p.M) {
                 mlo = -p.M / 2;
                 B = p.M;
@@ -416,13 +439,11 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
             d.B = B;
             d.Q = Q;
             d.taba = (int64_t)tab.size();
-            for (int64_t m = mlo; m < mlo + B; ++m)
-                tab.push_back(psi_aliased(w, p.scales[d.sa], 2.0 * M_PI * (double)m / p.M, ulo, uhi) / p.M);
+            for (int64_t m = mlo; m < mlo + B; ++m) tab.push_back(spec(p.scales[d.sa], m));
             d.tabb = d.taba;
             if (d.sb >= 0) {
                 d.tabb = (int64_t)tab.size();
-                for (int64_t m = mlo; m < mlo + B; ++m)
-                    tab.push_back(psi_aliased(w, p.scales[d.sb], 2.0 * M_PI * (double)m / p.M, ulo, uhi) / p.M);
+                for (int64_t m = mlo; m < mlo + B; ++m) tab.push_back(spec(p.scales[d.sb], m));
             }
             ColumnLaunch *cl = nullptr;
             for (auto &c : p.columns)
@@ -948,6 +969,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     sw.cmor = w.cmor;
     sw.kappa = w.kappa;
     sw.gnorm = w.gnorm;
+    sw.cn = w.cn;
     sw.ulo = ulo;
     sw.uhi = uhi;
     HIPCHK(launch_spectrum_tables(sw, reinterpret_cast<const SpecJob *>(base + o_jobs), (int)jobs.size(),
@@ -1059,6 +1081,11 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
     if (fft_len < 0) fail(CWT_EINVAL, "fft_len must be >= 0");
     if (opts && opts->fft_mode != CWT_FFT_SEGMENTED && opts->fft_mode != CWT_FFT_WHOLE)
         fail(CWT_EINVAL, "unknown fft_mode");
+    const int psi_mode = opts ? opts->psi_mode : CWT_PSI_ALIASED;
+    if (psi_mode != CWT_PSI_ALIASED && psi_mode != CWT_PSI_ANALYTIC) fail(CWT_EINVAL, "unknown psi_mode");
+    const int fft_mode = opts ? opts->fft_mode : CWT_FFT_SEGMENTED;
+    if (psi_mode == CWT_PSI_ANALYTIC && (method != CWT_METHOD_FFT || fft_mode != CWT_FFT_WHOLE))
+        fail(CWT_EINVAL, "psi_mode ANALYTIC needs the FFT method with fft_mode WHOLE");
     Wavelet w;
     w.kind = wv.kind;
     if (wv.kind == CWT_MORLET) {
@@ -1070,6 +1097,14 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
         if (!(std::isfinite(wv.param) && wv.param >= 1.0 && wv.param <= 16.0 && wv.param == std::floor(wv.param)))
             fail(CWT_EINVAL, "DOG order must be an integer in [1, 16]");
         w.m = (int)wv.param;
+    } else if (wv.kind == CWT_MW) {
+        // Table 2's MW: C_N (e^{-4ix} - e^{-8}) e^{-x^2/2} = Morlet(-4)
+        w.kind = CWT_MORLET;
+        w.w0 = -4.0;
+    } else if (wv.kind == CWT_CBSW || wv.kind == CWT_GDW || wv.kind == CWT_CWGDW) {
+        if (wv.kind == CWT_CBSW && !(psi_mode == CWT_PSI_ANALYTIC))
+            fail(CWT_EUNSUPPORTED, "the cubic B-spline wavelet's spectrum is not band-limited: it is supported "
+                                   "by the FFT method with fft_mode WHOLE and psi_mode ANALYTIC only");
     } else {
         fail(CWT_EINVAL, "unknown wavelet kind");
     }
@@ -1082,7 +1117,8 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
         p->N = N;
         p->boundary = boundary;
         p->kind = wv.kind;
-        p->param = wv.kind == CWT_MORLET ? w.w0 : (double)w.m;
+        p->param = w.kind == CWT_MORLET ? w.w0 : (double)w.m;
+        p->psi_mode = psi_mode;
         p->precision = precision;
         p->method = method;
         p->host_only = opts && opts->host_only != 0;
@@ -1096,7 +1132,7 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
         p->T.resize(S);
         for (int j = 0; j < S; ++j) p->T[j] = (int64_t)std::ceil(p->chi * scales[j]);
         if (method == CWT_METHOD_FFT) {
-            p->fft_mode = opts ? opts->fft_mode : CWT_FFT_SEGMENTED;
+            p->fft_mode = fft_mode;
             if (p->fft_mode == CWT_FFT_WHOLE) build_fft_plan(*p, w, fft_len);
             else build_seg_plan(*p, w);
         } else {

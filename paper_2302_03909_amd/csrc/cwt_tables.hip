@@ -8,7 +8,10 @@
 // over the images q whose argument lies in the wavelet's band [ulo, uhi];
 // A is the real amplitude of the wavelet's Fourier transform:
 //   Morlet(w0): C sqrt(2 pi) (e^{-(u - w0)^2/2} - e^{-w0^2/2} e^{-u^2/2})
+//               (w0 = -4: the MW of Table 2)
 //   DOG(m):     Gamma(m + 1/2)^{-1/2} sqrt(2 pi) u^m e^{-u^2/2}
+//   GDW:        8 sqrt(pi) C_N u^2 e^{-u^2}                       (Table 2)
+//   CW-GDW:     sqrt(2 pi) C_N u (u cosh u - sinh u) e^{-u^2/2}   (Table 2)
 #include <hip/hip_runtime.h>
 
 #include "../../include/cwt.h"
@@ -21,6 +24,11 @@ __device__ __forceinline__ double spec_amp(const SpecWavelet &w, double u) {
     if (w.kind == CWT_MORLET) {
         const double d = u - w.w0;
         return w.cmor * r2pi * (exp(-0.5 * d * d) - w.kappa * exp(-0.5 * u * u));
+    }
+    if (w.kind == CWT_GDW) return 8.0 * 1.7724538509055160273 * w.cn * u * u * exp(-u * u);
+    if (w.kind == CWT_CWGDW) {
+        const double ep = exp(u - 0.5 * u * u), em = exp(-u - 0.5 * u * u);
+        return r2pi * w.cn * u * (0.5 * u * (ep + em) - 0.5 * (ep - em));
     }
     double p = 1.0;
     for (int i = 0; i < w.m; ++i) p *= u;

@@ -17,6 +17,9 @@ Workloads (all seeded with numpy's PCG64):
   paper's own field parameters are not given in the text.
 * ``log_scales`` -- scales a * (b/a)^(j/(S-1)), j = 0..S-1, both ends
   included (the paper discretises scales evenly in log, Sec. 3.1).
+* ``paper_f1`` / ``paper_f2`` / ``paper_scale_grid`` -- the test signals of
+  Sec. 4 (Eqs. signal_f1, signal_f2) and the level/sub-level scale grid of
+  Sec. 3.1, for the paper's accuracy comparison.
 * ``batch_specs`` / ``request_stream`` -- many uneven instances and a
   Poisson request stream for the batched and served forms.
 """
@@ -68,6 +71,30 @@ def lognormal_field(n: int, seed: int = SEED_FIELD_1M, sigma_g: float = 1.0,
     g = np.fft.irfft(modes, n=box)[:n]
     g = (g - g.mean()) / g.std() * sigma_g
     return np.exp(g - 0.5 * sigma_g ** 2) - 1.0
+
+
+def paper_f1(n: int = 512) -> np.ndarray:
+    """The periodic test signal of Sec. 4 (Eq. signal_f1),
+    2 cos x + cos(8x)/2 + sin(32x)/4, sampled at x = 2 pi i / n (period 2 pi)."""
+    x = 2 * np.pi * np.arange(n) / n
+    return 2 * np.cos(x) + 0.5 * np.cos(8 * x) + 0.25 * np.sin(32 * x)
+
+
+def paper_f2(n: int = 512) -> np.ndarray:
+    """The non-periodic test signal of Sec. 4 (Eq. signal_f2), exp(-x^2/2),
+    sampled at x = -6 + 12 i / n on [-6, 6)."""
+    x = -6.0 + 12.0 * np.arange(n) / n
+    return np.exp(-0.5 * x * x)
+
+
+def paper_scale_grid(n: int, cw: float, nsubs: int) -> np.ndarray:
+    """Scales (in samples) of the log grid of Sec. 3.1: w~ = w~_min
+    2^(i + j/nsubs) with w~_min = c_w pi / n (the largest scale), levels
+    i = 0 .. Nint(log2 n) - 1 and sub-levels j = 0 .. nsubs - 1; the scale in
+    samples is 1/w~ (largest first)."""
+    wmin = cw * np.pi / n
+    nlev = int(round(np.log2(n)))
+    return np.array([1.0 / (wmin * 2.0 ** (i + j / nsubs)) for i in range(nlev) for j in range(nsubs)])
 
 
 def log_scales(a: float, b: float, s: int) -> np.ndarray:

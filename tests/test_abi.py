@@ -210,3 +210,23 @@ def test_segment_groups_not_merged_for_fp64_or_short_signals():
     q = cwt.Plan(700, "zero", "mexhat", [2.0, 8.0, 30.0], precision="fp32", host_only=True)
     for x in _groups(q):
         assert x[1] <= 2048 and x[6] >= 1
+
+
+def test_analytic_mode_rejections():
+    # psi_mode ANALYTIC needs the whole-signal FFT (Sec. 3.1 form), a
+    # periodic length the FFT takes as it is; the CBSW only in that form
+    import paper_2302_03909_amd as cwt
+    with pytest.raises(cwt.CwtError) as e:
+        cwt.Plan(512, "periodic", "gdw", [2.0], psi_mode="analytic", host_only=True)
+    assert e.value.code == cwt.CWT_EINVAL
+    with pytest.raises(cwt.CwtError) as e:
+        cwt.Plan(512, "periodic", "cbsw", [2.0], fft_mode="whole", host_only=True)
+    assert e.value.code == cwt.CWT_EUNSUPPORTED
+    with pytest.raises(cwt.CwtError) as e:
+        cwt.Plan(512, "periodic", "cbsw", [2.0], method="spline", host_only=True)
+    assert e.value.code == cwt.CWT_EUNSUPPORTED
+    with pytest.raises(cwt.CwtError) as e:
+        cwt.Plan(4800, "periodic", "gdw", [2.0], fft_mode="whole", psi_mode="analytic", host_only=True)
+    assert e.value.code == cwt.CWT_EUNSUPPORTED
+    p = cwt.Plan(512, "periodic", "cbsw", [2.0, 300.0], fft_mode="whole", psi_mode="analytic", host_only=True)
+    assert p.fft_len == 512 and p.scale_path().tolist() == [cwt.PATH_COLUMN] * 2
