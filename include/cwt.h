@@ -42,6 +42,23 @@
  *                        any N; the output is FP64 or FP32 (precision), the
  *                        arithmetic FP64.
  *
+ *   CWT_METHOD_A19    -- the A19CWT of Sec. 3.4 (Eqs. a19cwt_01 - a19cwt_04):
+ *                        the wavelet approximated by piecewise cubics on
+ *                        uniform knots whose third derivative on each piece
+ *                        is the difference quotient of psi'' between the
+ *                        knots (Eq. 3rd_derivative_wavelet).  Undoing the
+ *                        integration by parts of Eq. a19cwt_03, the method
+ *                        computes the CWT of the cubic-spline interpolant of
+ *                        the samples with that C^2 piecewise cubic, whose B-
+ *                        spline coefficients are h^2 times the double running
+ *                        sum of psi''(h k).  The knot step is chi / N_chi, N_chi
+ *                        the smallest count whose interpolating cubic meets
+ *                        AE_A = 5e-4 (Eq. a19cwt_error, Sec. 3.6), chi where
+ *                        |psi| falls below 1e-14 of its maximum, and per scale
+ *                        the step follows the spline method's rule (whole-sample
+ *                        knots where h s >= 1, exact taps below); the same
+ *                        kernels run it, with the same exactness.
+ *
  * Wavelets (unit L2 norm, psi^(w) = int psi(x) e^{-iwx} dx):
  *   CWT_MORLET(w0): C (e^{i w0 x} - e^{-w0^2/2}) e^{-x^2/2} (complex output;
  *                   the corrected Morlet wavelet of Table 2, conjugated)
@@ -107,6 +124,7 @@ extern "C" {
 
 #define CWT_METHOD_FFT 0
 #define CWT_METHOD_SPLINE 1
+#define CWT_METHOD_A19 2
 
 /* How the FFT method organises the transform:
  *   CWT_FFT_SEGMENTED -- overlap-save segments of L = 2^l samples per group of
@@ -145,7 +163,8 @@ typedef struct {
 
 typedef struct {
     int32_t precision; /* CWT_FP64 (default) or CWT_FP32 */
-    int32_t method;    /* CWT_METHOD_FFT (default) or CWT_METHOD_SPLINE */
+    int32_t method;    /* CWT_METHOD_FFT (default), CWT_METHOD_SPLINE or
+                          CWT_METHOD_A19 */
     int64_t fft_len;   /* 0: the library picks the length of the whole-signal
                           FFT; otherwise a length >= the minimum the plan
                           needs, of the form 2^a * {1,3,5,9}, 2^a >= 64 */

@@ -28,6 +28,10 @@ Contents
   ``spline_target`` / ``spline_target_h`` / ``spline_target_scale`` (the
   exact CWT of the spline interpolant with the spline wavelet, by
   Gauss-Legendre quadrature over the merged knots of both splines).
+* A19 method (Sec. 3.4): ``psi2`` (second derivative), ``a19_pieces`` /
+  ``a19_eval`` (the piecewise-cubic wavelet of Eqs. piecewise_polys_psi and
+  3rd_derivative_wavelet), ``ae_a`` (Eq. a19cwt_error), ``a19_nchi`` and
+  ``a19_target`` (the exact CWT of f_c with that wavelet).
 
 Readings of the paper that this oracle takes (each is repeated in the
 design notes): scales and positions are in samples; the canonical result is
@@ -92,6 +96,10 @@ def _load():
         lib.oracle_spline_target_step.argtypes = [dp, ctypes.c_long, ctypes.c_long, dp, dp,
                                                   ctypes.c_long, ctypes.c_double, ctypes.c_double,
                                                   lp, ctypes.c_long, dp, dp, ctypes.c_int]
+        lib.oracle_psi2.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_long, dp, dp]
+        lib.oracle_pp_target.argtypes = [dp, ctypes.c_long, ctypes.c_long, dp, dp, ctypes.c_long,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, lp,
+                                         ctypes.c_long, dp, dp, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -499,3 +507,126 @@ def spline_target_d(f, boundary: str, d, delta: int, s: float, x,
                                  float(s), xs.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
                                  xs.size, _dp(re), _dp(im), nthreads)
     return re + 1j * im
+
+
+# --------------------------------------------------------------------------
+# A19CWT (Sec. 3.4).
+
+def psi2(wavelet: str, param: float | None, x) -> np.ndarray:
+    """Second derivative of a smooth wavelet, analytic (the A19 method
+    needs it, Eq. 3rd_derivative_wavelet)."""
+    kind, p = _wavelet(wavelet, param)
+    if kind == CBSW:
+        raise ValueError("the CBSW is not twice differentiable everywhere")
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+    re = np.empty_like(x)
+    im = np.empty_like(x)
+    _load().oracle_psi2(kind, p, _dp(x), x.size, _dp(re), _dp(im))
+    return re + 1j * im if kind == MORLET else re
+
+
+def a19_pieces(wavelet: str, param: float | None, h: float, chi_: float):
+    """The wavelet of the A19 method (Sec. 3.4, Eqs. piecewise_polys_psi and
+    3rd_derivative_wavelet) on the knots h j: its third derivative is
+    constant on each piece, 6 alpha_3 = (e[j+1] - e[j]) / h with e[j] the
+    second derivative of psi at h j for |j| <= J = ceil(chi / h) and zero at
+    j = -(J+1) and J+1; the function, its first and its second derivative
+    vanish at -(J+1) h, and the lower-order coefficients of each piece follow
+    from continuity.  Returns (coefficients [pieces, 4] of t^0..t^3, y0, h)
+    over the 2J + 2 pieces of [-(J+1) h, (J+1) h)."""
+    import math
+    J = int(np.ceil(chi_ / h - 1e-9))
+    j = np.arange(-J - 1, J + 2)
+    e = psi2(wavelet, param, h * j).astype(np.complex128)
+    e[0] = 0.0
+    e[-1] = 0.0
+    npieces = 2 * J + 2
+    coef = np.zeros((npieces, 4), dtype=np.complex128)
+    # value and slope at the start of each piece: with a3 = (e[k+1] - e[k]) /
+    # (6 h), a piece adds (e[k] + e[k+1]) h / 2 to the slope and
+    # dv h + (2 e[k] + e[k+1]) h^2 / 6 to the value; each is summed exactly
+    # rounded (math.fsum) over all earlier pieces, since psi'' exceeds psi by
+    # about w0^2 and plain running sums keep 1e-12 of psi's scale
+    dterms_r, dterms_i, vterms_r, vterms_i = [], [], [], []
+    for k in range(npieces):
+        dv = complex(math.fsum(dterms_r), math.fsum(dterms_i))
+        v = complex(math.fsum(vterms_r), math.fsum(vterms_i))
+        a3 = (e[k + 1] - e[k]) / (6.0 * h)
+        coef[k] = (v, dv, e[k] / 2.0, a3)
+        dt = (e[k] + e[k + 1]) * h / 2.0
+        vt_a = dv * h
+        vt_b = (2.0 * e[k] + e[k + 1]) * h * h / 6.0
+        dterms_r.append(dt.real)
+        dterms_i.append(dt.imag)
+        vterms_r += [vt_a.real, vt_b.real]
+        vterms_i += [vt_a.imag, vt_b.imag]
+    return coef, -(J + 1) * h, h
+
+
+def a19_eval(coef, y0: float, h: float, y) -> np.ndarray:
+    """The piecewise cubic of ``a19_pieces`` at the points y."""
+    y = np.asarray(y, dtype=np.float64)
+    k = np.floor((y - y0) / h).astype(np.int64)
+    ok = (k >= 0) & (k < coef.shape[0])
+    kk = np.clip(k, 0, coef.shape[0] - 1)
+    t = y - y0 - h * kk
+    c = coef[kk]
+    val = ((c[..., 3] * t + c[..., 2]) * t + c[..., 1]) * t + c[..., 0]
+    return np.where(ok, val, 0.0)
+
+
+def ae_a(wavelet: str, param: float | None, chi_: float, nchi: int, npts: int = 20001) -> float:
+    """AE_A(N_chi) of Eq. a19cwt_error: the error of the piecewise cubic of
+    Eq. piecewise_polys_psi on the 2 N_chi pieces of [-chi, chi], read as
+    the cubic spline interpolating psi at the knots -chi + k chi / N_chi
+    (the first of the method's two approximations; the second, Eq.
+    3rd_derivative_wavelet, is in ``a19_pieces``).  With this reading the
+    N_chi that Table 3 prints give AE_A of 6e-4 to 7e-4, "roughly" 5e-4."""
+    return ae_m(lambda x: psi(wavelet, param, x), chi_, chi_ / nchi, npts)
+
+
+def a19_nchi(wavelet: str, param: float | None, chi_: float, target: float = 5e-4) -> int:
+    """Smallest N_chi whose AE_A is at most the target (Sec. 3.6)."""
+    n = 2
+    while ae_a(wavelet, param, chi_, n) > target:
+        n += 1
+        if n > 4000:
+            raise RuntimeError("AE_A never reaches the target")
+    return n
+
+
+def a19_hstar(wavelet: str, param: float | None = None) -> float:
+    """Knot step chi / N_chi of the A19 wavelet, chi where |psi| falls below
+    1e-14 of its maximum (as for the spline method)."""
+    ch = chi(wavelet, param, SPLINE_CHI_REL)
+    return ch / a19_nchi(wavelet, param, ch)
+
+
+def a19_target(f, boundary: str, wavelet: str, s: float, h: float, x,
+               param: float | None = None, nthreads: int = 0) -> np.ndarray:
+    """The A19 transform at scale s with the wavelet's knots every h: by Eq.
+    a19cwt_03 (integration by parts undone) the CWT of the spline
+    interpolant f_c with psi_pp, (1/s) int f_c(u) conj(psi_pp((u - x)/s)) du,
+    integrated exactly over the merged knots."""
+    f = np.asarray(f, dtype=np.float64)
+    ch = chi(wavelet, param, SPLINE_CHI_REL)
+    coef, y0, hh = a19_pieces(wavelet, param, h, ch)
+    half = abs(y0) * s + 4
+    cext, c0 = _spline_ext(f, boundary, half)
+    ar = np.ascontiguousarray(coef.real.ravel())
+    ai = np.ascontiguousarray(coef.imag.ravel())
+    xs = np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+    re = np.empty(xs.size)
+    im = np.empty(xs.size)
+    _load().oracle_pp_target(_dp(cext), c0, cext.size, _dp(ar), _dp(ai), coef.shape[0], float(y0), float(hh),
+                             float(s), xs.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), xs.size, _dp(re), _dp(im),
+                             nthreads)
+    w = re + 1j * im
+    return w if is_complex(wavelet) else w.real
+
+
+def a19_target_scale(f, boundary: str, wavelet: str, s: float, hstar: float, x,
+                     param: float | None = None, nthreads: int = 0) -> np.ndarray:
+    """The A19 target at scale s for the plan step h* = chi / N_chi, with
+    the step per scale of ``spline_step``."""
+    return a19_target(f, boundary, wavelet, s, spline_step(hstar, s), x, param=param, nthreads=nthreads)

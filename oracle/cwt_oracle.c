@@ -104,6 +104,54 @@ static void psi_eval(int kind, double p, double x, double *re, double *im) {
     }
 }
 
+/* Second derivative of the smooth wavelets (kinds 0, 1, 3, 4), written out
+ * by differentiating the forms above twice:
+ *   Morlet: C e^{-x^2/2} [e^{i w0 x}(x^2 - 2 i w0 x - w0^2 - 1) - e^{-w0^2/2}(x^2 - 1)]
+ *   DOG(m): -Gamma(m+1/2)^{-1/2} He_{m+2}(x) e^{-x^2/2}
+ *   GDW:    C e^{-x^2/4} [2 x^2 - 2 - (x^2 - 2)^2 / 4]
+ *   CW-GDW: C e^{(1-x^2)/2} [q2 - 2 x q1 + (x^2 - 1) q0] with
+ *           q0 = (1 - x^2) cos x - x sin x, q1 = -3 x cos x - (2 - x^2) sin x,
+ *           q2 = (x^2 - 5) cos x + 5 x sin x */
+static void psi2_eval(int kind, double p, double x, double *re, double *im) {
+    *im = 0.0;
+    if (kind == ORC_MORLET) {
+        double w0 = p;
+        double C = pow(M_PI, -0.25) /
+                   sqrt(1.0 + exp(-w0 * w0) - 2.0 * exp(-0.75 * w0 * w0));
+        double g = exp(-0.5 * x * x), k = exp(-0.5 * w0 * w0);
+        double ar = x * x - w0 * w0 - 1.0, ai = -2.0 * w0 * x;
+        double c = cos(w0 * x), s = sin(w0 * x);
+        *re = C * g * (c * ar - s * ai - k * (x * x - 1.0));
+        *im = C * g * (c * ai + s * ar);
+    } else if (kind == ORC_GDW) {
+        double u = x * x - 2.0;
+        *re = pow(18.0 * M_PI, -0.25) * exp(-0.25 * x * x) * (2.0 * x * x - 2.0 - 0.25 * u * u);
+    } else if (kind == ORC_CWGDW) {
+        double c = cos(x), s = sin(x);
+        double q0 = (1.0 - x * x) * c - x * s;
+        double q1 = -3.0 * x * c - (2.0 - x * x) * s;
+        double q2 = (x * x - 5.0) * c + 5.0 * x * s;
+        *re = sqrt(8.0 / (1.0 + 5.0 * exp(1.0))) * pow(M_PI, -0.25) * exp(0.5 * (1.0 - x * x)) *
+              (q2 - 2.0 * x * q1 + (x * x - 1.0) * q0);
+    } else if (kind == ORC_DOG) {
+        int m = (int)p + 2;
+        double hm1 = 1.0, h = x;
+        for (int n = 1; n < m; ++n) {
+            double hn = x * h - n * hm1;
+            hm1 = h;
+            h = hn;
+        }
+        *re = -h * exp(-0.5 * x * x) / sqrt(tgamma(p + 0.5));
+    } else {
+        *re = NAN;
+    }
+}
+
+int oracle_psi2(int kind, double p, const double *x, long n, double *re, double *im) {
+    for (long i = 0; i < n; ++i) psi2_eval(kind, p, x[i], &re[i], &im[i]);
+    return 0;
+}
+
 int oracle_psi(int kind, double p, const double *x, long n, double *re,
                double *im) {
     for (long i = 0; i < n; ++i) psi_eval(kind, p, x[i], &re[i], &im[i]);
@@ -410,6 +458,77 @@ int oracle_spline_target_step(const double *c, long c0, long nc,
                             pr += d_re[kk + Nd] * bb;
                             pi += d_im[kk + Nd] * bb;
                         }
+                        const double wq = hw * gw[q] / s;
+                        tr[cnt] = wq * fc * pr;
+                        ti[cnt] = -wq * fc * pi;
+                        ++cnt;
+                    }
+                }
+                a = b;
+            }
+            out_re[i] = pw_sum(tr, cnt);
+            out_im[i] = pw_sum(ti, cnt);
+        }
+        free(tr);
+        free(ti);
+    }
+    return 0;
+}
+
+/*
+ * CWT of the spline interpolant f_c with a piecewise-cubic wavelet given on
+ * np pieces of width dy starting at y0: on piece k (y in [y0 + k dy,
+ * y0 + (k+1) dy), t = y - y0 - k dy) the wavelet is sum_i a[4k+i] t^i
+ * (complex: a_re, a_im), zero outside.  W(s, x) = (1/s) int f_c(x + v)
+ * conj(psi(v/s)) dv over the merged knots (integers and s (y0 + k dy)),
+ * 4-point Gauss-Legendre per piece, in coordinates relative to the output.
+ */
+int oracle_pp_target(const double *c, long c0, long nc, const double *a_re,
+                     const double *a_im, long np, double y0, double dy,
+                     double s, const long *x, long nx, double *out_re,
+                     double *out_im, int nthreads) {
+    static const double gx[4] = {-0.8611363115940526, -0.3399810435848563,
+                                 0.3399810435848563, 0.8611363115940526};
+    static const double gw[4] = {0.3478548451374538, 0.6521451548625461,
+                                 0.6521451548625461, 0.3478548451374538};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    const double lo = s * y0, hi = s * (y0 + dy * (double)np);
+    const long maxpieces = (long)ceil(hi - lo) + np + 8;
+#pragma omp parallel
+    {
+        double *tr = (double *)malloc(sizeof(double) * maxpieces * 4);
+        double *ti = (double *)malloc(sizeof(double) * maxpieces * 4);
+#pragma omp for schedule(dynamic, 8)
+        for (long i = 0; i < nx; ++i) {
+            const long xi = x[i];
+            long nint = (long)floor(lo) + 1;
+            long k = 1; /* next wavelet knot: s (y0 + k dy) */
+            double a = lo;
+            long cnt = 0;
+            while (a < hi) {
+                double bi = (double)nint;
+                double bk = (k < np) ? s * (y0 + dy * (double)k) : hi;
+                double b = bi < bk ? bi : bk;
+                if (b > hi) b = hi;
+                if (bi <= b) ++nint;
+                if (bk <= b) ++k;
+                if (b > a) {
+                    const double mid = 0.5 * (a + b), hw = 0.5 * (b - a);
+                    const long nf = (long)floor(mid);
+                    long kp = (long)floor((mid / s - y0) / dy);
+                    if (kp < 0) kp = 0;
+                    if (kp >= np) kp = np - 1;
+                    for (int q = 0; q < 4; ++q) {
+                        const double v = mid + hw * gx[q];
+                        double fc = 0.0;
+                        for (long m = nf - 1; m <= nf + 2; ++m)
+                            fc += coef(c, c0, nc, xi + m) * beta3(v - (double)m);
+                        const double t = v / s - y0 - dy * (double)kp;
+                        const double *ar = a_re + 4 * kp, *ai = a_im + 4 * kp;
+                        const double pr = ((ar[3] * t + ar[2]) * t + ar[1]) * t + ar[0];
+                        const double pi = ((ai[3] * t + ai[2]) * t + ai[1]) * t + ai[0];
                         const double wq = hw * gw[q] / s;
                         tr[cnt] = wq * fc * pr;
                         ti[cnt] = -wq * fc * pi;

@@ -105,6 +105,38 @@ struct Wavelet {
         }
         return {-h * g * gnorm, 0.0};
     }
+    // psi''(x), differentiated by hand from psi_time (the A19 method's
+    // third-derivative estimate, Eq. 3rd_derivative_wavelet, needs it):
+    //   Morlet  C e^{-x^2/2} [e^{i w0 x} (x^2 - 2 i w0 x - w0^2 - 1) - kappa (x^2 - 1)]
+    //   DOG(m)  -Gamma(m + 1/2)^{-1/2} He_{m+2}(x) e^{-x^2/2}
+    //   GDW     C_N e^{-x^2/4} (2 x^2 - 2 - (x^2 - 2)^2 / 4)
+    //   CW-GDW  C_N e^{(1-x^2)/2} (q'' - 2 x q' + (x^2 - 1) q), q = (1 - x^2) cos x - x sin x
+    std::complex<double> psi2_time(double x) const {
+        if (kind == CWT_MORLET) {
+            const double g = std::exp(-0.5 * x * x);
+            const std::complex<double> e(std::cos(w0 * x), std::sin(w0 * x));
+            return cmor * g * (e * std::complex<double>(x * x - w0 * w0 - 1.0, -2.0 * w0 * x) - kappa * (x * x - 1.0));
+        }
+        if (kind == CWT_GDW) {
+            const double u = x * x - 2.0;
+            return {cn * std::exp(-0.25 * x * x) * (2.0 * x * x - 2.0 - 0.25 * u * u), 0.0};
+        }
+        if (kind == CWT_CWGDW) {
+            const double c = std::cos(x), sn = std::sin(x);
+            const double q0 = (1.0 - x * x) * c - x * sn;
+            const double q1 = -3.0 * x * c - (2.0 - x * x) * sn;
+            const double q2 = (x * x - 5.0) * c + 5.0 * x * sn;
+            return {cn * std::exp(0.5 * (1.0 - x * x)) * (q2 - 2.0 * x * q1 + (x * x - 1.0) * q0), 0.0};
+        }
+        if (kind == CWT_CBSW) return {std::nan(""), 0.0};
+        double hm1 = 1.0, h = x;
+        for (int n = 1; n < m + 2; ++n) {
+            double hn = x * h - n * hm1;
+            hm1 = h;
+            h = hn;
+        }
+        return {-h * std::exp(-0.5 * x * x) * gnorm, 0.0};
+    }
     // real amplitude of the spectrum psi^(u) = int psi(x) e^{-iux} dx:
     //   Morlet  C sqrt(2 pi) (e^{-(u - w0)^2/2} - kappa e^{-u^2/2})
     //   DOG(m)  Gamma(m + 1/2)^{-1/2} sqrt(2 pi) u^m e^{-u^2/2}   (times the phase i^-cph)

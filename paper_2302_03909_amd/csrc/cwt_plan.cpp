@@ -1077,7 +1077,8 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
     int method = opts ? opts->method : CWT_METHOD_FFT;
     int64_t fft_len = opts ? opts->fft_len : 0;
     if (precision != CWT_FP64 && precision != CWT_FP32) fail(CWT_EINVAL, "unknown precision");
-    if (method != CWT_METHOD_FFT && method != CWT_METHOD_SPLINE) fail(CWT_EINVAL, "unknown method");
+    if (method != CWT_METHOD_FFT && method != CWT_METHOD_SPLINE && method != CWT_METHOD_A19)
+        fail(CWT_EINVAL, "unknown method");
     if (fft_len < 0) fail(CWT_EINVAL, "fft_len must be >= 0");
     if (opts && opts->fft_mode != CWT_FFT_SEGMENTED && opts->fft_mode != CWT_FFT_WHOLE)
         fail(CWT_EINVAL, "unknown fft_mode");
@@ -1360,7 +1361,7 @@ static int exec_impl(cwt_plan_t plan, const void *signal, void *out, void *works
         const hipError_t e = launch();
         if (e != hipSuccess) fail(CWT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
-    if (p.method == CWT_METHOD_SPLINE) {
+    if (p.method != CWT_METHOD_FFT) {
         run(st, spline_kernel_name(p, 0), nn * sb + 16.0 * (double)p.spl_len, "spline sums launch",
             [&] { return launch_spline(p, signal, out, workspace, st, 0); });
         run(st, spline_kernel_name(p, 1), nn * p.S * eb, "spline taps launch",
@@ -1666,14 +1667,14 @@ int64_t cwt_plan_fft_len(cwt_plan_t plan) { return plan ? plan->p->M : -1; }
 int cwt_plan_spline_delta(cwt_plan_t plan, int32_t *delta) {
     if (!plan || !delta) return CWT_EINVAL;
     const Plan &p = *plan->p;
-    for (int j = 0; j < p.S; ++j) delta[j] = p.method == CWT_METHOD_SPLINE ? p.spl_delta[j] : 0;
+    for (int j = 0; j < p.S; ++j) delta[j] = p.method != CWT_METHOD_FFT ? p.spl_delta[j] : 0;
     return CWT_OK;
 }
 
 int cwt_plan_spline_taps(cwt_plan_t plan, int32_t *taps) {
     if (!plan || !taps) return CWT_EINVAL;
     const Plan &p = *plan->p;
-    for (int j = 0; j < p.S; ++j) taps[j] = p.method == CWT_METHOD_SPLINE ? p.spl_ntaps[j] : 0;
+    for (int j = 0; j < p.S; ++j) taps[j] = p.method != CWT_METHOD_FFT ? p.spl_ntaps[j] : 0;
     return CWT_OK;
 }
 
@@ -1689,7 +1690,9 @@ int cwt_plan_describe(cwt_plan_t plan, char *buf, size_t size) {
         s += line;
     };
     add("N=%lld S=%d method=%s precision=%s workspace=%zu tables=%zu\n", (long long)p.N, p.S,
-        p.method == CWT_METHOD_SPLINE ? "spline" : (p.fft_mode == CWT_FFT_WHOLE ? "fft-whole" : "fft-segmented"),
+        p.method == CWT_METHOD_SPLINE ? "spline"
+        : p.method == CWT_METHOD_A19 ? "a19"
+                                     : (p.fft_mode == CWT_FFT_WHOLE ? "fft-whole" : "fft-segmented"),
         p.precision == CWT_FP64 ? "fp64" : "fp32", p.ws_bytes, p.table_bytes);
     for (const auto &g : p.segs)
         add("%s L=%d P=%d B=%d Tg=%lld V=%lld nseg=%lld nchunk=%d iters=%d scales=%zu%s%s\n",
@@ -1699,7 +1702,7 @@ int cwt_plan_describe(cwt_plan_t plan, char *buf, size_t size) {
     for (const auto &l : p.seg_launches)
         add("launch P=%d groups=%zu forward=%zu reduce=%zu inverse=%zu\n", l.P, l.gdev.size(), l.fwd.size(),
             l.red.size(), l.inv.size());
-    if (p.method == CWT_METHOD_SPLINE) {
+    if (p.method != CWT_METHOD_FFT) {
         add("spline h*=%.6f E=%lld tiles=%zu\n", p.hstar, (long long)p.spl_E, p.spl_work.size());
         for (int j = 0; j < p.S; ++j)
             add("spline scale=%d delta=%d R=%d I=%d taps=%d exact=%d\n", j, p.spl[j].delta, p.spl[j].R, p.spl[j].I,

@@ -172,12 +172,56 @@ static std::vector<cd> exact_taps(const std::vector<cd> &d, int K, int nd, doubl
     return om;
 }
 
+// B-spline coefficients a[k], k in [-K, K] (at k + K), of the A19 wavelet at
+// step h (Sec. 3.4): the C^2 piecewise cubic on the knots h k whose second
+// derivative interpolates e[k] = psi''(h k), |k| <= J = ceil(chi / h) (zero
+// beyond), linearly between the knots (its third derivative on a piece is
+// then the difference quotient of Eq. 3rd_derivative_wavelet), and that
+// vanishes to the left of -(J + 1) h.  With psi(y) = sum_k a[k] beta3(y/h - k),
+// psi''(h m) = (a[m+1] - 2 a[m] + a[m-1]) / h^2, so a is h^2 times the
+// double running sum of e: a[k] = h^2 sum_{m < k} (k - m) e[m].
+// The two running sums are compensated (Neumaier): psi'' is larger than psi
+// by about w0^2 and the sums run over hundreds of knots, so plain sums would
+// leave about 1e-12 of psi's scale in a.
+struct CompSum {
+    double s = 0.0, c = 0.0;
+    void add(double x) {
+        const double t = s + x;
+        c += std::fabs(s) >= std::fabs(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    double value() const { return s + c; }
+};
+static std::vector<cd> a19_coeffs(const Wavelet &w, double h, int K, double chi) {
+    const int J = (int)std::ceil(chi / h - 1e-9);
+    std::vector<cd> a(2 * (size_t)K + 1, cd(0.0));
+    CompSum s1r, s1i, s2r, s2i;  // running sums of e and of the first sum
+    for (int k = -K; k <= K; ++k) {
+        a[(size_t)(k + K)] = h * h * cd(s2r.value(), s2i.value());
+        const cd e = (k >= -J && k <= J) ? w.psi2_time(h * k) : cd(0.0);
+        s1r.add(e.real());
+        s1i.add(e.imag());
+        s2r.add(s1r.s);
+        s2r.add(s1r.c);
+        s2i.add(s1i.s);
+        s2i.add(s1i.c);
+    }
+    return a;
+}
+
 static const int kSplineBlock = 2048;  // elements per block of the running sums and the max|f| reduction (= kSB of the kernels)
 
 void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
     const double chi14 = spline_chi(w, 1e-14);  // truncation used for h* (Table 2 keeps |psi| near 1e-14)
     const double chi17 = spline_chi(w, 1e-17);  // truncation of d_s
+    const bool a19 = p.method == CWT_METHOD_A19;
     p.hstar = cached_h_star(w, chi14);
+    if (a19) {
+        // N_chi: the fewest pieces on [-chi, chi] whose interpolating cubic
+        // spline meets AE_A = 5e-4, i.e. knot step chi / N_chi <= h*
+        const double nchi = std::ceil(chi14 / p.hstar - 1e-12);
+        p.hstar = chi14 / nchi;
+    }
     p.path.assign(p.S, PATH_SPLINE);
     p.spl.resize(p.S);
     p.spl_delta.resize(p.S);
@@ -198,7 +242,7 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
         const int nd = (int)std::ceil(chi17 / h - 2.0) + 2;
         if (nd > 1800) fail(CWT_EUNSUPPORTED, "spline method: more than 3601 wavelet coefficients at this scale");
         const int K = std::max(nd, (int)std::ceil(chi17 / h)) + 40;
-        const std::vector<cd> dk = wavelet_coeffs(w, h, K);
+        const std::vector<cd> dk = a19 ? a19_coeffs(w, h, K, chi14) : wavelet_coeffs(w, h, K);
         SplineScaleDev &sc = p.spl[j];
         sc.d_off = (int64_t)dtab.size();
         int ntap;

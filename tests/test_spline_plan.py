@@ -67,3 +67,14 @@ def test_workspace_grows_with_support():
     a = host_plan(1 << 16, "morlet", 6.0, [4.0])
     b = host_plan(1 << 16, "morlet", 6.0, [4.0, 4096.0])
     assert b.workspace_bytes > a.workspace_bytes > 16 * (1 << 16)
+
+
+@pytest.mark.parametrize("wav,par", [("mexhat", None), ("morlet", 6.0), ("dog", 4.0), ("cwgdw", None), ("mw", None)])
+def test_a19_step_matches_oracle(wav, par):
+    # A19 (Sec. 3.4): knot step chi / N_chi, N_chi the fewest pieces meeting
+    # AE_A = 5e-4 (Eq. a19cwt_error), found independently by the oracle
+    p = cwt.Plan(4096, "zero", wav, [0.5, 3.0, 40.0, 900.0], param=par, method="a19", host_only=True)
+    ref = oracle.a19_hstar(wav, par)
+    assert abs(p.spline_hstar() - ref) <= 1e-12 * ref
+    assert p.spline_delta().tolist() == [oracle.spline_delta(ref, s) for s in (0.5, 3.0, 40.0, 900.0)]
+    assert "method=a19" in p.describe()
