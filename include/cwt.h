@@ -58,6 +58,17 @@
  *                        the step follows the spline method's rule (whole-sample
  *                        knots where h s >= 1, exact taps below); the same
  *                        kernels run it, with the same exactness.
+ *   CWT_METHOD_V97    -- the V97CWT of Sec. 3.2 (Eqs. beta3_wavelet_approx -
+ *                        fir_filter_qi): the unit-step sum with the wavelet
+ *                        at scale s = 2^i r / w~_max (1 <= r < 2) replaced by
+ *                        sum_k p_r(k) beta3(t / 2^i - k), p_r = q_r * q12,
+ *                        q_r(k) the integral of psi(w~_max y / r) over the cell
+ *                        [k - 1/2, k + 1/2] (Eq. qj) and q12 the inverse filter
+ *                        of the sampled quartic B-spline (Eq. q_12), w~_max =
+ *                        1.34 c_w (Table 3); computed as the filter chain of
+ *                        Eqs. fir_filter_beta - fir_filter_qi per octave level
+ *                        i.  Scales below 1 / w~_max are rejected
+ *                        (CWT_EUNSUPPORTED); arithmetic FP64.
  *
  * Wavelets (unit L2 norm, psi^(w) = int psi(x) e^{-iwx} dx):
  *   CWT_MORLET(w0): C (e^{i w0 x} - e^{-w0^2/2}) e^{-x^2/2} (complex output;
@@ -125,6 +136,7 @@ extern "C" {
 #define CWT_METHOD_FFT 0
 #define CWT_METHOD_SPLINE 1
 #define CWT_METHOD_A19 2
+#define CWT_METHOD_V97 3
 
 /* How the FFT method organises the transform:
  *   CWT_FFT_SEGMENTED -- overlap-save segments of L = 2^l samples per group of
@@ -163,8 +175,8 @@ typedef struct {
 
 typedef struct {
     int32_t precision; /* CWT_FP64 (default) or CWT_FP32 */
-    int32_t method;    /* CWT_METHOD_FFT (default), CWT_METHOD_SPLINE or
-                          CWT_METHOD_A19 */
+    int32_t method;    /* CWT_METHOD_FFT (default), CWT_METHOD_SPLINE,
+                          CWT_METHOD_A19 or CWT_METHOD_V97 */
     int64_t fft_len;   /* 0: the library picks the length of the whole-signal
                           FFT; otherwise a length >= the minimum the plan
                           needs, of the form 2^a * {1,3,5,9}, 2^a >= 64 */

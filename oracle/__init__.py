@@ -32,6 +32,10 @@ Contents
   ``a19_eval`` (the piecewise-cubic wavelet of Eqs. piecewise_polys_psi and
   3rd_derivative_wavelet), ``ae_a`` (Eq. a19cwt_error), ``a19_nchi`` and
   ``a19_target`` (the exact CWT of f_c with that wavelet).
+* V97 method (Sec. 3.2): ``wavelet_cw``, ``v97_wmax`` (1.34 c_w), ``q12_filter``
+  (Eq. q_12), ``v97_q`` (Eq. qj), ``v97_kernel`` (the approximated wavelet of
+  Eqs. beta3_wavelet_approx and pj), ``v97_points`` (the unit-step sum with
+  it) and ``ae_v`` (Eq. v97cwt_error).
 
 Readings of the paper that this oracle takes (each is repeated in the
 design notes): scales and positions are in samples; the canonical result is
@@ -97,6 +101,8 @@ def _load():
                                                   ctypes.c_long, ctypes.c_double, ctypes.c_double,
                                                   lp, ctypes.c_long, dp, dp, ctypes.c_int]
         lib.oracle_psi2.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_long, dp, dp]
+        lib.oracle_kernel_sum.argtypes = [dp, ctypes.c_long, ctypes.c_int, dp, dp, ctypes.c_long, lp,
+                                          ctypes.c_long, dp, dp, ctypes.c_int]
         lib.oracle_pp_target.argtypes = [dp, ctypes.c_long, ctypes.c_long, dp, dp, ctypes.c_long,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, lp,
                                          ctypes.c_long, dp, dp, ctypes.c_int]
@@ -630,3 +636,137 @@ def a19_target_scale(f, boundary: str, wavelet: str, s: float, hstar: float, x,
     """The A19 target at scale s for the plan step h* = chi / N_chi, with
     the step per scale of ``spline_step``."""
     return a19_target(f, boundary, wavelet, s, spline_step(hstar, s), x, param=param, nthreads=nthreads)
+
+
+# --------------------------------------------------------------------------
+# V97CWT (Sec. 3.2).
+
+def wavelet_cw(wavelet: str, param: float | None = None) -> float:
+    """c_w = 1 / argmax |u| |psi^(u)|^2 (Table 2: the ratio of scale to
+    pseudo frequency), by a scan and a bounded scalar maximisation."""
+    from scipy import optimize
+    u = np.linspace(-40.0, 40.0, 160001)
+    g = np.abs(u) * np.abs(psi_hat(wavelet, param, u)) ** 2
+    u0 = u[int(np.argmax(g))]
+    r = optimize.minimize_scalar(lambda v: -abs(v) * abs(psi_hat(wavelet, param, [v])[0]) ** 2,
+                                 bounds=(u0 - 1e-3, u0 + 1e-3), method="bounded",
+                                 options={"xatol": 1e-14})
+    return 1.0 / abs(r.x)
+
+
+def v97_wmax(wavelet: str, param: float | None = None) -> float:
+    """w~_max = 1.34 c_w (Sec. 3.6; Table 3 prints these values)."""
+    return 1.34 * wavelet_cw(wavelet, param)
+
+
+def q12_filter(K: int = 60) -> np.ndarray:
+    """Taps |k| <= K of q12, the convolution inverse of the quartic B-spline
+    sampled on the integers, (1, 76, 230, 76, 1) / 384 (Eq. q_12), from a
+    banded solve with a unit impulse on a range 4K wide."""
+    from scipy.linalg import solve_banded
+    n = 4 * K + 1
+    ab = np.zeros((5, n))
+    for d, v in zip(range(5), (1.0, 76.0, 230.0, 76.0, 1.0)):
+        ab[d, :] = v / 384.0
+    rhs = np.zeros(n)
+    rhs[2 * K] = 1.0
+    q = solve_banded((2, 2), ab, rhs)
+    return q[K:3 * K + 1]
+
+
+def v97_level(s: float, wmax: float):
+    """Octave level i and sub-level factor r in [1, 2) of s = 2^i r / w~_max."""
+    t = s * wmax
+    if t < 1.0 - 1e-12:
+        raise ValueError("V97 scales start at 1 / w~_max")
+    i = max(0, int(np.floor(np.log2(max(t, 1.0)))))
+    while i > 0 and 2.0 ** i > t:
+        i -= 1
+    while 2.0 ** (i + 1) <= t:
+        i += 1
+    return i, t / 2.0 ** i
+
+
+def v97_q(wavelet: str, param: float | None, r: float, wmax: float, nq: int) -> np.ndarray:
+    """q(k) = int_{k-1/2}^{k+1/2} psi(w~_max y / r) dy, |k| <= nq (Eq. qj),
+    by adaptive quadrature per cell (cut at the knots of the CBSW)."""
+    from scipy import integrate
+    cplx = is_complex(wavelet)
+    out = np.zeros(2 * nq + 1, dtype=np.complex128)
+    knots = [r * m / wmax for m in range(-3, 4)] if wavelet.lower() == "cbsw" else []
+    for k in range(-nq, nq + 1):
+        cuts = sorted({k - 0.5, k + 0.5} | {y for y in knots if k - 0.5 < y < k + 0.5})
+        re = im = 0.0
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            re += integrate.quad(lambda y: psi(wavelet, param, [wmax * y / r])[0].real, a, b,
+                                 epsabs=1e-17, epsrel=1e-14)[0]
+            if cplx:
+                im += integrate.quad(lambda y: psi(wavelet, param, [wmax * y / r])[0].imag, a, b,
+                                     epsabs=1e-17, epsrel=1e-14)[0]
+        out[k + nq] = re + 1j * im
+    return out
+
+
+def v97_kernel(wavelet: str, param: float | None, s: float, wmax: float | None = None):
+    """Taps t = -T..T of the V97 approximation of the scaled wavelet at scale
+    s = 2^i r / w~_max (Eqs. beta3_wavelet_approx and pj):
+    psi_v(t) = sum_k p(k) beta3(t / 2^i - k), p = q * q12, returned as
+    conj(psi_v(t)) / s (the weights of the unit-step sum), and T."""
+    wmax = v97_wmax(wavelet, param) if wmax is None else wmax
+    i, r = v97_level(s, wmax)
+    ch = chi(wavelet, param, 1e-17)
+    nq = int(np.ceil(ch * r / wmax + 0.5))
+    q = v97_q(wavelet, param, r, wmax, nq)
+    q12 = q12_filter(60)
+    p = np.convolve(q, q12)                     # index k + nq + 60
+    kp = nq + 60
+    step = 2 ** i
+    T = step * (kp + 2)
+    t = np.arange(-T, T + 1)
+    y = t / step
+    acc = np.zeros(t.size, dtype=np.complex128)
+    k0 = np.floor(y).astype(np.int64) - 1
+    for jj in range(4):
+        kk = k0 + jj
+        ok = (kk >= -kp) & (kk <= kp)
+        acc += np.where(ok, p[np.clip(kk + kp, 0, p.size - 1)] * beta3(y - kk), 0.0)
+    return np.conj(acc) / s, T
+
+
+def v97_points(f, boundary: str, wavelet: str, s: float, pos, param: float | None = None,
+               wmax: float | None = None, nthreads: int = 0) -> np.ndarray:
+    """The V97 transform at scale s and positions pos: the unit-step sum of
+    Sec. 3, Eq. discreteCWT, with the wavelet replaced by its V97
+    approximation (``v97_kernel``)."""
+    k, T = v97_kernel(wavelet, param, s, wmax)
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+    kr = np.ascontiguousarray(k.real)
+    ki = np.ascontiguousarray(k.imag)
+    ps = np.ascontiguousarray(np.asarray(pos, dtype=np.int64))
+    re = np.empty(ps.size)
+    im = np.empty(ps.size)
+    bc = PERIODIC if boundary == "periodic" else ZERO
+    _load().oracle_kernel_sum(_dp(f), f.size, bc, _dp(kr), _dp(ki), T,
+                              ps.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), ps.size, _dp(re), _dp(im),
+                              nthreads)
+    w = re + 1j * im
+    return w if is_complex(wavelet) else w.real
+
+
+def ae_v(wavelet: str, param: float | None, w: float, npts: int = 20001) -> float:
+    """AE_V(w) of Eq. v97cwt_error: how well sum_m p(m) beta3(x - m) with
+    p = q * q12 (q the cell integrals of psi(w x)) matches psi(w x), on npts
+    points of the wavelet's support |x| <= chi / w."""
+    ch = chi(wavelet, param, 1e-14)
+    nq = int(np.ceil(ch / w + 0.5))
+    q = v97_q(wavelet, param, 1.0, w, nq)
+    p = np.convolve(q, q12_filter(60))
+    kp = nq + 60
+    x = np.linspace(-ch / w, ch / w, npts)
+    k0 = np.floor(x).astype(np.int64) - 1
+    approx = np.zeros(x.size, dtype=np.complex128)
+    for jj in range(4):
+        kk = k0 + jj
+        approx += p[kk + kp] * beta3(x - kk)
+    ex = psi(wavelet, param, w * x)
+    return float(np.sum(np.abs(ex - approx)) / np.sum(np.abs(ex)))

@@ -545,3 +545,31 @@ int oracle_pp_target(const double *c, long c0, long nc, const double *a_re,
     }
     return 0;
 }
+
+/*
+ * W[b] = sum_{t=-T..T} f_ext[b + t] k[t + T] at the positions pos[i]: a
+ * direct sum with given kernel taps (complex: kr, ki), f_ext the periodic or
+ * zero extension.  Pairwise summation, as for the transform above.
+ */
+int oracle_kernel_sum(const double *f, long N, int boundary, const double *kr,
+                      const double *ki, long T, const long *pos, long npos,
+                      double *out_re, double *out_im, int nthreads) {
+    scale_kernel k;
+    k.T = T;
+    k.kr = (double *)kr;
+    k.ki = (double *)ki;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        double *br = (double *)malloc(sizeof(double) * (2 * T + 1));
+        double *bi = (double *)malloc(sizeof(double) * (2 * T + 1));
+#pragma omp for schedule(dynamic, 16)
+        for (long i = 0; i < npos; ++i)
+            one_output(f, N, boundary, &k, pos[i], br, bi, &out_re[i], &out_im[i]);
+        free(br);
+        free(bi);
+    }
+    return 0;
+}

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libcwt.so")
 CWT_PERIODIC, CWT_ZERO = 0, 1
 CWT_MORLET, CWT_MEXHAT, CWT_DOG, CWT_CBSW, CWT_GDW, CWT_CWGDW, CWT_MW = 0, 1, 2, 3, 4, 5, 6
 CWT_FP64, CWT_FP32 = 0, 1
-CWT_METHOD_FFT, CWT_METHOD_SPLINE, CWT_METHOD_A19 = 0, 1, 2
+CWT_METHOD_FFT, CWT_METHOD_SPLINE, CWT_METHOD_A19, CWT_METHOD_V97 = 0, 1, 2, 3
 CWT_OK, CWT_EINVAL, CWT_EUNSUPPORTED, CWT_ENOMEM, CWT_EDEVICE = 0, -1, -2, -3, -4
 PATH_LOCAL, PATH_COLUMN, PATH_SPLINE, PATH_SPLINE_DIRECT = 0, 1, 2, 3
 
@@ -106,7 +106,7 @@ def _check(rc: int):
 
 _BOUNDARY = {"periodic": CWT_PERIODIC, "zero": CWT_ZERO}
 _PRECISION = {"fp64": CWT_FP64, "fp32": CWT_FP32}
-_METHOD = {"fft": CWT_METHOD_FFT, "spline": CWT_METHOD_SPLINE, "a19": CWT_METHOD_A19}
+_METHOD = {"fft": CWT_METHOD_FFT, "spline": CWT_METHOD_SPLINE, "a19": CWT_METHOD_A19, "v97": CWT_METHOD_V97}
 _FFT_MODE = {"segmented": 0, "whole": 1}
 _PSI_MODE = {"aliased": 0, "analytic": 1}
 

@@ -266,6 +266,20 @@ struct Plan {
     int64_t spl_lds_bytes = 0;  // LDS of the tap-sum launch (largest tile plus its taps)
     SplineScaleDev *d_spl = nullptr;
     SplineWork *d_spl_work = nullptr;
+
+    // V97 method (Sec. 3.2): the launch sequence.  kind 0: f_0 = beta3 * f
+    // into buffer dst; 1: f_{a+1} = f_a * [h] upsampled by 2^a, src -> dst;
+    // 2: F_a = f_a * [q12] upsampled by 2^a, src -> the F array; 3: tap sums
+    // of the scales of level a, work items [w0, w1) of spl_work
+    struct V97Step {
+        int32_t kind, a, src, dst, w0, w1;
+    };
+    std::vector<V97Step> v97_steps;
+    double v97_wmax = 0.0;      // w~_max = 1.34 c_w (Table 3)
+    int32_t v97_nq12 = 0;       // q12 taps on each side
+    int64_t v97_flen = 0;       // length of the f buffers (N periodic, N + 2E zero boundary)
+    double *d_v97_q12 = nullptr;
+    size_t ws_fa_off = 0, ws_fb_off = 0;
     size_t ws_maxp_off = 0, ws_fx_off = 0, ws_state_off = 0, ws_carry_off = 0, ws_H_off = 0, ws_C_off = 0;
 
     // device tables (owned).  Segmented plans keep all of them in one
@@ -333,6 +347,9 @@ hipError_t launch_column(const Plan &p, const ColumnLaunch &c, const void *ws, v
 // phase 0: fixed-point running sums of the spline coefficients, 1: tap sums
 hipError_t launch_spline(const Plan &p, const void *signal, void *out, void *ws, hipStream_t st, int phase);
 std::string spline_kernel_name(const Plan &p, int phase);
+// step k of Plan::v97_steps
+hipError_t launch_v97(const Plan &p, size_t k, const void *signal, void *out, void *ws, hipStream_t st);
+std::string v97_kernel_name(const Plan &p, size_t k);
 
 // supported sizes
 bool local_size_ok(int L, int precision);

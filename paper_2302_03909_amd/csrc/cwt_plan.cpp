@@ -262,6 +262,7 @@ static void push_w23(TableBuilder &tb, int64_t &hi_off, int64_t &lo_off) {
 static const int64_t kMaxN = int64_t(1) << 26;
 
 void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &tb);  // cwt_spline_plan.cpp
+void build_v97_plan(Plan &p, const Wavelet &w);                       // cwt_spline_plan.cpp
 
 static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
     const bool fp64 = p.precision == CWT_FP64;
@@ -1077,7 +1078,8 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
     int method = opts ? opts->method : CWT_METHOD_FFT;
     int64_t fft_len = opts ? opts->fft_len : 0;
     if (precision != CWT_FP64 && precision != CWT_FP32) fail(CWT_EINVAL, "unknown precision");
-    if (method != CWT_METHOD_FFT && method != CWT_METHOD_SPLINE && method != CWT_METHOD_A19)
+    if (method != CWT_METHOD_FFT && method != CWT_METHOD_SPLINE && method != CWT_METHOD_A19 &&
+        method != CWT_METHOD_V97)
         fail(CWT_EINVAL, "unknown method");
     if (fft_len < 0) fail(CWT_EINVAL, "fft_len must be >= 0");
     if (opts && opts->fft_mode != CWT_FFT_SEGMENTED && opts->fft_mode != CWT_FFT_WHOLE)
@@ -1103,9 +1105,10 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
         w.kind = CWT_MORLET;
         w.w0 = -4.0;
     } else if (wv.kind == CWT_CBSW || wv.kind == CWT_GDW || wv.kind == CWT_CWGDW) {
-        if (wv.kind == CWT_CBSW && !(psi_mode == CWT_PSI_ANALYTIC))
+        if (wv.kind == CWT_CBSW && psi_mode != CWT_PSI_ANALYTIC && method != CWT_METHOD_V97)
             fail(CWT_EUNSUPPORTED, "the cubic B-spline wavelet's spectrum is not band-limited: it is supported "
-                                   "by the FFT method with fft_mode WHOLE and psi_mode ANALYTIC only");
+                                   "by the FFT method with fft_mode WHOLE and psi_mode ANALYTIC, and by the V97 "
+                                   "method");
     } else {
         fail(CWT_EINVAL, "unknown wavelet kind");
     }
@@ -1136,6 +1139,8 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
             p->fft_mode = fft_mode;
             if (p->fft_mode == CWT_FFT_WHOLE) build_fft_plan(*p, w, fft_len);
             else build_seg_plan(*p, w);
+        } else if (method == CWT_METHOD_V97) {
+            build_v97_plan(*p, w);
         } else {
             TableBuilder tb;
             build_spline_plan(*p, w, tb);
@@ -1361,6 +1366,16 @@ static int exec_impl(cwt_plan_t plan, const void *signal, void *out, void *works
         const hipError_t e = launch();
         if (e != hipSuccess) fail(CWT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
+    if (p.method == CWT_METHOD_V97) {
+        for (size_t k = 0; k < p.v97_steps.size(); ++k) {
+            const auto &sp = p.v97_steps[k];
+            const double bytes = sp.kind == 3 ? nn * eb * (double)p.S : 8.0 * (double)p.spl_len;
+            run(st, v97_kernel_name(p, k), bytes, "V97 launch",
+                [&] { return launch_v97(p, k, signal, out, workspace, st); });
+        }
+        if (!bare) note_use(p, st);
+        return CWT_OK;
+    }
     if (p.method != CWT_METHOD_FFT) {
         run(st, spline_kernel_name(p, 0), nn * sb + 16.0 * (double)p.spl_len, "spline sums launch",
             [&] { return launch_spline(p, signal, out, workspace, st, 0); });
@@ -1692,6 +1707,7 @@ int cwt_plan_describe(cwt_plan_t plan, char *buf, size_t size) {
     add("N=%lld S=%d method=%s precision=%s workspace=%zu tables=%zu\n", (long long)p.N, p.S,
         p.method == CWT_METHOD_SPLINE ? "spline"
         : p.method == CWT_METHOD_A19 ? "a19"
+        : p.method == CWT_METHOD_V97 ? "v97"
                                      : (p.fft_mode == CWT_FFT_WHOLE ? "fft-whole" : "fft-segmented"),
         p.precision == CWT_FP64 ? "fp64" : "fp32", p.ws_bytes, p.table_bytes);
     for (const auto &g : p.segs)

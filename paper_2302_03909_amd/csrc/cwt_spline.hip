@@ -326,12 +326,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     const int64_t rho_max = w.i0 - nd + mvalid + 1;
     const int F = fx[0];
     const int bad = fx[1];
-    if (active && p.mode == 1) {
-        // exact taps on c: S row m is c 2^F at position i0 - nd + m (R = 1,
-        // delta = 1, every thread active); rows past the last one some
-        // output uses are clamped
-        const double *cp = C + (E + w.i0 - nd);
-        for (int m = tid; m < rowsS; m += 256) S[stile_idx(m, 1, 0)] = cp[min(m, mvalid - 1)];
+    if (p.mode == 1) {
+        // S read directly from C (c 2^F for the spline method's exact taps,
+        // F_i for the V97 method): S row m, column r is C at position
+        // (i0 - nd + m) delta + r0 + r; rows past the last one some output
+        // uses are clamped.  All threads load, consecutive threads take
+        // consecutive columns of a row.
+        const double *cp = C + (E + (w.i0 - nd) * delta + w.r0);
+        for (int idx = tid; idx < rowsS * R; idx += 256) {
+            const int m = idx / R, rr = idx - m * R;
+            S[stile_idx(m, R, rr)] = cp[(int64_t)min(m, mvalid - 1) * delta + rr];
+        }
     } else if (active) {
         // rows in batches of BR: S rows m0..m0+BR-1 need H rows i - 2 .. i + 2,
         // i.e. the BR + 4 rows starting at i0 - nd + m0 - 2, loaded together
@@ -508,6 +513,138 @@ std::string spline_kernel_name(const Plan &p, int phase) {
     const std::string t = p.precision == CWT_FP64 ? "f64" : "f32";
     if (phase == 0) return "spline_sums<" + t + ">";
     return "spl_tap_kernel<" + t + (p.cplx_out ? ",complex>" : ",real>");
+}
+
+
+// ---------------------------------------------------------------------------
+// V97 method (Sec. 3.2): the filter chain of Eqs. fir_filter_beta,
+// iir_filter_0, fir_filter_hi and iir_filter_i, in FP64.  An f buffer holds
+// positions [-E, N + E) (zero boundary; the chain's support ends 2^(i+1) + 1
+// samples beyond the signal, inside E, so reads past the buffer are zeros) or
+// [0, N) read with wrapped indices (periodic).  The F array always holds
+// [-E, N + E), filled on the part the tap sums read.
+
+// value of an f buffer at position x
+__device__ __forceinline__ double fbuf(const double *__restrict__ b, int64_t N, int periodic, int64_t E, int64_t x) {
+    if (periodic) {
+        int64_t m = x % N;
+        if (m < 0) m += N;
+        return b[m];
+    }
+    const int64_t i = x + E;
+    return (i >= 0 && i < N + 2 * E) ? b[i] : 0.0;
+}
+
+// f_0 = f * beta3 sampled: (f[x-1] + 4 f[x] + f[x+1]) / 6 (Eq. fir_filter_beta);
+// thread 0 also clears the scaling exponent and flag the tap kernel reads
+template <typename R>
+__global__ __launch_bounds__(256) void v97_f0_kernel(const R *__restrict__ f, int64_t N, int periodic, int64_t E,
+                                                     int64_t flen, double *__restrict__ out, int *__restrict__ fx) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) {
+        fx[0] = 0;
+        fx[1] = 0;
+    }
+    if (i >= flen) return;
+    const int64_t x = periodic ? i : i - E;
+    const double a = sig_ext(f, N, periodic, x - 1), b = sig_ext(f, N, periodic, x),
+                 c = sig_ext(f, N, periodic, x + 1);
+    out[i] = (a + c + 4.0 * b) * (1.0 / 6.0);
+}
+
+// f_{a+1} = f_a * [h] upsampled by 2^a, h = (1, 4, 6, 4, 1) / 8 (Eq. h_filter
+// with n = 3; Eq. fir_filter_hi)
+__global__ __launch_bounds__(256) void v97_h_kernel(const double *__restrict__ in, int64_t N, int periodic, int64_t E,
+                                                    int64_t flen, int64_t step, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= flen) return;
+    const int64_t x = periodic ? i : i - E;
+    const double v = 6.0 * fbuf(in, N, periodic, E, x) +
+                     4.0 * (fbuf(in, N, periodic, E, x - step) + fbuf(in, N, periodic, E, x + step)) +
+                     (fbuf(in, N, periodic, E, x - 2 * step) + fbuf(in, N, periodic, E, x + 2 * step));
+    out[i] = v * 0.125;
+}
+
+// F_a = f_a * [q12] upsampled by 2^a (Eq. iir_filter_i), taps |k| <= K, on
+// positions [-EF, N + EF) of the F array
+__global__ __launch_bounds__(256) void v97_q12_kernel(const double *__restrict__ in, int64_t N, int periodic, int64_t E,
+                                                      int64_t EF, int64_t step, const double *__restrict__ q12, int K,
+                                                      double *__restrict__ F) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N + 2 * EF) return;
+    const int64_t x = i - EF;
+    double acc = q12[K] * fbuf(in, N, periodic, E, x);
+    for (int k = 1; k <= K; ++k)
+        acc = fma(q12[K + k], fbuf(in, N, periodic, E, x - k * step) + fbuf(in, N, periodic, E, x + k * step), acc);
+    F[x + E] = acc;
+}
+
+template <typename OUT>
+static hipError_t v97_taps(const Plan &p, const Plan::V97Step &sp, char *ws, void *out, hipStream_t st) {
+    const int *fx = reinterpret_cast<const int *>(ws + p.ws_fx_off);
+    const double *C = reinterpret_cast<const double *>(ws + p.ws_C_off);
+    const double2 *dt = reinterpret_cast<const double2 *>(p.d_dtab);
+    const dim3 grid((unsigned)(sp.w1 - sp.w0));
+    const size_t lds = (size_t)p.spl_lds_bytes;
+    const SplineWork *work = p.d_spl_work + sp.w0;
+    if (p.cplx_out)
+        hipLaunchKernelGGL((spl_tap_kernel<OUT, true>), grid, dim3(256), lds, st, p.N, p.spl_E, p.d_spl, work, nullptr,
+                           C, dt, fx, reinterpret_cast<OUT *>(out));
+    else
+        hipLaunchKernelGGL((spl_tap_kernel<OUT, false>), grid, dim3(256), lds, st, p.N, p.spl_E, p.d_spl, work,
+                           nullptr, C, dt, fx, reinterpret_cast<OUT *>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_v97(const Plan &p, size_t k, const void *signal, void *out, void *ws, hipStream_t st) {
+    char *w = reinterpret_cast<char *>(ws);
+    const Plan::V97Step &sp = p.v97_steps[k];
+    const int periodic = p.boundary == CWT_PERIODIC;
+    double *fb[2] = {reinterpret_cast<double *>(w + p.ws_fa_off), reinterpret_cast<double *>(w + p.ws_fb_off)};
+    const int64_t E = p.spl_E;
+    const bool fp64 = p.precision == CWT_FP64;
+    if (sp.kind == 0) {
+        const dim3 grid((unsigned)((p.v97_flen + 255) / 256));
+        int *fx = reinterpret_cast<int *>(w + p.ws_fx_off);
+        if (fp64)
+            hipLaunchKernelGGL(v97_f0_kernel<double>, grid, dim3(256), 0, st, reinterpret_cast<const double *>(signal),
+                               p.N, periodic, E, p.v97_flen, fb[sp.dst], fx);
+        else
+            hipLaunchKernelGGL(v97_f0_kernel<float>, grid, dim3(256), 0, st, reinterpret_cast<const float *>(signal),
+                               p.N, periodic, E, p.v97_flen, fb[sp.dst], fx);
+        return hipGetLastError();
+    }
+    if (sp.kind == 1) {
+        const dim3 grid((unsigned)((p.v97_flen + 255) / 256));
+        hipLaunchKernelGGL(v97_h_kernel, grid, dim3(256), 0, st, fb[sp.src], p.N, periodic, E, p.v97_flen,
+                           int64_t(1) << sp.a, fb[sp.dst]);
+        return hipGetLastError();
+    }
+    if (sp.kind == 2) {
+        // the part of F the tap sums of this level read
+        int64_t EF = 16;
+        for (const Plan::V97Step &t : p.v97_steps)
+            if (t.kind == 3 && t.a == sp.a)
+                for (int32_t q = t.w0; q < t.w1; ++q) {
+                    const SplineScaleDev &sc = p.spl[p.spl_work[q].j];
+                    EF = std::max<int64_t>(EF, (int64_t)(sc.nd + 2) * sc.delta + 16);
+                }
+        EF = std::min(EF, E);
+        const dim3 grid((unsigned)((p.N + 2 * EF + 255) / 256));
+        hipLaunchKernelGGL(v97_q12_kernel, grid, dim3(256), 0, st, fb[sp.src], p.N, periodic, E, EF,
+                           int64_t(1) << sp.a, p.d_v97_q12, p.v97_nq12, reinterpret_cast<double *>(w + p.ws_C_off));
+        return hipGetLastError();
+    }
+    return fp64 ? v97_taps<double>(p, sp, w, out, st) : v97_taps<float>(p, sp, w, out, st);
+}
+
+std::string v97_kernel_name(const Plan &p, size_t k) {
+    static const char *nm[4] = {"v97_f0_kernel", "v97_h_kernel", "v97_q12_kernel", "spl_tap_kernel"};
+    const Plan::V97Step &sp = p.v97_steps[k];
+    if (sp.kind == 3)
+        return std::string("spl_tap_kernel<") + (p.precision == CWT_FP64 ? "f64" : "f32") +
+               (p.cplx_out ? ",complex>" : ",real>");
+    return nm[sp.kind];
 }
 
 }  // namespace cwt

@@ -209,6 +209,42 @@ static std::vector<cd> a19_coeffs(const Wavelet &w, double h, int K, double chi)
     return a;
 }
 
+// Work items of the tap-sum launch for scale j (knot spacing delta, ntap
+// taps): tiles of R <= 16 columns (consecutive positions) x I = 16 floor(256 /
+// R) rows (positions delta apart); the S tile holds R (I + ntap) values plus
+// one spare row per 16, and the taps follow it in LDS.
+static void add_tiles(Plan &p, int j, SplineScaleDev &sc, int64_t delta, int ntap) {
+    auto tile_fits = [&](int r) {
+        const int rows_s = 16 * (256 / r) + ntap;
+        return r * (rows_s + rows_s / 16 + 1) + 2 * ntap <= 8192;  // 64 KiB of LDS
+    };
+    int rmax = 16;
+    while (rmax > 1 && !tile_fits(rmax)) rmax /= 2;
+    if (!tile_fits(rmax)) fail(CWT_EUNSUPPORTED, "spline method: wavelet support too long for the tap tile");
+    const int64_t nck = (delta + rmax - 1) / rmax;
+    const int R = (int)((delta + nck - 1) / nck);
+    sc.R = R;
+    sc.I = 16 * (256 / R);
+    {
+        const int64_t rows_s = sc.I + ntap;
+        const int64_t lds = 8 * (int64_t)R * (rows_s + rows_s / 16 + 1) + 16 * (int64_t)ntap;
+        p.spl_lds_bytes = std::max(p.spl_lds_bytes, lds);
+    }
+    const int64_t rows = (p.N + delta - 1) / delta;
+    for (int64_t i0 = 0; i0 < rows; i0 += sc.I)
+        for (int64_t k = 0; k < nck; ++k) {
+            const int64_t r0 = k * R;
+            if (r0 >= delta) break;
+            SplineWork wk;
+            wk.j = j;
+            wk.r0 = (int32_t)r0;
+            wk.R = (int32_t)std::min<int64_t>(R, delta - r0);
+            wk.pad = 0;
+            wk.i0 = i0;
+            p.spl_work.push_back(wk);
+        }
+}
+
 static const int kSplineBlock = 2048;  // elements per block of the running sums and the max|f| reduction (= kSB of the kernels)
 
 void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
@@ -270,37 +306,7 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
             p.spl_ntaps[j] = 2 * nd + 1;
         }
         sc.ntap = ntap;
-        // tile: R <= 16 columns x I = 16 floor(256 / R) rows; the S tile holds
-        // R (I + ntap) values plus one spare row per 16, and the taps follow it
-        auto tile_fits = [&](int r) {
-            const int rows_s = 16 * (256 / r) + ntap;
-            return r * (rows_s + rows_s / 16 + 1) + 2 * ntap <= 8192;  // 64 KiB of LDS
-        };
-        int rmax = 16;
-        while (rmax > 1 && !tile_fits(rmax)) rmax /= 2;
-        if (!tile_fits(rmax)) fail(CWT_EUNSUPPORTED, "spline method: wavelet support too long for the tap tile");
-        const int64_t nck = (delta + rmax - 1) / rmax;
-        const int R = (int)((delta + nck - 1) / nck);
-        sc.R = R;
-        sc.I = 16 * (256 / R);
-        {
-            const int64_t rows_s = sc.I + ntap;
-            const int64_t lds = 8 * (int64_t)R * (rows_s + rows_s / 16 + 1) + 16 * (int64_t)ntap;
-            p.spl_lds_bytes = std::max(p.spl_lds_bytes, lds);
-        }
-        const int64_t rows = (p.N + delta - 1) / delta;
-        for (int64_t i0 = 0; i0 < rows; i0 += sc.I)
-            for (int64_t k = 0; k < nck; ++k) {
-                const int64_t r0 = k * R;
-                if (r0 >= delta) break;
-                SplineWork wk;
-                wk.j = j;
-                wk.r0 = (int32_t)r0;
-                wk.R = (int32_t)std::min<int64_t>(R, delta - r0);
-                wk.pad = 0;
-                wk.i0 = i0;
-                p.spl_work.push_back(wk);
-            }
+        add_tiles(p, j, sc, delta, ntap);
         if (direct) {
             p.spl_delta[j] = 0;
             p.path[j] = PATH_SPLINE_DIRECT;
@@ -347,6 +353,197 @@ void build_spline_plan(Plan &p, const Wavelet &w, TableBuilder &) {
         p.table_bytes += bytes;
         HIPCHK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
     };
+    upload(dtab.data(), dtab.size() * sizeof(cd), &p.d_dtab);
+    upload(p.spl.data(), p.spl.size() * sizeof(SplineScaleDev), reinterpret_cast<void **>(&p.d_spl));
+    p.d_extra.push_back(p.d_spl);
+    upload(p.spl_work.data(), p.spl_work.size() * sizeof(SplineWork), reinterpret_cast<void **>(&p.d_spl_work));
+    p.d_extra.push_back(p.d_spl_work);
+}
+
+}  // namespace cwt
+
+namespace cwt {
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on the Legendre
+// recurrence from the Chebyshev guesses).
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// c_w = 1 / argmax_u |u| |psi^(u)|^2 (Table 2): a 1/256 scan of [-64, 64],
+// then golden-section refinement of the best bracket
+static double wavelet_cw(const Wavelet &w) {
+    auto g = [&](double u) { return std::fabs(u) * w.amp(u) * w.amp(u); };
+    const double step = 1.0 / 256.0;
+    double best = 0.0, ub = 1.0;
+    for (double u = -64.0; u <= 64.0; u += step)
+        if (g(u) > best) {
+            best = g(u);
+            ub = u;
+        }
+    double a = ub - step, b = ub + step;
+    const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+    double c = b - gr * (b - a), d = a + gr * (b - a);
+    for (int it = 0; it < 200 && b - a > 1e-15 * std::fabs(ub); ++it) {
+        if (g(c) > g(d)) b = d;
+        else a = c;
+        c = b - gr * (b - a);
+        d = a + gr * (b - a);
+    }
+    return 1.0 / std::fabs(0.5 * (a + b));
+}
+
+// q12: the inverse filter of the sampled quartic B-spline (1, 76, 230, 76, 1)
+// / 384 (Eq. q_12), taps |k| <= K, by the trapezoid rule on the unit circle
+// (its images lie 4096 taps apart, where the taps are below 1e-1800)
+static std::vector<double> q12_taps(int K) {
+    const int M = 4096;
+    std::vector<double> q(2 * (size_t)K + 1, 0.0);
+    for (int k = -K; k <= K; ++k) {
+        double acc = 0.0;
+        for (int m = 0; m < M; ++m) {
+            const double om = 2.0 * M_PI * m / M;
+            const double b4 = (230.0 + 152.0 * std::cos(om) + 2.0 * std::cos(2.0 * om)) / 384.0;
+            acc += std::cos(om * k) / b4;
+        }
+        q[(size_t)(k + K)] = acc / M;
+    }
+    return q;
+}
+
+// V97 method (Sec. 3.2).  Scale s = 2^i r / w~_max, 1 <= r < 2: taps
+// conj(q_r(k)) / s at spacing 2^i on F_i = f * beta3 * h * [h]2 * ... *
+// [h]2^(i-1) * [q12]2^i, q_r(k) = int_{k-1/2}^{k+1/2} psi(w~_max y / r) dy.
+void build_v97_plan(Plan &p, const Wavelet &w) {
+    const double chi17 = spline_chi(w, 1e-17);
+    p.v97_wmax = 1.34 * wavelet_cw(w);  // Table 3: w~_max = 1.34 c_w
+    p.hstar = p.v97_wmax;
+    p.path.assign(p.S, PATH_SPLINE_DIRECT);
+    p.spl.resize(p.S);
+    p.spl_delta.resize(p.S);
+    p.spl_ntaps.assign(p.S, 0);
+    p.spl_work.clear();
+    p.spl_lds_bytes = 0;
+    p.spl_direct = true;
+    p.v97_nq12 = 40;  // (2 - sqrt 3)-like decay: |q12[k]| < 0.362^k, below 1e-17 past 40
+    std::vector<double> gx, gw;
+    gauss_legendre(16, gx, gw);
+    std::vector<double> g4x, g4w;
+    gauss_legendre(4, g4x, g4w);
+    std::vector<cd> dtab;
+    std::map<int, std::vector<int>> level_scales;
+    std::map<int, int64_t> level_ef;
+    for (int j = 0; j < p.S; ++j) {
+        const double s = p.scales[j];
+        const double t = s * p.v97_wmax;
+        if (!(t >= 1.0 - 1e-12))
+            fail(CWT_EUNSUPPORTED, "V97 method: scales below 1 / w~_max = " + std::to_string(1.0 / p.v97_wmax) +
+                                       " samples are not supported");
+        int i = std::max(0, (int)std::floor(std::log2(std::max(t, 1.0))));
+        while (i > 0 && std::ldexp(1.0, i) > t) --i;
+        while (std::ldexp(1.0, i + 1) <= t) ++i;
+        if (i > 30) fail(CWT_EUNSUPPORTED, "V97 method: scale too large");
+        const double r = t / std::ldexp(1.0, i);
+        const int64_t delta = int64_t(1) << i;
+        const int nq = (int)std::ceil(chi17 * r / p.v97_wmax + 0.5);
+        // cell integrals of psi(w~_max y / r); the cubic B-spline wavelet is
+        // cut at its knots y = r m / w~_max so that each piece is a cubic
+        std::vector<cd> q(2 * (size_t)nq + 1);
+        for (int k = -nq; k <= nq; ++k) {
+            std::vector<double> cut = {k - 0.5, k + 0.5};
+            if (w.kind == CWT_CBSW)
+                for (int m = -3; m <= 3; ++m) {
+                    const double y = r * m / p.v97_wmax;
+                    if (y > k - 0.5 && y < k + 0.5) cut.push_back(y);
+                }
+            std::sort(cut.begin(), cut.end());
+            const std::vector<double> &nx = w.kind == CWT_CBSW ? g4x : gx;
+            const std::vector<double> &nw = w.kind == CWT_CBSW ? g4w : gw;
+            cd acc = 0.0;
+            for (size_t c = 0; c + 1 < cut.size(); ++c) {
+                const double mid = 0.5 * (cut[c] + cut[c + 1]), hw = 0.5 * (cut[c + 1] - cut[c]);
+                for (size_t g = 0; g < nx.size(); ++g)
+                    acc += hw * nw[g] * w.psi_time(p.v97_wmax * (mid + hw * nx[g]) / r);
+            }
+            q[(size_t)(k + nq)] = acc;
+        }
+        SplineScaleDev &sc = p.spl[j];
+        const int ntap = (2 * nq + 1 + 7) / 8 * 8;
+        sc.delta = (int32_t)delta;
+        sc.nd = nq;
+        sc.ntap = ntap;
+        sc.mode = 1;
+        sc.d_off = (int64_t)dtab.size();
+        for (int n = 0; n < ntap; ++n) dtab.push_back(n <= 2 * nq ? std::conj(q[(size_t)n]) / s : cd(0.0));
+        p.spl_ntaps[j] = 2 * nq + 1;
+        p.spl_delta[j] = (int32_t)delta;
+        level_scales[i].push_back(j);
+        level_ef[i] = std::max<int64_t>(level_ef[i], (int64_t)(nq + 2) * delta + 16);
+    }
+    // arrays: F on [-EF, N + EF) inside [-E, N + E); f buffers on [-E, N + E)
+    // (zero boundary: f_i vanishes beyond 2^(i+1) + 1 samples of the signal)
+    // or [0, N) with wrapped reads (periodic)
+    int64_t E = 16;
+    for (auto &kv : level_ef)
+        E = std::max<int64_t>(E, kv.second + (int64_t)(p.v97_nq12 + 2) * (int64_t(1) << kv.first) + 16);
+    if (p.N + 2 * E > (int64_t(1) << 31)) fail(CWT_EUNSUPPORTED, "V97 method: signal plus filter support above 2^31");
+    p.spl_E = E;
+    p.spl_len = p.N + 2 * E;
+    p.v97_flen = p.boundary == CWT_PERIODIC ? p.N : p.spl_len;
+    // launch sequence: f_0, then per level: advance f, F_i, tap sums
+    p.v97_steps.clear();
+    p.v97_steps.push_back({0, 0, -1, 0, 0, 0});
+    int cur = 0, buf = 0;
+    for (auto &kv : level_scales) {
+        const int i = kv.first;
+        while (cur < i) {
+            p.v97_steps.push_back({1, cur, buf, 1 - buf, 0, 0});
+            buf = 1 - buf;
+            ++cur;
+        }
+        p.v97_steps.push_back({2, i, buf, -1, 0, 0});
+        const int32_t w0 = (int32_t)p.spl_work.size();
+        for (int j : kv.second) add_tiles(p, j, p.spl[j], p.spl[j].delta, p.spl[j].ntap);
+        p.v97_steps.push_back({3, i, -1, -1, w0, (int32_t)p.spl_work.size()});
+    }
+    size_t ws = 0;
+    auto take = [&](size_t bytes) {
+        size_t off = (ws + 255) & ~size_t(255);
+        ws = off + bytes;
+        return off;
+    };
+    p.ws_fx_off = take(16);
+    p.ws_fa_off = take((size_t)p.v97_flen * 8);
+    p.ws_fb_off = take((size_t)p.v97_flen * 8);
+    p.ws_C_off = take((size_t)p.spl_len * 8);
+    p.ws_bytes = ws;
+    if (p.host_only) return;
+    auto upload = [&](const void *src, size_t bytes, void **dst) {
+        HIPCHK(hipMalloc(dst, bytes));
+        p.table_bytes += bytes;
+        HIPCHK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    };
+    const std::vector<double> q12 = q12_taps(p.v97_nq12);
+    upload(q12.data(), q12.size() * sizeof(double), reinterpret_cast<void **>(&p.d_v97_q12));
+    p.d_extra.push_back(p.d_v97_q12);
     upload(dtab.data(), dtab.size() * sizeof(cd), &p.d_dtab);
     upload(p.spl.data(), p.spl.size() * sizeof(SplineScaleDev), reinterpret_cast<void **>(&p.d_spl));
     p.d_extra.push_back(p.d_spl);

@@ -78,3 +78,18 @@ def test_a19_step_matches_oracle(wav, par):
     assert abs(p.spline_hstar() - ref) <= 1e-12 * ref
     assert p.spline_delta().tolist() == [oracle.spline_delta(ref, s) for s in (0.5, 3.0, 40.0, 900.0)]
     assert "method=a19" in p.describe()
+
+
+@pytest.mark.parametrize("wav,par", [("mexhat", None), ("morlet", 6.0), ("cbsw", None), ("gdw", None), ("mw", None)])
+def test_v97_plan_levels(wav, par):
+    # V97 (Sec. 3.2): w~_max = 1.34 c_w (the plan's h* query reports it);
+    # scale s = 2^i r / w~_max runs at knot spacing 2^i
+    wmax = oracle.v97_wmax(wav, par)
+    scales = [1.0001 / wmax, 1.5 / wmax, 3.0 / wmax, 1000.0]
+    p = cwt.Plan(4096, "zero", wav, scales, param=par, method="v97", host_only=True)
+    assert abs(p.spline_hstar() - wmax) < 1e-7 * wmax
+    assert p.spline_delta().tolist() == [2 ** oracle.v97_level(s, wmax)[0] for s in scales]
+    assert "method=v97" in p.describe()
+    with pytest.raises(cwt.CwtError) as e:
+        cwt.Plan(4096, "zero", wav, [0.9 / wmax], param=par, method="v97", host_only=True)
+    assert e.value.code == cwt.CWT_EUNSUPPORTED
