@@ -677,7 +677,7 @@ def q12_filter(K: int = 60) -> np.ndarray:
 def v97_level(s: float, wmax: float):
     """Octave level i and sub-level factor r in [1, 2) of s = 2^i r / w~_max."""
     t = s * wmax
-    if t < 1.0 - 1e-12:
+    if t < 1.0 - 1e-6:
         raise ValueError("V97 scales start at 1 / w~_max")
     i = max(0, int(np.floor(np.log2(max(t, 1.0)))))
     while i > 0 and 2.0 ** i > t:

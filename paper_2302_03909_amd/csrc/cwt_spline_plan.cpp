@@ -454,7 +454,7 @@ void build_v97_plan(Plan &p, const Wavelet &w) {
     for (int j = 0; j < p.S; ++j) {
         const double s = p.scales[j];
         const double t = s * p.v97_wmax;
-        if (!(t >= 1.0 - 1e-12))
+        if (!(t >= 1.0 - 1e-6))
             fail(CWT_EUNSUPPORTED, "V97 method: scales below 1 / w~_max = " + std::to_string(1.0 / p.v97_wmax) +
                                        " samples are not supported");
         int i = std::max(0, (int)std::floor(std::log2(std::max(t, 1.0))));
