@@ -295,6 +295,41 @@ int cwt_exec_scratch(cwt_plan_t plan, const void *signal, void *out, void *strea
 size_t cwt_scratch_bytes(void);
 
 /*
+ * cwt_exec_wps -- wavelet power spectra of the signal instead of its
+ * coefficients (Sec. 5): per scale, the environment-dependent power spectrum
+ * (Eq. env_wps) -- the mean of |W(s, x)|^2 over the positions x whose
+ * environment value env[x] falls in a bin -- and the global one (Eq.
+ * global_wps), the mean over all N positions.  The bins split the real line
+ * at nthr thresholds: position x is in bin k = #{i : env[x] >= thresholds[i]}
+ * (k = 0 .. nthr), so every position is in exactly one bin and
+ * global = sum_k (N_k / N) env_k (Eq. global_wps_env_wps); a NaN env value
+ * falls in bin 0.  The paper's split into underdense and overdense
+ * positions is nthr = 1, thresholds = {0}, env = the density contrast.
+ * W is the transform cwt_exec computes; its squares are added up inside the
+ * output kernels (FP64 sums of FP32 or FP64 values, in a fixed order), so
+ * the S x N coefficients are never written.
+ *   signal:     device, N values of the plan's precision.
+ *   env:        device, N values of the plan's precision, or NULL for the
+ *               signal itself.
+ *   thresholds: host, nthr strictly ascending finite values, 0 <= nthr <= 3.
+ *   wps:        device, [S][nthr + 2] doubles: columns 0..nthr the
+ *               environment-dependent spectra of bins 0..nthr (NaN for an
+ *               empty bin), column nthr + 1 the global spectrum.
+ *   counts:     device, nthr + 1 int64 bin sizes N_k, or NULL.
+ *   workspace:  device, cwt_wps_workspace_bytes(plan) bytes, 256-byte aligned
+ *               (the plan's workspace plus per-workgroup partial sums).
+ * Supported for segmented FFT plans (method CWT_METHOD_FFT, fft_mode
+ * CWT_FFT_SEGMENTED, psi_mode CWT_PSI_ALIASED: the defaults) and otherwise
+ * CWT_EUNSUPPORTED; cwt_wps_workspace_bytes returns 0 for the others.
+ * Errors: CWT_EINVAL for NULL plan/signal/wps/workspace, bad thresholds or
+ * misaligned pointers; CWT_EDEVICE when a launch fails.  Streams, events and
+ * graph capture as for cwt_exec; the result does not depend on scheduling.
+ */
+size_t cwt_wps_workspace_bytes(cwt_plan_t plan);
+int cwt_exec_wps(cwt_plan_t plan, const void *signal, const void *env, const double *thresholds, int32_t nthr,
+                 double *wps, int64_t *counts, void *workspace, void *stream);
+
+/*
  * cwt_exec_batch -- transform n independent signals, each with its own plan
  * (lengths, scales, wavelets, boundaries and precisions may differ), in one
  * enqueue on `stream`.  signals[i], outs[i] as for cwt_exec with plans[i].

@@ -36,6 +36,9 @@ Contents
   (Eq. q_12), ``v97_q`` (Eq. qj), ``v97_kernel`` (the approximated wavelet of
   Eqs. beta3_wavelet_approx and pj), ``v97_points`` (the unit-step sum with
   it) and ``ae_v`` (Eq. v97cwt_error).
+* Wavelet power spectra (Sec. 5): ``wps_bins``, ``wps`` (Eqs. env_wps and
+  global_wps: means of |W|^2 per environment bin and over all positions)
+  and ``cwt_wps``.
 
 Readings of the paper that this oracle takes (each is repeated in the
 design notes): scales and positions are in samples; the canonical result is
@@ -770,3 +773,45 @@ def ae_v(wavelet: str, param: float | None, w: float, npts: int = 20001) -> floa
         approx += p[kk + kp] * beta3(x - kk)
     ex = psi(wavelet, param, w * x)
     return float(np.sum(np.abs(ex - approx)) / np.sum(np.abs(ex)))
+
+
+# ---------------------------------------------------------------------------
+# Wavelet power spectra (Sec. 5)
+
+def wps_bins(env, thresholds) -> np.ndarray:
+    """Environment bin of every position: the number of thresholds t with
+    env >= t (a NaN value compares false everywhere: bin 0)."""
+    env = np.asarray(env, dtype=np.float64)
+    k = np.zeros(env.shape, dtype=np.int64)
+    for t in thresholds:
+        k += env >= t
+    return k
+
+
+def wps(W, env, thresholds):
+    """Wavelet power spectra of the coefficients W [S, N] (Sec. 5):
+    column b < nb of the [S, nb + 1] result is the environment-dependent
+    spectrum (Eq. env_wps), the mean of |W|^2 over the positions of bin b
+    (NaN when the bin is empty); the last column is the global spectrum
+    (Eq. global_wps), the mean over all positions.  Also returns the bin
+    sizes N_b."""
+    p2 = np.abs(np.asarray(W)) ** 2
+    k = wps_bins(env, thresholds)
+    nb = len(thresholds) + 1
+    out = np.empty((p2.shape[0], nb + 1))
+    counts = np.array([np.count_nonzero(k == b) for b in range(nb)], dtype=np.int64)
+    for b in range(nb):
+        out[:, b] = p2[:, k == b].mean(axis=1) if counts[b] else np.nan
+    out[:, nb] = p2.mean(axis=1)
+    return out, counts
+
+
+def cwt_wps(f, boundary: str, wavelet: str, scales, env=None, thresholds=(0.0,),
+            param: float | None = None, spectral: bool = False):
+    """``wps`` of the canonical transform of f (the direct sum ``cwt``, or
+    ``cwt_spectral_rows`` when spectral); env defaults to f itself."""
+    if spectral:
+        W = np.array([w for _, w in cwt_spectral_rows(f, boundary, wavelet, scales, param)])
+    else:
+        W = cwt(f, boundary, wavelet, scales, param)
+    return wps(W, f if env is None else env, thresholds)

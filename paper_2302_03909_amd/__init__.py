@@ -49,7 +49,7 @@ EXPORTS = ["cwt_plan", "cwt_destroy", "cwt_out_is_complex", "cwt_out_elems", "cw
            "cwt_workspace_bytes", "cwt_footprint_bytes", "cwt_exec", "cwt_batch_workspace_bytes",
            "cwt_exec_batch", "cwt_plan_fft_len", "cwt_plan_spline_delta", "cwt_plan_spline_taps", "cwt_plan_spline_hstar",
            "cwt_plan_scale_path", "cwt_plan_describe", "cwt_plan_timing_enable", "cwt_plan_timing_read", "cwt_last_error",
-           "cwt_exec_scratch", "cwt_scratch_bytes"]
+           "cwt_exec_scratch", "cwt_scratch_bytes", "cwt_wps_workspace_bytes", "cwt_exec_wps"]
 
 _lib = None
 
@@ -95,6 +95,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cwt_exec_scratch.argtypes = [vp, vp, vp, vp]
     lib.cwt_scratch_bytes.argtypes = []
     lib.cwt_scratch_bytes.restype = ctypes.c_size_t
+    lib.cwt_wps_workspace_bytes.argtypes = [vp]
+    lib.cwt_wps_workspace_bytes.restype = ctypes.c_size_t
+    lib.cwt_exec_wps.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -260,6 +263,41 @@ class Plan:
                                ctypes.c_void_p(workspace.data_ptr() if workspace is not None else 0),
                                ctypes.c_void_p(st.cuda_stream)))
         return out
+
+
+def wps_workspace_bytes(plan: Plan) -> int:
+    return int(load().cwt_wps_workspace_bytes(plan.handle))
+
+
+def exec_wps(plan: Plan, signal, env=None, thresholds=(0.0,), workspace=None, stream=None, with_counts=True):
+    """``cwt_exec_wps``: wavelet power spectra (Sec. 5) of a device signal.
+    Returns (wps, counts): wps a float64 [S, len(thresholds) + 2] tensor
+    (environment-dependent spectra of the len(thresholds) + 1 bins, then the
+    global one), counts the int64 bin sizes (None unless with_counts).
+    env: device tensor of n values (the signal's dtype) or None (the signal)."""
+    import torch
+    sdt, _ = plan._dtypes()
+    if signal.dtype != sdt or signal.device.type != "cuda" or signal.numel() != plan.n:
+        raise ValueError(f"signal must be a cuda {sdt} tensor of {plan.n} values")
+    signal = signal.contiguous()
+    if env is not None:
+        if env.dtype != sdt or env.device != signal.device or env.numel() != plan.n:
+            raise ValueError(f"env must be a {sdt} tensor of {plan.n} values on the signal's device")
+        env = env.contiguous()
+    thr = (ctypes.c_double * max(1, len(thresholds)))(*[float(t) for t in thresholds])
+    nb = len(thresholds) + 1
+    wps = torch.empty((plan.num_scales, nb + 1), dtype=torch.float64, device=signal.device)
+    counts = torch.empty(nb, dtype=torch.int64, device=signal.device) if with_counts else None
+    if workspace is None:
+        wb = wps_workspace_bytes(plan)
+        workspace = torch.empty(max(wb, 1), dtype=torch.uint8, device=signal.device)
+    st = stream if stream is not None else torch.cuda.current_stream(signal.device)
+    _check(load().cwt_exec_wps(plan.handle, ctypes.c_void_p(signal.data_ptr()),
+                               ctypes.c_void_p(env.data_ptr() if env is not None else 0), thr, len(thresholds),
+                               ctypes.c_void_p(wps.data_ptr()),
+                               ctypes.c_void_p(counts.data_ptr() if counts is not None else 0),
+                               ctypes.c_void_p(workspace.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
+    return wps, counts
 
 
 def exec_scratch(plan: Plan, signal, out=None, stream=None):

@@ -71,7 +71,7 @@ struct SegGroupDev {
     int32_t lgL, B, nchunk, iters;
     int32_t unit0, nunits;
     int32_t colpair, cshift;
-    int32_t colodd, pad;
+    int32_t colodd, inv0;   // inv0: index of the group's first inverse work item
     int64_t V, Tg, klo, nseg;
     int64_t xp_off, x_off;  // workspace byte offsets of the partial and reduced band spectra
     int64_t gtw_off;        // byte offset of the column factors in the twiddle allocation
@@ -126,6 +126,7 @@ struct KeyDesc {
     int64_t Tg, V, nseg;   // LOCAL group
     int32_t nscale, pad;
     const int32_t *scale_ids;
+    const int64_t *wps_base;  // statistics epilogue: first slot of each scale (plan-wide table)
 };
 
 // caller buffers of one transform
@@ -133,6 +134,21 @@ struct BatchInst {
     const void *f;
     void *out;
     char *ws;
+    const void *env;  // statistics epilogue: environment values (plan precision)
+    double *part;     // statistics epilogue: per-slot partial sums
+};
+
+// Statistics epilogue (Sec. 5, Eqs. env_wps and global_wps): instead of the
+// coefficients, the two output kernels add up |W|^2 per scale and
+// environment bin.  Bin of position x: the number of thresholds thr[k]
+// (k < nbin - 1, ascending) with env[x] >= thr[k]; every position falls in
+// one bin.  Each workgroup writes its sums to its own slot:
+// part[(wps_base[scale] + slot) * nbin + bin], slot = the workgroup's index
+// within the scale's group (local block, or inverse work item - inv0).
+constexpr int kWpsMaxBins = 4;
+struct WpsArgs {
+    double thr[kWpsMaxBins - 1];
+    int32_t nbin, pad;
 };
 
 // blocks [block0, next range's block0) of a merged launch run key `key` on
@@ -155,6 +171,7 @@ struct BatchArgs {
     int32_t nranges, pad;
     KeyDesc k0;
     BatchInst i0;
+    WpsArgs wps;  // read by the statistics variants only
 };
 
 // Plan-time evaluation of sampled wavelet spectra on the device
@@ -250,6 +267,10 @@ struct Plan {
     int32_t fft_mode = 0;  // 0 segmented, 1 whole signal
     int64_t w23_hi_off = -1, w23_lo_off = -1;  // FP64 w_{2^23} tables, bytes
     bool pair_real = false;
+    // statistics epilogue slots (segmented plans): scale j owns slots
+    // [wps_base[j], wps_base[j + 1]), one per workgroup of its group
+    std::vector<int64_t> wps_base;
+    int64_t *d_wps_base = nullptr;
 
     // spline method
     double hstar = 0.0;
@@ -329,7 +350,15 @@ struct SegKernelId {
     }
 };
 hipError_t launch_seg_kernel(const SegKernelId &id, const BatchArgs &a, int64_t blocks, hipStream_t st);
-std::string seg_kernel_id_name(const SegKernelId &id);
+// the statistics variants of kinds 0 and 3 (cwt_wps.hip); kinds 1 and 2 as above
+hipError_t launch_seg_kernel_wps(const SegKernelId &id, const BatchArgs &a, int64_t blocks, hipStream_t st);
+std::string seg_kernel_id_name(const SegKernelId &id, bool wps = false);
+// statistics epilogue: bin counts of env (partials per workgroup, kWpsCountBlocks
+// workgroups) and the final division (one workgroup per scale)
+constexpr int kWpsCountBlocks = 512;
+hipError_t launch_wps_count(const void *env, int64_t N, bool fp64, const WpsArgs &w, uint64_t *cpart, hipStream_t st);
+hipError_t launch_wps_finalize(const double *part, const int64_t *base, int S, const WpsArgs &w,
+                               const uint64_t *cpart, int64_t N, double *wps, int64_t *counts, hipStream_t st);
 bool local2_size_ok(int L, int precision);
 bool seg_size_ok(int P, int precision);
 int local2_segs_per_block(int L, bool pair, bool fp64);

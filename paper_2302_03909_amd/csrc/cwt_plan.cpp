@@ -820,6 +820,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         gd.colpair = g.colpair;
         gd.cshift = g.cshift;
         gd.colodd = g.colodd;
+        gd.inv0 = (int32_t)sl->inv.size();
         gd.V = g.V;
         gd.Tg = g.Tg;
         gd.klo = g.klo;
@@ -849,6 +850,33 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     }
     p.ws_bytes = ws;
     p.tab_elems = tab_n;
+    // statistics epilogue slots: one per workgroup that writes outputs of
+    // the scale (local blocks; inverse work items of a band group)
+    {
+        std::vector<int64_t> nslot(p.S, -1);
+        auto own = [&](int32_t j, int64_t n) {
+            if (j < 0 || j >= p.S || nslot[j] >= 0) fail(CWT_EINVAL, "internal: scale in two segment groups");
+            nslot[j] = n;
+        };
+        for (auto &g : p.segs) {
+            if (g.kind == SegGroup::LOCAL) {
+                const int64_t per = local2_segs_per_block(g.L, p.pair_real, fp64);
+                for (int32_t j : g.scales) own(j, (g.nseg + per - 1) / per);
+            } else {
+                const int64_t Q = (int64_t)g.L / g.P, cols = g.colpair ? 32 : 16;
+                const int64_t n = g.nseg * ((Q + cols - 1) / cols);
+                for (int32_t u = g.unit0; u < g.unit0 + g.nunits; ++u) {
+                    own(p.units[u].sa, n);
+                    if (p.units[u].sb >= 0) own(p.units[u].sb, n);
+                }
+            }
+        }
+        p.wps_base.assign(p.S + 1, 0);
+        for (int32_t j = 0; j < p.S; ++j) {
+            if (nslot[j] < 0) fail(CWT_EINVAL, "internal: scale in no segment group");
+            p.wps_base[j + 1] = p.wps_base[j] + nslot[j];
+        }
+    }
     if (p.host_only) return;
 
     // One device allocation holds every table of the plan:
@@ -884,6 +912,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     for (auto &g : p.segs) nkeys += g.kind == SegGroup::LOCAL ? 1 : 0;
     nkeys += 3 * p.seg_launches.size();
     const size_t o_keys = take(nkeys * sizeof(KeyDesc));
+    const size_t o_wps = take(p.wps_base.size() * sizeof(int64_t));
     const size_t total = off;
 
     hipStream_t pst = plan_stream();
@@ -906,6 +935,8 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     }
     put(o_units, p.units.data(), p.units.size() * sizeof(SegUnit));
     p.d_units = reinterpret_cast<SegUnit *>(base + o_units);
+    put(o_wps, p.wps_base.data(), p.wps_base.size() * sizeof(int64_t));
+    p.d_wps_base = reinterpret_cast<int64_t *>(base + o_wps);
     for (size_t li = 0; li < p.seg_launches.size(); ++li) {
         SegLaunch &l = p.seg_launches[li];
         put(o_l[li].groups, l.gdev.data(), l.gdev.size() * sizeof(SegGroupDev));
@@ -930,6 +961,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     kb.twbase = tw;
     kb.whi = reinterpret_cast<const double2 *>(tw + p.w23_hi_off);
     kb.wlo = reinterpret_cast<const double2 *>(tw + p.w23_lo_off);
+    kb.wps_base = p.d_wps_base;
     p.keys.clear();
     for (auto &g : p.segs) {
         if (g.kind != SegGroup::LOCAL) continue;
@@ -1739,5 +1771,111 @@ int cwt_plan_scale_path(cwt_plan_t plan, int32_t *path) {
 }
 
 const char *cwt_last_error(void) { return cwt::g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// statistics epilogue (Sec. 5): environment-dependent and global wavelet
+// power spectra of a segmented FFT plan, reduced in the output kernels
+
+namespace cwt {
+
+static bool wps_plan_ok(const Plan &p) {
+    return p.method == CWT_METHOD_FFT && p.fft_mode == CWT_FFT_SEGMENTED && !p.segs.empty() && p.psi_mode == CWT_PSI_ALIASED;
+}
+static size_t wps_part_bytes(const Plan &p) {
+    return align256((size_t)(p.wps_base.empty() ? 0 : p.wps_base.back()) * kWpsMaxBins * sizeof(double));
+}
+static size_t wps_ws_bytes(const Plan &p) {
+    return align256(p.ws_bytes) + wps_part_bytes(p) + align256((size_t)kWpsCountBlocks * kWpsMaxBins * sizeof(uint64_t));
+}
+
+static int exec_wps_impl(cwt_plan_t plan, const void *signal, const void *env, const double *thr, int32_t nthr,
+                         double *wps, int64_t *counts, void *workspace, void *stream) {
+    if (!plan) fail(CWT_EINVAL, "plan is NULL");
+    Plan &p = *plan->p;
+    if (!wps_plan_ok(p))
+        fail(CWT_EUNSUPPORTED, "power spectra need a segmented FFT plan with the aliased spectrum (the default)");
+    if (p.host_only) fail(CWT_EINVAL, "plan was built host-only");
+    if (!signal || !wps) fail(CWT_EINVAL, "signal/wps is NULL");
+    if (!workspace) fail(CWT_EINVAL, "workspace is NULL");
+    if (nthr < 0 || nthr > kWpsMaxBins - 1)
+        fail(CWT_EINVAL, "between 0 and " + std::to_string(kWpsMaxBins - 1) + " thresholds");
+    if (nthr > 0 && !thr) fail(CWT_EINVAL, "thresholds is NULL");
+    for (int32_t k = 0; k < nthr; ++k) {
+        if (!std::isfinite(thr[k])) fail(CWT_EINVAL, "thresholds must be finite");
+        if (k > 0 && !(thr[k] > thr[k - 1])) fail(CWT_EINVAL, "thresholds must be strictly ascending");
+    }
+    if (!env) env = signal;
+    const size_t ealign = p.precision == CWT_FP64 ? 8 : 4;
+    if ((uintptr_t)signal % ealign || (uintptr_t)env % ealign || (uintptr_t)wps % 8 || (uintptr_t)counts % 8)
+        fail(CWT_EINVAL, "signal/env/wps/counts not aligned to their element size");
+    if ((uintptr_t)workspace % 256) fail(CWT_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    double *part = reinterpret_cast<double *>(ws + align256(p.ws_bytes));
+    uint64_t *cpart = reinterpret_cast<uint64_t *>(ws + align256(p.ws_bytes) + wps_part_bytes(p));
+    BatchArgs a{};
+    a.i0 = {signal, nullptr, ws, env, part};
+    a.wps.nbin = nthr + 1;
+    for (int32_t k = 0; k < nthr; ++k) a.wps.thr[k] = thr[k];
+    const bool fp64 = p.precision == CWT_FP64;
+    const double nn = (double)p.N, sb = fp64 ? 8.0 : 4.0;
+    auto run = [&](hipStream_t ks, const std::string &name, double bytes, const char *what, auto &&launch) {
+        if (p.timing) {
+            timed(p, ks, name, bytes, what, launch);
+            return;
+        }
+        const hipError_t e = launch();
+        if (e != hipSuccess) fail(CWT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    run(st, "wps_count_kernel", nn * sb, "power spectrum count launch",
+        [&] { return launch_wps_count(env, p.N, fp64, a.wps, cpart, st); });
+    bool has_local = false, has_band = false;
+    for_each_seg_launch(p, [&](const SegKernelId &id, int32_t, int64_t, double) {
+        (id.kind == 0 ? has_local : has_band) = true;
+    });
+    static const char *what[4] = {"local launch", "segment spectra launch", "segment reduce launch",
+                                  "segment inverse launch"};
+    SegStreams ss(st, has_local && has_band && !p.timing && !p.single_stream);
+    for_each_seg_launch(p, [&](const SegKernelId &id, int32_t key, int64_t blocks, double bytes) {
+        a.k0 = p.keys[key];
+        hipStream_t ks = ss.of(id.kind);
+        // the output kernels read the signal (or band spectra) and env, and
+        // write one slot of sums per scale and workgroup
+        double b = bytes;
+        if (id.kind == 0) b = 2.0 * nn * sb;
+        for (auto &l : p.seg_launches)
+            if (id.kind == 3 && l.key[2] == key) {
+                b = nn * sb;
+                for (auto &gd : l.gdev) b += (double)gd.nseg * gd.B * 16.0;
+            }
+        run(ks, seg_kernel_id_name(id, id.kind == 0 || id.kind == 3), b, what[id.kind],
+            [&] { return launch_seg_kernel_wps(id, a, blocks, ks); });
+    });
+    ss.end();
+    run(st, "wps_finalize_kernel", (double)p.wps_base.back() * a.wps.nbin * 8.0, "power spectrum finalize launch",
+        [&] {
+            return launch_wps_finalize(part, p.d_wps_base, p.S, a.wps, cpart, p.N, wps, counts, st);
+        });
+    note_use(p, st);
+    return CWT_OK;
+}
+
+}  // namespace cwt
+
+extern "C" {
+
+size_t cwt_wps_workspace_bytes(cwt_plan_t plan) {
+    if (!plan || !cwt::wps_plan_ok(*plan->p)) return 0;
+    return cwt::wps_ws_bytes(*plan->p);
+}
+
+int cwt_exec_wps(cwt_plan_t plan, const void *signal, const void *env, const double *thresholds, int32_t nthr,
+                 double *wps, int64_t *counts, void *workspace, void *stream) {
+    return guarded([&]() -> int {
+        return cwt::exec_wps_impl(plan, signal, env, thresholds, nthr, wps, counts, workspace, stream);
+    });
+}
 
 }  // extern "C"

@@ -124,6 +124,27 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
     }
 }
 
+// The (column, position) pairs cols_pass_last hands this thread, in the order
+// of its emit calls: fn(k, col, p) for emit k = 0, 1, ...
+template <int P, int NCOL, int NT, bool POSFAST, class F>
+__device__ __forceinline__ void cols_last_positions(F &&fn) {
+    constexpr int PASS = num_passes(P) - 1;
+    constexpr int R = radix_of(P, PASS);
+    constexpr int NS = ns_before(P, PASS);
+    constexpr int NB = NCOL * (P / R);
+    constexpr int PER = (NB + NT - 1) / NT;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int gb = tid + q * NT;
+        if (NB % NT == 0 || gb < NB) {
+            int c = POSFAST ? gb / (P / R) : gb % NCOL, i = POSFAST ? gb % (P / R) : gb / NCOL;
+#pragma unroll
+            for (int r = 0; r < R; ++r) fn(q * R + r, c, i + r * NS);
+        }
+    }
+}
+
 template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int PASS, bool TWCALC = false>
 __device__ __forceinline__ void cols_mid_from(C *buf, const C *twl) {
     if constexpr (PASS + 1 < num_passes(P)) {

@@ -20,6 +20,12 @@ Workloads (all seeded with numpy's PCG64):
 * ``paper_f1`` / ``paper_f2`` / ``paper_scale_grid`` -- the test signals of
   Sec. 4 (Eqs. signal_f1, signal_f2) and the level/sub-level scale grid of
   Sec. 3.1, for the paper's accuracy comparison.
+* ``zeldovich_field`` -- the 1D Zel'dovich density field of Sec. 5 (Eq.
+  nonlinear_dens), delta + 1 = 1 / (1 - theta delta_0), delta_0 a periodic
+  Gaussian field with P(k) = A k^-2, A = 2.5e-6, on a box of length
+  ``box`` (k = 2 pi n / box).  The paper takes the box length and grid from
+  another work; here the box is a parameter, 48 by default, which keeps
+  theta = 100 before the first orbit crossing (max theta delta_0 < 1).
 * ``batch_specs`` / ``request_stream`` -- many uneven instances and a
   Poisson request stream for the batched and served forms.
 """
@@ -35,6 +41,7 @@ SEED_FIELD_1M = 20230210
 SEED_FIELD_4M = 20230211
 SEED_BATCH = 20230212
 SEED_SERVE = 20230213
+SEED_ZELDOVICH = 20230214
 
 
 def tones_noise(n: int, seed: int = SEED_SMALL, noise: float = 0.1) -> np.ndarray:
@@ -71,6 +78,34 @@ def lognormal_field(n: int, seed: int = SEED_FIELD_1M, sigma_g: float = 1.0,
     g = np.fft.irfft(modes, n=box)[:n]
     g = (g - g.mean()) / g.std() * sigma_g
     return np.exp(g - 0.5 * sigma_g ** 2) - 1.0
+
+
+def zeldovich_field(n: int, theta: float = 100.0, seed: int = SEED_ZELDOVICH, amp: float = 2.5e-6,
+                    box: float = 48.0, return_initial: bool = False):
+    """Density contrast delta(x, theta) of the 1D Zel'dovich approximation on
+    n periodic grid points (Sec. 5, Eq. nonlinear_dens):
+    delta + 1 = 1 / (1 - theta delta_0(x)), with delta_0 the linear field at
+    theta = 1, a Gaussian random field of power spectrum P(k) = amp k^-2.
+
+    delta_0(x_j) = sum_{m=1}^{n/2-1} 2 Re(a_m e^{i k_m x_j}), x_j = j box / n,
+    k_m = 2 pi m / box, a_m complex Gaussian with <|a_m|^2> = P(k_m) / box
+    (so <delta_0^2> = sum_m 2 P(k_m) / box).  Raises ValueError when
+    theta delta_0 reaches 1 somewhere (past the first orbit crossing).
+    return_initial: also return delta_0."""
+    rng = np.random.default_rng(seed)
+    m = np.arange(n // 2 + 1, dtype=np.float64)
+    p = np.zeros_like(m)
+    k = 2.0 * np.pi * m[1:] / box
+    p[1:] = amp / (k * k)
+    a = (rng.standard_normal(m.size) + 1j * rng.standard_normal(m.size)) * np.sqrt(p / box / 2.0)
+    a[0] = 0.0
+    a[-1] = 0.0  # no Nyquist mode
+    # irfft(c) = (1/n) sum_m c_m e^{2 pi i m j / n} + conj. terms
+    d0 = np.fft.irfft(a * n, n=n)
+    if np.max(theta * d0) >= 1.0:
+        raise ValueError(f"theta = {theta} is past the first orbit crossing of this field")
+    d = 1.0 / (1.0 - theta * d0) - 1.0
+    return (d, d0) if return_initial else d
 
 
 def paper_f1(n: int = 512) -> np.ndarray:

@@ -230,3 +230,25 @@ def test_analytic_mode_rejections():
     assert e.value.code == cwt.CWT_EUNSUPPORTED
     p = cwt.Plan(512, "periodic", "cbsw", [2.0, 300.0], fft_mode="whole", psi_mode="analytic", host_only=True)
     assert p.fft_len == 512 and p.scale_path().tolist() == [cwt.PATH_COLUMN] * 2
+
+
+def test_wps_workspace_and_rejections_host_only():
+    # statistics epilogue (Sec. 5): workspace = the plan's own plus one slot of
+    # partial sums per workgroup and scale and the bin-count partials;
+    # rejected before any device work for host-only or non-segmented plans
+    lib = cwt.load()
+    sc = np.geomspace(2.0, 65536.0, 128)
+    p = cwt.Plan(1 << 22, "periodic", "cwgdw", sc, precision="fp32", host_only=True)
+    wb = cwt.wps_workspace_bytes(p)
+    assert wb > p.workspace_bytes
+    # at most 4 bins of 8 bytes per workgroup and scale: bounded by the plan size
+    assert wb - p.workspace_bytes < 64 << 20
+    thr = (ctypes.c_double * 1)(0.0)
+    rc = lib.cwt_exec_wps(p.handle, None, None, thr, 1, None, None, None, None)
+    assert rc == cwt.CWT_EINVAL
+    sp = cwt.Plan(4096, "zero", "mexhat", [3.0, 30.0], method="spline", host_only=True)
+    assert cwt.wps_workspace_bytes(sp) == 0
+    assert lib.cwt_exec_wps(sp.handle, None, None, thr, 1, None, None, None, None) == cwt.CWT_EUNSUPPORTED
+    wp = cwt.Plan(4096, "periodic", "morlet", [3.0, 30.0], fft_mode="whole", host_only=True)
+    assert cwt.wps_workspace_bytes(wp) == 0
+    assert lib.cwt_exec_wps(None, None, None, thr, 1, None, None, None, None) == cwt.CWT_EINVAL
