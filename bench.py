@@ -45,6 +45,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -54,6 +55,7 @@ sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 FP64_PEAK_TFS = 78.6       # MI355X FP64 vector, published
+FP32_PEAK_TFS = 157.3      # MI355X FP32 vector, published
 
 
 def kernel_source_hash() -> str:
@@ -287,9 +289,15 @@ def main():
                     help="served form instead: Poisson request streams (2^12..2^22 samples, 32..256 scales, "
                          "Morlet(6) / Mexican hat / DOG(4), FP32) at 0.5, 0.8 and 0.95 of the plain-batched "
                          "capacity, continuous batching against plain batching, p50 / p99 latency")
+    ap.add_argument("--wps", action="store_true",
+                    help="statistics epilogue instead (Sec. 5): env-WPS (split at delta = 0) and global WPS "
+                         "of a periodic 1D Zel'dovich field (theta = 100), N = 2^22, 128 log scales 2..2^16, "
+                         "CW-GDW, FP32 form, against the plain transform of the same field")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
-    ap.add_argument("--wavelet", default=None, choices=["morlet", "dog2", "mexhat"])
+    ap.add_argument("--wavelet", default=None, choices=["morlet", "dog2", "mexhat", "cwgdw"])
+    ap.add_argument("--thresholds", default="0",
+                    help="--wps: comma-separated environment thresholds (empty: one bin)")
     ap.add_argument("--boundary", default="zero", choices=["zero", "periodic"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-table", action="store_true")
@@ -312,6 +320,8 @@ def main():
         return bench_batch(args)
     if args.serve:
         return bench_serve(args)
+    if args.wps:
+        return bench_wps(args)
     if args.method == "fft":
         n, nscales, smax, precision = 1 << 22, 128, 2.0 ** 16, "fp32"
         seed, nname = synth.SEED_FIELD_4M, "2^22"
@@ -320,7 +330,8 @@ def main():
         n, nscales, smax, precision = 1 << 20, 64, 2.0 ** 14, "fp64"
         seed, nname = synth.SEED_FIELD_1M, "2^20"
         wavelet = args.wavelet or "mexhat"
-    wav, par = {"morlet": ("morlet", 6.0), "dog2": ("dog", 2.0), "mexhat": ("mexhat", None)}[wavelet]
+    wav, par = {"morlet": ("morlet", 6.0), "dog2": ("dog", 2.0), "mexhat": ("mexhat", None),
+                "cwgdw": ("cwgdw", None)}[wavelet]
     scales = synth.log_scales(2.0, smax, nscales)
     dt = np.float32 if precision == "fp32" else np.float64
     f = synth.lognormal_field(n, seed=seed).astype(dt)
@@ -429,6 +440,104 @@ def main():
                        "precision": precision},
             "roofline": roof, "whole_step": whole, "measured_peaks": peaks, "per_scale_error": err,
             "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
+def fft_flops(plan, kernel):
+    """FFT flops of one launch of an output kernel, 5 L log2 L per complex
+    L-point inverse it takes (the usual count), from the plan's segment
+    groups: local2_kernel<..,L,..> takes G-column blocks of L points per
+    scale (or real-scale pair), seg_inverse_kernel<..,P,..> 16 P-point
+    columns per work item and unit."""
+    import re
+    m = re.match(r"(local2_kernel|seg_inverse_kernel)<f(32|64),(\d+),", kernel)
+    if not m:
+        return None
+    size, fp64 = int(m.group(3)), m.group(2) == "64"
+    cplx = plan.is_complex
+    total = 0.0
+    for line in plan.describe().splitlines():
+        g = dict(kv.split("=") for kv in line.split()[1:] if "=" in kv)
+        if line.startswith("local ") and m.group(1) == "local2_kernel" and int(g["L"]) == size:
+            L, k = int(g["L"]), int(g["scales"])
+            ncol = max((2048 if fp64 else 4096) // L, 1)
+            units = k if cplx else (k + 1) // 2
+            total += -(-int(g["nseg"]) // ncol) * ncol * units * 5.0 * L * math.log2(L)
+        if line.startswith("band ") and m.group(1) == "seg_inverse_kernel" and int(g["P"]) == size:
+            L, P, k = int(g["L"]), int(g["P"]), int(g["scales"])
+            cp = g.get("colpair") == "1"
+            cols = 32 if cp else 16
+            units = k if (cplx or cp) else (k + 1) // 2
+            total += int(g["nseg"]) * -(-(L // P) // cols) * 16 * units * 5.0 * P * math.log2(P)
+    return total
+
+
+def bench_wps(args):
+    """One step = one cwt_exec_wps call: the environment-dependent and global
+    wavelet power spectra of the field, with the coefficients reduced inside
+    the output kernels (nothing of size S x N is written)."""
+    import numpy as np
+    import torch
+    import paper_2302_03909_amd as cwt
+    import synth
+
+    n, nscales, smax = 1 << 22, 128, 2.0 ** 16
+    wav, par = "cwgdw", None
+    scales = synth.log_scales(2.0, smax, nscales)
+    f = synth.zeldovich_field(n).astype(np.float32)
+    dev = torch.device("cuda", 0)
+    print(f"bench: power spectra, CW-GDW N={n} S={nscales} fp32 periodic", file=sys.stderr, flush=True)
+    plan = cwt.Plan(n, "periodic", wav, scales, param=par, precision="fp32")
+    x = torch.as_tensor(f, device=dev)
+    ws = torch.empty(cwt.wps_workspace_bytes(plan), dtype=torch.uint8, device=dev)
+    thr = tuple(float(t) for t in args.thresholds.split(",") if t.strip())
+
+    def step():
+        return cwt.exec_wps(plan, x, None, thr, workspace=ws, with_counts=False)
+
+    warm = warm_up(step, args.warmup)
+    ms, per_step = timed_steps(step, args.steps)
+    # the plain transform of the same field (coefficients written)
+    out = plan.empty_output(dev)
+    wsp = plan.empty_workspace(dev)
+    warm_up(lambda: plan(x, out, wsp), 3)
+    ms_plain, per_plain = timed_steps(lambda: plan(x, out, wsp), args.steps)
+    del out
+    plan.timing(True)
+    ms_ev, _ = timed_steps(step, args.steps)
+    plan.timing(False)
+    kern = plan.timing_read()
+    wps, _ = step()
+    torch.cuda.synchronize()
+    wps = wps.cpu().numpy()
+    name, (cnt, tot_ms, bpl) = max(kern.items(), key=lambda kv: kv[1][1])
+    avg_s = tot_ms / cnt * 1e-3
+    flops = fft_flops(plan, name)
+    achieved = flops / avg_s / 1e12
+    coeffs = n * nscales
+    workload = ("power spectra (env-WPS split at delta = 0, global WPS) of a periodic 1D Zel'dovich field "
+                "theta = 100, N=2^22, CW-GDW, 128 log scales 2..2^16, fp32 form")
+    line = {"metric": "CWT coefficients reduced to power spectra per second (N x scales)",
+            "value": coeffs / (ms * 1e-3), "unit": "coefficients/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": workload, "n": n, "scales": nscales, "thresholds": list(thr)},
+            "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFS, "unit": "TFLOP/s",
+                         "frac": round(achieved / FP32_PEAK_TFS, 4), "traffic": None, "kernel": name,
+                         "avg_launch_ms": round(tot_ms / cnt, 4), "fft_flops_per_launch": flops},
+            "whole_step": {"ms_median": round(float(np.median(per_step)), 4),
+                           "ms_min": round(float(np.min(per_step)), 4),
+                           "warmup_steps": warm[0],
+                           "plain_transform_ms": round(ms_plain, 4),
+                           "plain_transform_ms_median": round(float(np.median(per_plain)), 4),
+                           "speedup_vs_plain": round(ms_plain / ms, 3),
+                           "ms_per_step_with_kernel_events": round(ms_ev, 4),
+                           "kernels": {k: {"launches": v[0], "ms_per_step": round(v[1] / args.steps, 4),
+                                           "bytes_per_launch": v[2]} for k, v in kern.items()},
+                           "env_over_global_first_last_scale": [
+                               [round(float(wps[0, b] / wps[0, -1]), 4) for b in range(len(thr) + 1)],
+                               [round(float(wps[-1, b] / wps[-1, -1]), 4) for b in range(len(thr) + 1)]]},
+            "cpu_baseline": None}
     print(json.dumps(line), flush=True)
 
 

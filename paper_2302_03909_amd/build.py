@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcwt.so")
 ROOT = os.path.dirname(HERE)
-SOURCES = ["cwt_plan.cpp", "cwt_spline_plan.cpp", "cwt_fft.hip", "cwt_seg.hip", "cwt_spline.hip", "cwt_tables.hip", "cwt_wps.hip"]
+SOURCES = ["cwt_plan.cpp", "cwt_spline_plan.cpp", "cwt_fft.hip", "cwt_seg.hip", "cwt_spline.hip", "cwt_tables.hip", "cwt_wps.hip",
+           "cwt_wps_b1.hip", "cwt_wps_b2.hip", "cwt_wps_b4.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

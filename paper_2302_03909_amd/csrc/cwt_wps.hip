@@ -3,10 +3,11 @@
 //   P(s, bin) = <|W(s, x)|^2> over the positions x whose environment value
 //               falls in the bin                              (Eq. env_wps)
 //   P(s)      = <|W(s, x)|^2> over all positions              (Eq. global_wps)
-// reduced inside the two output kernels (seg_kernels.h, instantiated here
-// with RED = true) instead of writing the S x N coefficients.  Every
-// position falls in exactly one bin, so P(s) = sum_bin f_bin P(s, bin) with
-// f_bin = N_bin / N (Eq. global_wps_env_wps) holds by construction.
+// reduced inside the two output kernels (seg_kernels.h, instantiated for 1,
+// 2 and up to 4 bins in cwt_wps_b*.hip) instead of writing the S x N
+// coefficients.  Every position falls in exactly one bin, so
+// P(s) = sum_bin f_bin P(s, bin) with f_bin = N_bin / N (Eq.
+// global_wps_env_wps) holds by construction.
 //
 // Workgroup sums go to fixed slots and are added in a fixed order, so the
 // result does not depend on scheduling.
@@ -92,11 +93,19 @@ hipError_t launch_wps_finalize(const double *part, const int64_t *base, int S, c
     return hipGetLastError();
 }
 
+hipError_t launch_out_kernel_wps1(const SegKernelId &id, const BatchArgs &a, int64_t blocks, hipStream_t st);
+hipError_t launch_out_kernel_wps2(const SegKernelId &id, const BatchArgs &a, int64_t blocks, hipStream_t st);
+hipError_t launch_out_kernel_wps4(const SegKernelId &id, const BatchArgs &a, int64_t blocks, hipStream_t st);
+
 hipError_t launch_seg_kernel_wps(const SegKernelId &id, const BatchArgs &a, int64_t blocks, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (id.kind == 0 || id.kind == 3) return launch_out_kernel<true>(id, a, blocks, st);
-    return launch_seg_kernel(id, a, blocks, st);  // the forward and reduce kernels are shared
+    if (id.kind != 0 && id.kind != 3) return launch_seg_kernel(id, a, blocks, st);  // forward, reduce: shared
+    // variants specialised on the bin count (1, 2, or up to 4)
+    if (a.wps.nbin == 1) return launch_out_kernel_wps1(id, a, blocks, st);
+    if (a.wps.nbin == 2) return launch_out_kernel_wps2(id, a, blocks, st);
+    if (a.wps.nbin <= kWpsMaxBins) return launch_out_kernel_wps4(id, a, blocks, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace cwt

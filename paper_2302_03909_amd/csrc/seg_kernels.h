@@ -173,25 +173,58 @@ __device__ __forceinline__ void put_code(uint32_t (&codes)[4], int k, uint32_t c
 __device__ __forceinline__ uint32_t get_code(const uint32_t (&codes)[4], int k) {
     return (codes[k >> 3] >> ((k & 7) * 4)) & 15u;
 }
-// acc[bin(code)] += v (codes of other bins, and kNoBin, add nothing)
-template <typename A>
-__device__ __forceinline__ void wps_acc(A (&acc)[kWpsMaxBins], uint32_t code, A v, int nbin) {
+// acc[bin(code)] += x^2 (codes of other bins, and kNoBin, add nothing): one
+// compare, select and fused multiply-add per bin
+template <int NB, typename A>
+__device__ __forceinline__ void wps_acc(A (&acc)[kWpsMaxBins], uint32_t code, A x) {
 #pragma unroll
-    for (int b = 0; b < kWpsMaxBins; ++b)
-        if (b < nbin) acc[b] += code == (uint32_t)b ? v : (A)0;
+    for (int b = 0; b < NB; ++b) acc[b] = fma(x, code == (uint32_t)b ? x : (A)0, acc[b]);
 }
-// per-wave sums (FP64, fixed butterfly order) parked in LDS:
-// red[(wave * 2 + half) * kWpsMaxBins + bin]
-__device__ __forceinline__ void wps_park_one(double v, double *red, int half, int b) {
+// the same for |x + i y|^2
+template <int NB, typename A>
+__device__ __forceinline__ void wps_acc(A (&acc)[kWpsMaxBins], uint32_t code, A x, A y) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) red[((threadIdx.x >> 6) * 2 + half) * kWpsMaxBins + b] = v;
+    for (int b = 0; b < NB; ++b) {
+        const bool in = code == (uint32_t)b;
+        acc[b] = fma(y, in ? y : (A)0, fma(x, in ? x : (A)0, acc[b]));
+    }
+}
+// Sum over the 64 lanes of a wave with DPP moves (VALU only, no LDS round
+// trip): lane pairs and quads by quad permutations, rows of 16 by row shifts
+// of 4 and 8, then the row totals broadcast upward (lane 15 of each row into
+// the next row, lane 31 into rows 2 and 3).  Lane 63 ends with the total;
+// the summation order is fixed.  Lanes a move does not write, and sources
+// outside the row, contribute 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWMASK, 0xf, true));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const u32x2 h = __builtin_bit_cast(u32x2, v);
+    u32x2 r;
+    r.x = (unsigned)__builtin_amdgcn_update_dpp(0, (int)h.x, CTRL, ROWMASK, 0xf, true);
+    r.y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)h.y, CTRL, ROWMASK, 0xf, true);
+    return __builtin_bit_cast(double, r);
 }
 template <typename A>
-__device__ __forceinline__ void wps_park(const A (&acc)[kWpsMaxBins], double *red, int half, int nbin) {
+__device__ __forceinline__ A wave_total(A v) {
+    v += dpp_move<0xb1, 0xf>(v);   // quad_perm(1, 0, 3, 2)
+    v += dpp_move<0x4e, 0xf>(v);   // quad_perm(2, 3, 0, 1)
+    v += dpp_move<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);  // row_shr:8: lanes 12..15 of a row hold its total
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+// per-wave sums parked in LDS: red[(wave * 2 + half) * kWpsMaxBins + bin]
+template <int NB, typename A>
+__device__ __forceinline__ void wps_park(const A (&acc)[kWpsMaxBins], double *red, int half) {
 #pragma unroll
-    for (int b = 0; b < kWpsMaxBins; ++b)
-        if (b < nbin) wps_park_one((double)acc[b], red, half, b);
+    for (int b = 0; b < NB; ++b) {
+        const A t = wave_total(acc[b]);
+        if ((threadIdx.x & 63) == 63) red[((threadIdx.x >> 6) * 2 + half) * kWpsMaxBins + b] = (double)t;
+    }
 }
 // after a barrier: the workgroup's sums (waves added in order) to its slot
 template <int NT>
@@ -234,7 +267,7 @@ constexpr int seg_kls_elems(int rbytes, int P) {
 // registers, so the staged samples stay real), and column r < 0 of row p is
 // the output t = r + Q p (+ L when negative).
 
-template <typename R, int P, int NT, bool PAIR, bool CPLX, bool RED = false>
+template <typename R, int P, int NT, bool PAIR, bool CPLX, int RED = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void seg_inverse_kernel(
     const BatchArgs a) {
     using C = cplx_t<R>;
@@ -433,20 +466,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
                 int k = 0;
                 auto remit = [&](int, int, C val) {
                     if constexpr (CPLX) {
-                        wps_acc(acc_a, get_code(codes, k), val.x * val.x + val.y * val.y, nbin);
+                        wps_acc<RED>(acc_a, get_code(codes, k), val.x, val.y);
                     } else if constexpr (CP) {
-                        wps_acc(acc_a, get_code(codes, 2 * k), val.x * val.x, nbin);
-                        wps_acc(acc_a, get_code(codes, 2 * k + 1), val.y * val.y, nbin);
+                        wps_acc<RED>(acc_a, get_code(codes, 2 * k), val.x);
+                        wps_acc<RED>(acc_a, get_code(codes, 2 * k + 1), val.y);
                     } else {
-                        wps_acc(acc_a, get_code(codes, k), val.x * val.x, nbin);
-                        wps_acc(acc_b, get_code(codes, k), val.y * val.y, nbin);
+                        wps_acc<RED>(acc_a, get_code(codes, k), val.x);
+                        wps_acc<RED>(acc_b, get_code(codes, k), val.y);
                     }
                     ++k;
                 };
                 cols_fft_after0<C, P, G, NT, LD, +1, false>(buf, twl, remit);
                 const bool has_b = PAIR && !CP && sb >= 0;
-                wps_park(acc_a, red, 0, nbin);
-                if (has_b) wps_park(acc_b, red, 1, nbin);
+                wps_park<RED>(acc_a, red, 0);
+                if (has_b) wps_park<RED>(acc_b, red, 1);
                 lds_barrier();
                 const int64_t slot = rv.local - gd.inv0;
                 wps_store<NT>(red, 0, rv.bi.part, cload(kd->wps_base + sa) + slot, nbin);
@@ -522,7 +555,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
 // Real wavelets (PAIR): the spectrum of a scale, phase folded into X, is
 // Hermitian (real and even, or imaginary and odd), so X K_a + i X K_b inverts
 // to w_a + i w_b: one inverse yields two scales, real part and imaginary part.
-template <typename R, int L, int G, int NT, bool PAIR, bool CPLX, bool RED = false>
+template <typename R, int L, int G, int NT, bool PAIR, bool CPLX, int RED = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2))) void local2_kernel(
     const BatchArgs a) {
     using C = cplx_t<R>;
@@ -667,17 +700,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             auto remit = [&](int, int, C val) {
                 const uint32_t code = get_code(codes, k);
                 if constexpr (CPLX) {
-                    wps_acc(acc_a, code, val.x * val.x + val.y * val.y, nbin);
+                    wps_acc<RED>(acc_a, code, val.x, val.y);
                 } else {
-                    wps_acc(acc_a, code, val.x * val.x, nbin);
-                    wps_acc(acc_b, code, val.y * val.y, nbin);
+                    wps_acc<RED>(acc_a, code, val.x);
+                    wps_acc<RED>(acc_b, code, val.y);
                 }
                 ++k;
             };
             cols_fft_after0<C, L, G, NT, LD, +1, false, decltype(remit), true>(buf, twl, remit);
             const bool has_b = PAIR && j + 1 < nscale;
-            wps_park(acc_a, red, 0, nbin);
-            if (has_b) wps_park(acc_b, red, 1, nbin);
+            wps_park<RED>(acc_a, red, 0);
+            if (has_b) wps_park<RED>(acc_b, red, 1);
             lds_barrier();
             wps_store<NT>(red, 0, rv.bi.part, cload(kd->wps_base + cload(scale_ids + j)) + rv.local, nbin);
             if (has_b) wps_store<NT>(red, 1, rv.bi.part, cload(kd->wps_base + cload(scale_ids + j + 1)) + rv.local, nbin);
@@ -707,14 +740,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
 }
 
 // ---------------------------------------------------------------------------
-// launchers of the two output kernels (RED: the statistics variants)
+// launchers of the two output kernels (RED > 0: the statistics variants
+// for up to RED environment bins)
 
 // local2 columns per workgroup: 4096 points (FP32) or 2048 points (FP64), at
 // least one
 constexpr int local2_ncol(int L, bool fp64) { return (fp64 ? 2048 : 4096) / L > 1 ? (fp64 ? 2048 : 4096) / L : 1; }
 constexpr int local2_nt(int L, bool fp64) { return local2_ncol(L, fp64) * L / 16; }
 
-template <typename R, int L, bool RED>
+template <typename R, int L, int RED>
 hipError_t local2_launch_L(const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
     constexpr int NCOL = local2_ncol(L, sizeof(R) == 8);
     constexpr int NT = local2_nt(L, sizeof(R) == 8);
@@ -725,7 +759,7 @@ hipError_t local2_launch_L(const BatchArgs &a, int64_t blocks, bool cplx, hipStr
     return hipGetLastError();
 }
 
-template <typename R, bool RED>
+template <typename R, int RED>
 hipError_t local2_typed(int L, const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
     switch (L) {
         case 64: return local2_launch_L<R, 64, RED>(a, blocks, cplx, st);
@@ -739,7 +773,7 @@ hipError_t local2_typed(int L, const BatchArgs &a, int64_t blocks, bool cplx, hi
     }
 }
 
-template <typename R, int P, bool RED>
+template <typename R, int P, int RED>
 hipError_t inverse_launch_P(const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
     constexpr int NT = P;  // 16 columns x P / 16 elements per thread
     if (cplx)
@@ -749,7 +783,7 @@ hipError_t inverse_launch_P(const BatchArgs &a, int64_t blocks, bool cplx, hipSt
     return hipGetLastError();
 }
 
-template <typename R, bool RED>
+template <typename R, int RED>
 hipError_t inverse_typed(int P, const BatchArgs &a, int64_t blocks, bool cplx, hipStream_t st) {
     switch (P) {
         case 64: return inverse_launch_P<R, 64, RED>(a, blocks, cplx, st);
@@ -761,7 +795,7 @@ hipError_t inverse_typed(int P, const BatchArgs &a, int64_t blocks, bool cplx, h
 }
 
 // kind 0 (local2) or 3 (band inverse)
-template <bool RED>
+template <int RED>
 hipError_t launch_out_kernel(const SegKernelId &id, const BatchArgs &a, int64_t blocks, hipStream_t st) {
     const bool fp64 = id.precision == 0, cplx = id.cplx != 0;
     if (id.kind == 0)
