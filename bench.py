@@ -295,10 +295,15 @@ def main():
                          "CW-GDW, FP32 form, against the plain transform of the same field")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
+                    help="offered loads, as fractions of the plain-batched capacity")
     ap.add_argument("--wavelet", default=None, choices=["morlet", "dog2", "mexhat", "cwgdw"])
     ap.add_argument("--thresholds", default="0",
                     help="--wps: comma-separated environment thresholds (empty: one bin)")
     ap.add_argument("--boundary", default="zero", choices=["zero", "periodic"])
+    ap.add_argument("--fft-mode", default="segmented", choices=["segmented", "whole"],
+                    help="FFT method layout: overlap-save segments (default) or one FFT of the whole "
+                         "signal (Fig. fftCWT's form), for comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-table", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -338,7 +343,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     print(f"bench: {args.method} {wav} N={n} S={nscales} {precision}", file=sys.stderr, flush=True)
-    plan = cwt.Plan(n, args.boundary, wav, scales, param=par, precision=precision, method=args.method)
+    plan = cwt.Plan(n, args.boundary, wav, scales, param=par, precision=precision, method=args.method,
+                    fft_mode=args.fft_mode)
     x = torch.as_tensor(f, device=dev)
     out = plan.empty_output(dev)
     ws = plan.empty_workspace(dev)
@@ -351,7 +357,7 @@ def main():
     # the same plan with every launch on the caller's stream (no second
     # stream for the local kernels), for the choice of the default
     alt = None
-    if args.method == "fft":
+    if args.method == "fft" and args.fft_mode == "segmented":
         plan1 = cwt.Plan(n, args.boundary, wav, scales, param=par, precision=precision, single_stream=True)
         warm_up(lambda: plan1(x, out, ws), 3)
         ms1, per1 = timed_steps(lambda: plan1(x, out, ws), args.steps)
@@ -379,7 +385,8 @@ def main():
     workload = (f"lognormal field N={nname} {args.boundary} boundary, {wname}, "
                 f"{nscales} log scales 2..2^{int(np.log2(smax))}, "
                 f"{'fp32 form' if precision == 'fp32' else 'fp64'}"
-                + (", spline method" if args.method == "spline" else ""))
+                + (", spline method" if args.method == "spline" else "")
+                + (", whole-signal FFT" if args.fft_mode == "whole" else ""))
 
     # dominant kernel: largest total time over the timed region
     name, (cnt, tot_ms, bpl) = max(kern.items(), key=lambda kv: kv[1][1])
@@ -610,6 +617,10 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+PLANNERS = 4  # host threads that build request plans beside the polling loop
+IDLE_SLEEP = 20e-6  # polling loop: pause after an idle poll (lets the planner threads run)
+
+
 def bench_serve(args):
     """Served form: requests take the first N samples of one of a few
     device-resident signals of 2^22 samples (periodic tones + noise for the
@@ -640,31 +651,52 @@ def bench_serve(args):
         return out
 
     total = args.serve_requests + args.serve_warmup
-    budget = 64 << 30
+    budget = 32 << 30
     mean_coef = synth.mean_request_coefficients()
-    # plain-batched capacity: every request available at once
+    # plain-batched capacity of the GPU: every request available at once,
+    # plans built beforehand (the device's rate, not the planners')
     print("bench: measuring plain-batched capacity", file=sys.stderr, flush=True)
     specs = synth.request_specs(min(total, 600), rate_hz=1e9, seed=synth.SEED_SERVE + 1)
-    ex = GpuExecutor(streams=1, keep_outputs=False)
-    done = run_open_loop(StaticBatcher(ex, max_batch=32, window=0.0), make(specs))
+    ex = GpuExecutor(streams=1, keep_outputs=False, plan_cache=1 << 20, arena_bytes=budget)
+    reqs = make(specs)
+    for r in reqs:
+        r.footprint = ex.prepare(r)
+    sched = StaticBatcher(ex, max_batch=32, window=0.0, budget_bytes=budget)
+    done = run_open_loop(sched, reqs)
     torch.cuda.synchronize()
     cap = latency_summary(done)["coefficients_per_s"]
     cap_rps = cap / mean_coef
+    del ex, sched, reqs, done
     results = {}
-    for load in (0.5, 0.8, 0.95):
+    loads = [float(x) for x in args.serve_loads.split(",")]
+    for load in loads:
         specs = synth.request_specs(total, rate_hz=load * cap_rps, seed=synth.SEED_SERVE)
-        for mode in ("continuous", "plain"):
-            print(f"bench: load {load} {mode}", file=sys.stderr, flush=True)
-            ex = GpuExecutor(streams=2, keep_outputs=False)
-            sched = (ContinuousScheduler(ex, budget_bytes=budget, streams=2) if mode == "continuous"
-                     else StaticBatcher(ex, max_batch=32, window=2e-3))
-            done = run_open_loop(sched, make(specs))
-            torch.cuda.synchronize()
-            summ = latency_summary(done, skip=args.serve_warmup)
-            summ["mean_batch"] = float(np.mean(sched.batches))
-            results[f"{mode}@{load}"] = summ
-    top = results["continuous@0.95"]
-    line = {"metric": "served CWT coefficients/s and p50/p99 latency at 0.95 x plain-batched capacity",
+        # cold: each request planned at arrival by the planner threads;
+        # warm: plans of the stream's shapes already built (a plan cache hit)
+        for plans in ("cold", "warm"):
+            for mode in ("continuous", "plain"):
+                print(f"bench: load {load} {mode} {plans} plans", file=sys.stderr, flush=True)
+                ex = GpuExecutor(streams=2, keep_outputs=False, plan_cache=1 << 20, arena_bytes=budget)
+                reqs = make(specs)
+                if plans == "warm":
+                    for r in reqs:
+                        r.footprint = ex.prepare(r)
+                sched = (ContinuousScheduler(ex, budget_bytes=budget, streams=2, planners=PLANNERS)
+                         if mode == "continuous" else StaticBatcher(ex, max_batch=32, window=2e-3, planners=PLANNERS,
+                                                                    budget_bytes=budget))
+                done = run_open_loop(sched, reqs, idle_sleep=IDLE_SLEEP)
+                sched.close()
+                torch.cuda.synchronize()
+                summ = latency_summary(done, skip=args.serve_warmup)
+                summ["mean_batch"] = float(np.mean(sched.batches))
+                summ["launch_host_s"] = round(ex.launch_s, 3)
+                summ["arena_fallbacks"] = ex.arena_fallbacks
+                results[f"{mode}@{load}/{plans}"] = summ
+                for p_ in list(ex.plans.values()):
+                    p_.close()
+                del ex, sched, reqs, done
+    top = results[f"continuous@{loads[-1]}/cold"]
+    line = {"metric": f"served CWT coefficients/s and p50/p99 latency at {loads[-1]} x plain-batched capacity",
             "value": top["coefficients_per_s"], "unit": "coefficients/s", "n_gpus": 1,
             "steps": args.serve_requests, "warmup": args.serve_warmup, "ms_per_step": top["mean_ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -672,7 +704,8 @@ def bench_serve(args):
             "config": {"workload": "Poisson request stream: N log-uniform 2^12..2^22, 32..256 log scales, "
                                    "Morlet(6) / Mexican hat / DOG(4), periodic or zero boundary, fp32 form",
                        "plain_batched_capacity_coef_per_s": cap, "capacity_requests_per_s": cap_rps,
-                       "mean_request_coefficients": mean_coef, "budget_bytes": budget},
+                       "mean_request_coefficients": mean_coef, "budget_bytes": budget,
+                       "planner_threads": PLANNERS},
             "serve": results, "roofline": None, "cpu_baseline": None}
     print(json.dumps(line), flush=True)
 

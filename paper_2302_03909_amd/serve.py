@@ -15,6 +15,13 @@ Two schedulers share one executor interface:
   requests or until ``window`` seconds passed since the oldest, run them as
   one batch, wait for it, release, repeat.
 
+Planning (building a request's plan: validation, segment framing, device
+tables, on the host and the calling thread's plan stream) happens either
+inline in ``poll`` (``planners=0``) or on a pool of ``planners`` host
+threads started at ``submit``, so that the polling loop only admits,
+launches and collects; a request is admitted once its plan is ready (the
+head of the queue waits for its own).  Each request records ``plan_ms``.
+
 ``GpuExecutor`` runs batches with the library; tests drive the schedulers
 with a simulated executor and clock.  Every result is bit-identical to the
 same request transformed alone (``cwt_exec_batch`` guarantees it).
@@ -26,7 +33,9 @@ device completion.
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import dataclasses
+import threading
 import time
 from typing import Any, Callable, Optional
 
@@ -54,19 +63,63 @@ class Request:
     output: Any = None
     error: Optional[str] = None
     plan: Any = None
+    plan_ms: Optional[float] = None
+    planned: Any = None  # future of a background planning job
 
     @property
     def coefficients(self) -> int:
         return int(self.n) * int(np.asarray(self.scales).size)
 
 
+def _plan(ex, r: Request) -> None:
+    """Builds the request's plan (sets footprint or error, and plan_ms)."""
+    t0 = time.perf_counter()
+    try:
+        r.footprint = int(ex.prepare(r))
+    except Exception as e:  # unsupported request
+        r.error = str(e)
+    r.plan_ms = (time.perf_counter() - t0) * 1e3
+
+
+class _Planning:
+    """Inline or pooled planning shared by the two schedulers."""
+
+    def __init__(self, executor, planners: int):
+        if planners < 0:
+            raise ValueError("planners must be >= 0")
+        self.ex = executor
+        self.pool = concurrent.futures.ThreadPoolExecutor(planners) if planners > 0 else None
+
+    def start(self, r: Request) -> None:
+        if self.pool is not None:
+            r.planned = self.pool.submit(_plan, self.ex, r)
+
+    def ready(self, r: Request) -> bool:
+        """True once the request's plan (or its error) is there; plans it
+        inline when there is no pool."""
+        if r.planned is not None:
+            if not r.planned.done():
+                return False
+            r.planned.result()
+            r.planned = None
+            return True
+        if r.footprint == 0 and r.error is None:
+            _plan(self.ex, r)
+        return True
+
+    def close(self) -> None:
+        if self.pool is not None:
+            self.pool.shutdown(wait=True)
+
+
 class ContinuousScheduler:
     """Continuous batching over ``streams`` slots within ``budget_bytes``."""
 
     def __init__(self, executor, budget_bytes: int, streams: int = 2, max_batch: int = 256,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, planners: int = 0):
         if streams < 1 or max_batch < 1 or budget_bytes <= 0:
             raise ValueError("streams, max_batch and budget_bytes must be positive")
+        self.planning = _Planning(executor, planners)
         self.ex = executor
         self.budget = int(budget_bytes)
         self.streams = int(streams)
@@ -80,7 +133,11 @@ class ContinuousScheduler:
         self.batches: list[int] = []  # sizes of the launched batches
 
     def submit(self, req: Request) -> None:
+        self.planning.start(req)
         self.queue.append(req)
+
+    def close(self) -> None:
+        self.planning.close()
 
     @property
     def idle(self) -> bool:
@@ -103,11 +160,8 @@ class ContinuousScheduler:
         # admission in arrival order (the head waits until it fits)
         while self.queue:
             r = self.queue[0]
-            if r.footprint == 0 and r.error is None:
-                try:
-                    r.footprint = int(self.ex.prepare(r))
-                except Exception as e:  # unsupported request
-                    r.error = str(e)
+            if not self.planning.ready(r):
+                break
             if r.error is None and r.footprint > self.budget:
                 r.error = f"footprint {r.footprint} bytes exceeds the budget of {self.budget}"
             if r.error is not None:
@@ -142,7 +196,10 @@ class StaticBatcher:
     overlap."""
 
     def __init__(self, executor, max_batch: int = 64, window: float = 2e-3,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, planners: int = 0,
+                 budget_bytes: Optional[int] = None):
+        self.planning = _Planning(executor, planners)
+        self.budget = budget_bytes
         self.ex = executor
         self.max_batch = int(max_batch)
         self.window = float(window)
@@ -152,7 +209,11 @@ class StaticBatcher:
         self.batches: list[int] = []
 
     def submit(self, req: Request) -> None:
+        self.planning.start(req)
         self.pending.append((self.clock(), req))
+
+    def close(self) -> None:
+        self.planning.close()
 
     @property
     def idle(self) -> bool:
@@ -172,15 +233,24 @@ class StaticBatcher:
             self.current = None
         if self.pending and (len(self.pending) >= self.max_batch or now - self.pending[0][0] >= self.window):
             batch = []
+            used = 0
             while self.pending and len(batch) < self.max_batch:
-                _, r = self.pending.popleft()
-                try:
-                    r.footprint = int(self.ex.prepare(r))
-                except Exception as e:
-                    r.error = str(e)
+                # the batch takes the planned requests in arrival order,
+                # within the footprint budget (if any)
+                r = self.pending[0][1]
+                if not self.planning.ready(r):
+                    break
+                if r.error is None and self.budget is not None:
+                    if r.footprint > self.budget:
+                        r.error = f"footprint {r.footprint} bytes exceeds the budget of {self.budget}"
+                    elif used + r.footprint > self.budget:
+                        break
+                self.pending.popleft()
+                if r.error is not None:
                     r.done = now
                     out.append(r)
                     continue
+                used += r.footprint
                 r.admitted = r.launched = now
                 batch.append(r)
             if batch:
@@ -191,11 +261,20 @@ class StaticBatcher:
 
 class GpuExecutor:
     """Runs batches with ``cwt_exec_batch`` on ``streams`` torch streams
-    (default priority).  Plans are cached by request shape (LRU); outputs
-    are allocated per request on the launching stream.  ``keep_outputs``
-    False drops each output once its batch has finished (benchmarks)."""
+    (default priority).  Plans are cached by request shape (LRU).
 
-    def __init__(self, device="cuda:0", streams: int = 2, plan_cache: int = 256, keep_outputs: bool = True):
+    Outputs: with ``keep_outputs`` (the default) each request gets its own
+    output tensor, allocated on the launching stream and handed over in
+    ``Request.output``.  Otherwise (a consumer that reads each result when
+    its batch completes, and benchmarks) every stream owns a device arena of
+    ``arena_bytes`` allocated once, and a batch's outputs and workspace are
+    carved from its stream's arena: a stream runs one batch at a time, so
+    the arena is free again when the next batch is launched on it, and the
+    loop allocates no device memory (a batch larger than the arena falls
+    back to allocation)."""
+
+    def __init__(self, device="cuda:0", streams: int = 2, plan_cache: int = 256, keep_outputs: bool = True,
+                 arena_bytes: int = 0):
         import torch
         import paper_2302_03909_amd as cwt
         self.torch, self.cwt = torch, cwt
@@ -206,6 +285,11 @@ class GpuExecutor:
         self.keep_outputs = keep_outputs
         self._busy_plans: dict[int, int] = collections.Counter()
         self._retired: list = []
+        self._lock = threading.Lock()  # plan cache (planning may run on other threads)
+        self.launch_s = 0.0  # host time spent in launch()
+        self.arena_fallbacks = 0
+        self.arenas = ([torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device) for _ in self.streams]
+                       if arena_bytes > 0 and not keep_outputs else None)
 
     @staticmethod
     def _key(r: Request):
@@ -213,15 +297,28 @@ class GpuExecutor:
 
     def prepare(self, r: Request) -> int:
         key = self._key(r)
-        plan = self.plans.get(key)
+        with self._lock:
+            plan = self.plans.get(key)
+            if plan is not None:
+                self.plans.move_to_end(key)
+                self._busy_plans[id(plan)] += 1
         if plan is None:
-            plan = self.cwt.Plan(r.n, r.boundary, r.wavelet, r.scales, param=r.param, precision=r.precision)
-            self.plans[key] = plan
-            self._evict()
-        else:
-            self.plans.move_to_end(key)
+            built = self.cwt.Plan(r.n, r.boundary, r.wavelet, r.scales, param=r.param, precision=r.precision)
+            with self._lock:
+                plan = self.plans.get(key)
+                if plan is None:  # (another thread may have built the same shape meanwhile)
+                    plan = built
+                    self.plans[key] = plan
+                    self._evict()
+                else:
+                    self.plans.move_to_end(key)
+                    self._retired.append(built)
+                self._busy_plans[id(plan)] += 1
+            if plan is not built:
+                with self._lock:
+                    self._retired.remove(built)
+                built.close()
         r.plan = plan
-        self._busy_plans[id(plan)] += 1
         return plan.footprint_bytes
 
     def _evict(self):
@@ -235,13 +332,45 @@ class GpuExecutor:
                 plan.close()
 
     def launch(self, batch: list[Request], slot: int):
+        t0 = time.perf_counter()
+        try:
+            return self._launch(batch, slot)
+        finally:
+            self.launch_s += time.perf_counter() - t0
+
+    def _carve(self, plans, slot):
+        """Outputs and workspace of a batch as views of the slot's arena, or
+        None when they do not fit."""
+        if self.arenas is None:
+            return None
+        arena = self.arenas[slot]
+        off, views = 0, []
+        for p in plans:
+            _, odt = p._dtypes()
+            nb = p.num_scales * p.n * torch_itemsize(odt)
+            if off + nb > arena.numel():
+                return None
+            views.append(arena[off:off + nb].view(odt).view(p.num_scales, p.n))
+            off = (off + nb + 255) & ~255
+        wb = self.cwt.batch_workspace_bytes(plans)
+        if off + max(wb, 1) > arena.numel():
+            return None
+        return views, arena[off:off + max(wb, 1)]
+
+    def _launch(self, batch: list[Request], slot: int):
         torch = self.torch
         st = self.streams[slot]
         plans = [r.plan for r in batch]
         with torch.cuda.stream(st):
-            outs = [p.empty_output(self.device) for p in plans]
-            wb = self.cwt.batch_workspace_bytes(plans)
-            ws = torch.empty(max(wb, 1), dtype=torch.uint8, device=self.device)
+            carved = self._carve(plans, slot)
+            if carved is not None:
+                outs, ws = carved
+            else:
+                if self.arenas is not None:
+                    self.arena_fallbacks += 1
+                outs = [p.empty_output(self.device) for p in plans]
+                wb = self.cwt.batch_workspace_bytes(plans)
+                ws = torch.empty(max(wb, 1), dtype=torch.uint8, device=self.device)
             self.cwt.exec_batch(plans, [r.signal for r in batch], outs, ws, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
@@ -254,20 +383,32 @@ class GpuExecutor:
         i = handle["batch"].index(r)
         r.output = handle["outs"][i] if self.keep_outputs else None
         plan = r.plan
-        self._busy_plans[id(plan)] -= 1
-        if self._busy_plans[id(plan)] == 0:
-            del self._busy_plans[id(plan)]
-            if plan in self._retired:
-                self._retired.remove(plan)
-                plan.close()
+        close = False
+        with self._lock:
+            self._busy_plans[id(plan)] -= 1
+            if self._busy_plans[id(plan)] == 0:
+                del self._busy_plans[id(plan)]
+                if plan in self._retired:
+                    self._retired.remove(plan)
+                    close = True
+        if close:
+            plan.close()
         r.plan = None
 
 
+def torch_itemsize(dt) -> int:
+    import torch
+    return torch.empty((), dtype=dt).element_size()
+
+
 def run_open_loop(scheduler, requests: list[Request], clock: Callable[[], float] = time.perf_counter,
-                  advance: Optional[Callable[[float], None]] = None) -> list[Request]:
+                  advance: Optional[Callable[[float], None]] = None, idle_sleep: float = 0.0) -> list[Request]:
     """Submit each request at its arrival time (seconds after the start) and
     poll until all have completed.  ``advance(t)``, if given, moves a
-    simulated clock to t when nothing else can happen."""
+    simulated clock to t when nothing else can happen.  ``idle_sleep``: with
+    the real clock, sleep that long after a poll that completed nothing and
+    with no arrival due, so that planner threads get the interpreter (a
+    spinning loop would hold it for whole switch intervals)."""
     reqs = sorted(requests, key=lambda r: r.arrival)
     t0 = clock()
     for r in reqs:
@@ -283,6 +424,8 @@ def run_open_loop(scheduler, requests: list[Request], clock: Callable[[], float]
         if advance is not None and not got:
             nxt = reqs[i].arrival if i < len(reqs) else None
             advance(nxt)
+        elif idle_sleep > 0 and not got and (i == len(reqs) or reqs[i].arrival > clock()):
+            time.sleep(idle_sleep)
     return done
 
 
@@ -295,7 +438,12 @@ def latency_summary(done: list[Request], skip: int = 0) -> dict:
     lat = np.array([r.done - r.arrival for r in ok])
     span = max(r.done for r in ok) - min(r.arrival for r in ok)
     coeffs = sum(r.coefficients for r in ok)
-    return {"count": len(ok), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-            "coefficients_per_s": coeffs / span if span > 0 else None,
-            "rejected": sum(1 for r in done if r.error is not None)}
+    out = {"count": len(ok), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+           "coefficients_per_s": coeffs / span if span > 0 else None,
+           "rejected": sum(1 for r in done if r.error is not None)}
+    pm = np.array([r.plan_ms for r in ok if r.plan_ms is not None])
+    if pm.size:
+        out.update({"plan_ms_p50": float(np.percentile(pm, 50)), "plan_ms_p99": float(np.percentile(pm, 99)),
+                    "plan_ms_mean": float(pm.mean())})
+    return out

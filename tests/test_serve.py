@@ -153,3 +153,33 @@ def test_continuous_has_lower_tail_latency_than_plain_batching():
 def test_invalid_scheduler_parameters():
     with pytest.raises(ValueError):
         ContinuousScheduler(FakeExecutor(SimClock()), budget_bytes=0)
+
+
+class SlowPlanExecutor(FakeExecutor):
+    """Planning takes real (wall-clock) time, as building device tables does."""
+
+    def prepare(self, r):
+        import time
+        time.sleep(0.0005)
+        return super().prepare(r)
+
+
+@pytest.mark.parametrize("kind", ["continuous", "static"])
+def test_pooled_planning_keeps_order_and_completes(kind):
+    # plans built on two background threads: every request completes, bad
+    # ones are rejected, admission stays in arrival order, plan_ms recorded
+    clock = SimClock()
+    ex = SlowPlanExecutor(clock)
+    reqs = stream(120, 3000.0, seed=6)
+    reqs.append(Request(500, 1000, "zero", "bogus", None, np.linspace(2, 50, 4), arrival=0.003))
+    sched = (ContinuousScheduler(ex, budget_bytes=64 << 20, streams=2, clock=clock, planners=2) if kind == "continuous"
+             else StaticBatcher(ex, max_batch=16, window=1e-3, clock=clock, planners=2))
+    done = drive(sched, ex, clock, reqs)
+    sched.close()
+    assert len(done) == 121
+    assert {r.rid for r in done if r.error is not None} == {500}
+    ok = sorted((r for r in done if r.error is None), key=lambda r: r.arrival)
+    adm = [r.admitted for r in ok]
+    assert all(a <= b for a, b in zip(adm, adm[1:]))
+    assert all(r.plan_ms is not None and r.plan_ms >= 0.4 for r in ok)
+    assert "plan_ms_p50" in latency_summary(done)
