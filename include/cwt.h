@@ -12,7 +12,7 @@
  *
  * b = 0..N-1, with f_ext the periodic extension (CWT_PERIODIC) or the zero
  * extension (CWT_ZERO) of the signal.  Scales s_j and positions b are in
- * samples.  Two methods are offered:
+ * samples.  Four methods are offered:
  *
  *   CWT_METHOD_FFT    -- FFTCWT (Sec. 3.1, Eqs. FT_signal and
  *                        discrete_CWT_conv): one FFT of the signal, then per
@@ -168,7 +168,8 @@ extern "C" {
 typedef struct cwt_plan_s *cwt_plan_t;
 
 typedef struct {
-    int32_t kind;  /* CWT_MORLET, CWT_MEXHAT or CWT_DOG */
+    int32_t kind;  /* CWT_MORLET, CWT_MEXHAT, CWT_DOG, or a Table 2 wavelet
+                      (CWT_CBSW, CWT_GDW, CWT_CWGDW, CWT_MW) */
     double param;  /* omega0 > 0 for Morlet; integer order m >= 1 for DOG;
                       ignored for the Mexican hat */
 } cwt_wavelet;
