@@ -410,6 +410,9 @@ def main():
                 "algorithmic_bytes_per_launch": bpl,
                 "frac_of_measured_store_peak": round(achieved / peaks["store_gbs"], 4)}
     step_gbs = out_bytes / (ms * 1e-3) / 1e9
+    # the whole step beside the dominant kernel: output bytes over ms_per_step
+    roof["whole_step_output_gbs"] = round(step_gbs, 1)
+    roof["whole_step_frac"] = round(step_gbs / HBM_PEAK_GBS, 4)
     whole = {"output_bytes": out_bytes,
              "output_write_gbs": round(step_gbs, 1),
              "hbm_frac_of_spec": round(step_gbs / HBM_PEAK_GBS, 4),
