@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <type_traits>
 
 #include "../../include/cwt.h"
 #include "cwt_internal.h"
@@ -381,30 +382,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     // offsets
     const double *Sc = S + stile_idx(u0, R, r);
     auto rowp = [&](int m) { return Sc + R * (m + (m >> 4)); };  // m relative to u0, u0 % 16 == 0
-    double ar[16], ai[16], win[24], nxt[8];
-    double2 dc[8], dn[8];
+    double ar[16], ai[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         ar[u] = 0.0;
         ai[u] = 0.0;
     }
-    {
-        const double *p0 = rowp(0), *p1 = rowp(16);
+    if constexpr (CPLX) {
+        // window of S rows u0 + nb .. u0 + nb + 23, shifted by 8 rows per
+        // block of 8 taps; the next block's rows are loaded before this
+        // block's multiply-adds, the taps per tap (the complex form's
+        // register budget has no room for more)
+        double win[24], nxt[8];
+        {
+            const double *p0 = rowp(0), *p1 = rowp(16);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) win[k] = p0[k * R];
+            for (int k = 0; k < 16; ++k) win[k] = p0[k * R];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) win[16 + k] = p1[k * R];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) dc[t] = dl[t];
-    }
-    // taps in blocks of 8 (ntap is a multiple of 8); win holds S rows
-    // u0 + nb .. u0 + nb + 23; the next block's rows and taps are loaded
-    // before this block's multiply-adds
-    // (complex taps: no prefetch, which would exceed the register budget)
-    for (int nb = 0; nb < ntap; nb += 8) {
-        const bool more = nb + 8 < ntap;
-        if (CPLX) {
-            if (more) {
+            for (int k = 0; k < 8; ++k) win[16 + k] = p1[k * R];
+        }
+        for (int nb = 0; nb < ntap; nb += 8) {
+            if (nb + 8 < ntap) {
                 const double *pn = rowp(nb + 24);
 #pragma unroll
                 for (int k = 0; k < 8; ++k) nxt[k] = pn[k * R];
@@ -422,29 +420,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
             for (int k = 0; k < 16; ++k) win[k] = win[8 + k];
 #pragma unroll
             for (int k = 0; k < 8; ++k) win[16 + k] = nxt[k];
-            continue;
         }
-        if (more) {
-            const double *pn = rowp(nb + 24);
+    } else {
+        // S rows u0 + nb .. in four rotating blocks of 8 registers: the
+        // 8-tap step k (taps nb + 8k ..) reads rows nb + 8k .. nb + 8k + 22
+        // from blocks k, k + 1, k + 2 (mod 4) and loads the next step's last
+        // block into block k + 3, and the next step's taps, before its
+        // multiply-adds; nb is a multiple of 32, so every row's block is known
+        // at compile time and no register moves between steps
+        double blk[4][8], tr[2][8];
+        {
+            const double *p0 = rowp(0), *p1 = rowp(16);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) nxt[k] = pn[k * R];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) dn[t] = dl[nb + 8 + t];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                ar[u] = fma(dc[t].x, win[u + t], ar[u]);
-                if (CPLX) ai[u] = fma(dc[t].y, win[u + t], ai[u]);
+            for (int k = 0; k < 8; ++k) {
+                blk[0][k] = p0[k * R];
+                blk[1][k] = p0[(8 + k) * R];
+                blk[2][k] = p1[k * R];
             }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) tr[0][t] = dl[t].x;
         }
+        auto step = [&](int nb, auto kc) {
+            constexpr int K = decltype(kc)::value;
+            const int nbk = nb + 8 * K;
+            if (nbk >= ntap) return;
+            if (nbk + 8 < ntap) {
+                const double *pn = rowp(nbk + 24);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) win[k] = win[8 + k];
+                for (int k = 0; k < 8; ++k) blk[(K + 3) & 3][k] = pn[k * R];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) win[16 + k] = nxt[k];
+                for (int t = 0; t < 8; ++t) tr[(K + 1) & 1][t] = dl[nbk + 8 + t].x;
+            }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) dc[t] = dn[t];
+            for (int t = 0; t < 8; ++t) {
+                const double dv = tr[K & 1][t];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) ar[u] = fma(dv, blk[(K + ((u + t) >> 3)) & 3][(u + t) & 7], ar[u]);
+            }
+        };
+        for (int nb = 0; nb < ntap; nb += 32) {
+            step(nb, std::integral_constant<int, 0>{});
+            step(nb, std::integral_constant<int, 1>{});
+            step(nb, std::integral_constant<int, 2>{});
+            step(nb, std::integral_constant<int, 3>{});
+        }
     }
     const double nan = __builtin_nan("");
     OUT *row = out + (int64_t)w.j * N * (CPLX ? 2 : 1);
