@@ -33,7 +33,9 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
     using C = cplx_t<R>;
     constexpr int G = 16;       // real columns per iteration
     constexpr int GC = G / 2;   // complex columns: real columns 2z and 2z+1 share column z
-    constexpr int LD = lds_len(P);
+    // column stride = 2 (mod 16) complex elements: the sample scatter below
+    // (16 real columns x consecutive rows per wave) then hits distinct banks
+    constexpr int LD = lds_len(P) + 1;
     constexpr int E = G * P / NT;  // samples per thread per iteration
     static_assert(NT >= P && (G * P) % NT == 0, "launch shape");
     __shared__ C buf[GC * LD];
