@@ -72,3 +72,43 @@ def test_two_stream_execution_equals_serialized(torch_cuda, wavelet, param):
     plan.timing_read()
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_wps_graph_replays_match_eager(torch_cuda):
+    # the statistics epilogue (Sec. 5) under capture: count, forward, reduce,
+    # the reducing output kernels and the finalisation replay exactly
+    import ctypes
+    import paper_2302_03909_amd as cwt
+    torch = torch_cuda
+    n = 1 << 17
+    d = synth.zeldovich_field(n)
+    plan = cwt.Plan(n, "periodic", "cwgdw", synth.log_scales(2.0, 2.0 ** 12, 24), precision="fp32")
+    f = torch.as_tensor(d.astype(np.float32), device="cuda")
+    ws = torch.empty(cwt.wps_workspace_bytes(plan), dtype=torch.uint8, device="cuda")
+    ref, ref_c = cwt.exec_wps(plan, f, None, (0.0,), workspace=ws)
+    torch.cuda.synchronize()
+    wps = torch.empty_like(ref)
+    cnt = torch.empty_like(ref_c)
+    thr = (ctypes.c_double * 1)(0.0)
+    side = torch.cuda.Stream()
+
+    def call():
+        rc = cwt.load().cwt_exec_wps(plan.handle, ctypes.c_void_p(f.data_ptr()), None, thr, 1,
+                                     ctypes.c_void_p(wps.data_ptr()), ctypes.c_void_p(cnt.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(side.cuda_stream))
+        assert rc == 0, cwt.load().cwt_last_error()
+
+    with torch.cuda.stream(side):
+        call()  # creates the paired second stream of this caller stream
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        call()
+    for rep in range(3):
+        wps.fill_(float("nan"))
+        cnt.fill_(-1)
+        ws.fill_(0xFF)  # stale partial sums must not leak into a replay
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(wps, ref) and torch.equal(cnt, ref_c), f"replay {rep} differs from the eager result"
