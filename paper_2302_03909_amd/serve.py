@@ -306,17 +306,14 @@ class GpuExecutor:
             built = self.cwt.Plan(r.n, r.boundary, r.wavelet, r.scales, param=r.param, precision=r.precision)
             with self._lock:
                 plan = self.plans.get(key)
-                if plan is None:  # (another thread may have built the same shape meanwhile)
+                if plan is None:
                     plan = built
                     self.plans[key] = plan
                     self._evict()
-                else:
+                else:  # another thread built the same shape meanwhile: keep that one
                     self.plans.move_to_end(key)
-                    self._retired.append(built)
                 self._busy_plans[id(plan)] += 1
             if plan is not built:
-                with self._lock:
-                    self._retired.remove(built)
                 built.close()
         r.plan = plan
         return plan.footprint_bytes
