@@ -306,6 +306,10 @@ def main():
                          "signal (Fig. fftCWT's form), for comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-table", action="store_true")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="measurement probe instead: a 16-point FP32 DFT of 2^20 columns as the radix-16 "
+                         "butterfly on the vector ALUs against the same DFT as 16x16 matrix products on "
+                         "the matrix cores (libcwt_probe.so), points per second of each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device 3 times (a plain copy "
                          "kernel of known size, for scaling HBM byte counters)")
@@ -315,6 +319,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; the transform shards by scale "
                                    "(see the design notes), but no multi-GPU path is provided"}))
         sys.exit(2)
+
+    if args.mfma_probe:
+        return probe_dft16()
 
     import numpy as np
     import torch
@@ -451,6 +458,31 @@ def main():
             "roofline": roof, "whole_step": whole, "measured_peaks": peaks, "per_scale_error": err,
             "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
+
+
+def probe_dft16():
+    """One radix-16 stage, butterfly on the vector ALUs against matrix products."""
+    import ctypes
+    path = os.path.join(HERE, "paper_2302_03909_amd", "libcwt_probe.so")
+    if not os.path.exists(path):
+        raise SystemExit(f"{path} is not built: run paper_2302_03909_amd/build.py")
+    lib = ctypes.CDLL(path)
+    lib.cwt_probe_dft16.argtypes = [ctypes.POINTER(ctypes.c_double)] * 3
+    lib.cwt_probe_dft16.restype = ctypes.c_int
+    valu, mfma, diff = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    rc = lib.cwt_probe_dft16(ctypes.byref(valu), ctypes.byref(mfma), ctypes.byref(diff))
+    if rc != 0:
+        raise SystemExit(f"cwt_probe_dft16 failed ({rc})")
+    simd_cycles = 256 * 4 * 2.4e9    # SIMDs x clock: SIMD cycles per second at the rated clock
+    print(json.dumps({
+        "probe": "dft16: 2^20 columns of 16 complex FP32 points, 256 in-register stages per column",
+        "valu_points_per_s": valu.value, "mfma_points_per_s": mfma.value,
+        "valu_over_mfma": round(valu.value / mfma.value, 3),
+        "valu_simd_cycles_per_point": round(simd_cycles / valu.value, 4),
+        "mfma_simd_cycles_per_point": round(simd_cycles / mfma.value, 4),
+        "one_stage_max_rel_diff": diff.value}))
+    if not diff.value < 1e-5:
+        raise SystemExit("matrix-core DFT disagrees with the butterfly")
 
 
 def fft_flops(plan, kernel):

@@ -4,7 +4,8 @@
 
 Every source is compiled with -O3 --offload-arch=gfx950 and packed FP32
 instructions disabled; the objects are linked into
-paper_2302_03909_amd/libcwt.so.
+paper_2302_03909_amd/libcwt.so.  The measurement probe (csrc/probe_dft16.hip,
+no part of the transform) becomes a library of its own, libcwt_probe.so.
 """
 from __future__ import annotations
 
@@ -17,6 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcwt.so")
+PROBE_LIB = os.path.join(HERE, "libcwt_probe.so")
+PROBE_SOURCES = ["probe_dft16.hip"]
 ROOT = os.path.dirname(HERE)
 SOURCES = ["cwt_plan.cpp", "cwt_spline_plan.cpp", "cwt_fft.hip", "cwt_seg.hip", "cwt_spline.hip", "cwt_tables.hip", "cwt_wps.hip",
            "cwt_wps_b1.hip", "cwt_wps_b2.hip", "cwt_wps_b4.hip"]
@@ -39,16 +42,18 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
-    r = subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs],
-                       capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    if verbose:
-        print("built", LIB)
+    srcs = SOURCES + PROBE_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=min(len(srcs), os.cpu_count() or 4)) as ex:
+        objs = dict(zip(srcs, ex.map(_compile, srcs)))
+    for lib, names in ((LIB, SOURCES), (PROBE_LIB, PROBE_SOURCES)):
+        tmp = lib + ".tmp"
+        r = subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp,
+                            *(objs[n] for n in names)], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link of {os.path.basename(lib)} failed:\n{r.stderr}")
+        os.replace(tmp, lib)
+        if verbose:
+            print("built", lib)
     return LIB
 
 
