@@ -82,10 +82,13 @@ struct SegGroupDev {
 // group)
 struct SegUnit {
     int32_t sa, sb;
-    int64_t ka, kb;  // offsets of their spectrum samples in the spectrum table
+    // offsets of their spectrum samples in the spectrum table; a single-row
+    // unit (sb < 0) of a shifted group has kb = its complex samples with the
+    // shift phase w_L^{-m dsh} folded in
+    int64_t ka, kb;
     // single-row units: the work item of first column r0 computes columns
     // r0 - dsh .. (modulo the segment), so that the row's store runs start on
-    // 128-byte lines; its spectrum samples take the factor w_L^{-m dsh}
+    // 128-byte lines
     int32_t dsh, pad;
 };
 
@@ -182,11 +185,13 @@ struct SpecWavelet {
     double w0, cmor, kappa, gnorm, cn, ulo, uhi;
 };
 // count entries at tab[off..]: Psi_s(2 pi m / L) / L for m = m0 + e (full:
-// the signed bin of e in [0, L)); the job's workgroups start at block0
+// the signed bin of e in [0, L)); shift >= 0: count complex entries (re, im
+// at off + 2e, off + 2e + 1), each sample times w_L^{-m shift}.  The job's
+// workgroups start at block0.
 struct SpecJob {
     int64_t off, m0, count, L, block0;
     double s;
-    int32_t full, pad;
+    int32_t full, shift;
 };
 hipError_t launch_spectrum_tables(const SpecWavelet &w, const SpecJob *jobs, int njobs, int64_t blocks, void *tab,
                                   bool fp64, hipStream_t st);

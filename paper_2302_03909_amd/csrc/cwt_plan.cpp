@@ -624,16 +624,19 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
     // counts the table's elements
     std::vector<SpecJob> jobs;
     int64_t tab_n = 0;
-    auto add_job = [&](double s, int64_t L, int64_t m0, int64_t count, bool full) {
+    // shift >= 0: complex entries, the samples times w_L^{-m shift}
+    auto add_job = [&](double s, int64_t L, int64_t m0, int64_t count, bool full, int32_t shift = -1) {
         SpecJob jb{};
+        if (shift >= 0) tab_n += tab_n & 1;  // complex entries start on an even element
         jb.off = tab_n;
         jb.m0 = m0;
         jb.count = count;
         jb.L = L;
         jb.s = s;
         jb.full = full ? 1 : 0;
+        jb.shift = shift;
         jobs.push_back(jb);
-        tab_n += count;
+        tab_n += shift >= 0 ? 2 * count : count;
         return jb.off;
     };
     TableBuilder tb;
@@ -742,9 +745,27 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         while (nchunk * 4 <= iters_total && nchunk * 2 <= 256 && g.nseg * nchunk < 2048) nchunk *= 2;
         g.nchunk = (int32_t)nchunk;
         g.iters = (int32_t)(iters_total / nchunk);
-        // spectrum samples of each scale on the group band
-        std::vector<int64_t> koff(js.size());
-        for (size_t u = 0; u < js.size(); ++u) koff[u] = add_job(p.scales[js[u]], g.L, g.klo, g.B, false);
+        // column shift of a single-row unit: its row starts dsh elements past
+        // a line boundary (for an output aligned to 128 bytes; the result
+        // does not depend on it).  Segment starts and first columns are
+        // multiples of the line length already.
+        const bool scale_pairs = p.pair_real && !g.colpair;
+        std::vector<int32_t> dsh(js.size(), 0);
+        if (!scale_pairs)
+            for (size_t u = 0; u < js.size(); ++u) {
+                dsh[u] = (int32_t)(((int64_t)js[u] * p.N) % line_e);
+                if (dsh[u] != 0) g.cshift = 1;
+            }
+        if (g.colodd) g.cshift = 1;  // the odd-length path is a shifted one
+        // spectrum samples of each scale on the group band; a shifted group
+        // also gets them as complex values with the unit's shift phase
+        // w_L^{-m dsh} folded in (the statistics variants, which never shift,
+        // read the real ones)
+        std::vector<int64_t> koff(js.size()), kcoff(js.size(), 0);
+        for (size_t u = 0; u < js.size(); ++u) {
+            koff[u] = add_job(p.scales[js[u]], g.L, g.klo, g.B, false);
+            if (g.cshift) kcoff[u] = add_job(p.scales[js[u]], g.L, g.klo, g.B, false, dsh[u]);
+        }
         // column factors, g < 16: w_L^{m g}, or w_L^{2 m g} (1 + i w_L^m) for
         // the column pair (2g, 2g + 1)
         {
@@ -767,7 +788,6 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         // output units: single scales (complex output, column pairs) or
         // scale pairs (other real output)
         g.unit0 = (int32_t)p.units.size();
-        const bool scale_pairs = p.pair_real && !g.colpair;
         for (size_t u = 0; u < js.size(); u += scale_pairs ? 2 : 1) {
             SegUnit un{};
             un.sa = js[u];
@@ -777,20 +797,12 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
                 un.kb = koff[u + 1];
             } else {
                 un.sb = -1;
-                un.kb = koff[u];
+                un.kb = g.cshift ? kcoff[u] : koff[u];
             }
-            // column shift of a single-row unit: its row starts dsh elements
-            // past a line boundary (for an output aligned to 128 bytes; the
-            // result does not depend on it).  Segment starts and first
-            // columns are multiples of the line length already.
-            if (p.cplx_out || g.colpair) {
-                un.dsh = (int32_t)(((int64_t)un.sa * p.N) % line_e);
-                if (un.dsh != 0) g.cshift = 1;
-            }
+            un.dsh = dsh[u];
             p.units.push_back(un);
         }
         g.nunits = (int32_t)p.units.size() - g.unit0;
-        if (g.colodd) g.cshift = 1;  // the odd-length path is a shifted one
         {
             const int64_t need = (scale_pairs ? 2 : 1) * (int64_t)g.nunits;
             if (need * g.B > std::max<int64_t>(2 * g.P, kSegKlsBytes / (fp64 ? 8 : 4)))

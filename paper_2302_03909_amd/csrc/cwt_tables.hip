@@ -12,6 +12,8 @@
 //   DOG(m):     Gamma(m + 1/2)^{-1/2} sqrt(2 pi) u^m e^{-u^2/2}
 //   GDW:        8 sqrt(pi) C_N u^2 e^{-u^2}                       (Table 2)
 //   CW-GDW:     sqrt(2 pi) C_N u (u cosh u - sinh u) e^{-u^2/2}   (Table 2)
+// A shifted job (a band unit whose output columns move by d) stores each
+// entry as a complex value, times w_L^{-m d}.
 #include <hip/hip_runtime.h>
 
 #include "../../include/cwt.h"
@@ -55,7 +57,18 @@ __global__ __launch_bounds__(256) void spectrum_kernel(SpecWavelet w, const Spec
     const int64_t q0 = (int64_t)ceil((w.ulo / jb.s - om) / tp), q1 = (int64_t)floor((w.uhi / jb.s - om) / tp);
     double acc = 0.0;
     for (int64_t q = q0; q <= q1; ++q) acc += spec_amp(w, jb.s * (om + tp * (double)q));
-    tab[jb.off + e] = (T)(acc / (double)jb.L);
+    const double v = acc / (double)jb.L;
+    if (jb.shift < 0) {
+        tab[jb.off + e] = (T)v;
+        return;
+    }
+    // times w_L^{-m shift} = e^{-2 pi i x / L}, x = m shift mod L (exact integer)
+    int64_t x = (m % jb.L) * (int64_t)jb.shift % jb.L;
+    if (x < 0) x += jb.L;
+    double sn, cs;
+    sincospi(2.0 * (double)x / (double)jb.L, &sn, &cs);
+    tab[jb.off + 2 * e] = (T)(v * cs);
+    tab[jb.off + 2 * e + 1] = (T)(-v * sn);
 }
 
 hipError_t launch_spectrum_tables(const SpecWavelet &w, const SpecJob *jobs, int njobs, int64_t blocks, void *tab,

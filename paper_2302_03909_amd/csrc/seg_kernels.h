@@ -263,9 +263,9 @@ constexpr int seg_kls_elems(int rbytes, int P) {
 // shifted: for that unit the work item computes columns r0 - dsh .. instead
 // (dsh = the row's offset in its line), so its runs again start on lines.
 // Since W[t] = sum_k Y[k] w_L^{k t} for any t modulo L, the shift only
-// multiplies the unit's spectrum samples by w_L^{-k dsh} (applied in
-// registers, so the staged samples stay real), and column r < 0 of row p is
-// the output t = r + Q p (+ L when negative).
+// multiplies the unit's spectrum samples by w_L^{-k dsh} (folded into complex
+// samples at plan time, staged a chunk of units at a time), and column r < 0
+// of row p is the output t = r + Q p (+ L when negative).
 
 template <typename R, int P, int NT, bool PAIR, bool CPLX, int RED = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !PAIR ? 3 : 2))) void seg_inverse_kernel(
@@ -279,7 +279,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     static_assert(NT == P, "one pass-0 butterfly per thread");
     __shared__ C buf[G * LD];
     __shared__ C twl[twl_len(P)];
-    __shared__ R kls[KLS];  // spectrum samples of the group's units (and pair partners)
+    // spectrum samples of the group's units (and pair partners); complex
+    // samples of shifted units in chunks of kls_chunk units
+    __shared__ __align__(16) R kls[KLS];
     __shared__ double red[RED ? (NT / 64) * 2 * kWpsMaxBins : 1];  // statistics: per-wave sums
     const Resolved rv = resolve(a);
     const KeyDesc *kd = &rv.kd;
@@ -331,10 +333,33 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
         xs[tid] = to_c<C>(cmul(X[(int64_t)w.seg * B + tid], w23(whi, wlo, ((mm * r0) & (L - 1)) << sh)));
     }
     load_twl<C, P, NT>(twl, static_cast<const C *>(kd->twl));
+    const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, 0x7ffffff0u);
+    // shifted units (uniform): their complex samples, with the shift phase
+    // folded in, are staged kls_chunk units at a time (two reals per bin)
+    const bool sh_path = !RED && (shf || codd);
+    const int kls_chunk = sh_path ? KLS / (2 * B) : nunits;
+    auto stage_complex = [&](int ub, int ue) {
+        C *klc = reinterpret_cast<C *>(kls);
+        if (tid < B) {
+            for (int u0 = ub; u0 < ue; u0 += 8) {
+                C kc[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int u = u0 + j < ue ? u0 + j : ue - 1;
+                    const SegUnit su = cload(units + gd.unit0 + u);
+                    kc[j] = bload((const C *)nullptr, kr, (uint32_t)((uni(su.kb) + 2 * tid) * (int64_t)sizeof(R)));
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (u0 + j < ue) klc[(u0 + j - ub) * B + tid] = kc[j];
+            }
+        }
+    };
     // spectrum samples of every unit of the group (and pair partners),
     // staged in LDS once, eight units per batch of loads
-    if (tid < B) {
-        const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, 0x7ffffff0u);
+    if (sh_path) {
+        stage_complex(0, kls_chunk < nunits ? kls_chunk : nunits);
+    } else if (tid < B) {
         for (int u0 = 0; u0 < nunits; u0 += 8) {
             R ka[8], kb[8];
 #pragma unroll
@@ -400,24 +425,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
         constexpr bool CP = decltype(cp_const)::value;
         constexpr bool SH = decltype(sh_const)::value;
         constexpr bool ODD = decltype(odd_const)::value;
-        // shifted units: the phase w_L^{-m dsh} of the thread's bins
-        // m_r = klo + fro[r], from w_L^{-m_0 dsh} (m_0 = klo + f0, looked up one
-        // unit ahead) by steps w_L^{-NB dsh}, and w_L^{(P - NB) dsh} at the step
-        // where fro wraps past P
-        const int64_t m0 = gd.klo + f0;
-        const int rw = (P - f0 + NB - 1) / NB;  // first r with f0 + r NB >= P
-        // the three phases of unit uu (first bin, step, wrapped step)
-        struct Phases {
-            C first, step, wrap;
-        };
-        auto phases = [&](int uu) {
-            const int d = __builtin_amdgcn_readfirstlane(cload(units + gd.unit0 + uu).dsh);
-            return Phases{to_c<C>(w23(whi, wlo, ((-m0 * d) & (L - 1)) << sh)),
-                          to_c<C>(w23(whi, wlo, ((-(int64_t)NB * d) & (L - 1)) << sh)),
-                          to_c<C>(w23(whi, wlo, (((int64_t)(P - NB) * d) & (L - 1)) << sh))};
-        };
-        Phases ph_next{};
-        if constexpr (SH) ph_next = phases(0);
         for (int u = 0; u < nunits; ++u) {
             // unit fields are uniform; say so, so that the store descriptors
             // live in scalar registers (no waterfall loop around the stores)
@@ -427,16 +434,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             const int dl = SH ? __builtin_amdgcn_readfirstlane(su.dsh) : 0;
             C v[16];
             if constexpr (SH) {
-                // this unit's phases, looked up during the previous unit
-                const Phases cur = ph_next;
-                if (u + 1 < nunits) ph_next = phases(u + 1);
-                C ph = cur.first;
-                const C step = cur.step, wrap = cur.wrap;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    v[r] = cmul(xg[r], cscale(ph, kls[u * B + fro[r]]));
-                    ph = cmul(ph, r + 1 == rw ? wrap : step);
+                // the next chunk of complex samples (every read of the
+                // previous chunk ended before the last unit's final barrier)
+                const int uk = u % kls_chunk;
+                if (u > 0 && uk == 0) {
+                    stage_complex(u, u + kls_chunk < nunits ? u + kls_chunk : nunits);
+                    lds_barrier();
                 }
+                // samples times w_L^{-m dsh}, m = klo + fro[r]: the shift of
+                // the unit's columns by dsh
+                const C *klc = reinterpret_cast<const C *>(kls) + uk * B;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[r] = cmul(xg[r], klc[fro[r]]);
             }
             if constexpr (!SH) {
 #pragma unroll
