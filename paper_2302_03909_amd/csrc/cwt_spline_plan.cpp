@@ -210,15 +210,20 @@ static std::vector<cd> a19_coeffs(const Wavelet &w, double h, int K, double chi)
 }
 
 // Work items of the tap-sum launch for scale j (knot spacing delta, ntap
-// taps): tiles of R <= 16 columns (consecutive positions) x I = 16 floor(256 /
+// taps): tiles of R <= 32 columns (consecutive positions) x I = 16 floor(256 /
 // R) rows (positions delta apart); the S tile holds R (I + ntap) values plus
-// one spare row per 16, and the taps follow it in LDS.
+// one spare row per 16, and the taps follow it in LDS.  Wide tiles measured
+// best although they repeat more halo rows per output: R = 32 against 16
+// took the tap kernel 0.36 against 0.39 ms (Mexican hat, 53 taps) and 1.10
+// against 1.19 ms (Morlet, 155 taps) at N = 2^20, 64 scales; R = 8 and 4
+// were slower (0.45, 0.64 ms Mexican hat).  Each row's R outputs are one
+// store run, and each thread's H loads are R-lane runs.
 static void add_tiles(Plan &p, int j, SplineScaleDev &sc, int64_t delta, int ntap) {
     auto tile_fits = [&](int r) {
         const int rows_s = 16 * (256 / r) + ntap;
         return r * (rows_s + rows_s / 16 + 1) + 2 * ntap <= 8192;  // 64 KiB of LDS
     };
-    int rmax = 16;
+    int rmax = 32;
     while (rmax > 1 && !tile_fits(rmax)) rmax /= 2;
     if (!tile_fits(rmax)) fail(CWT_EUNSUPPORTED, "spline method: wavelet support too long for the tap tile");
     const int64_t nck = (delta + rmax - 1) / rmax;
