@@ -582,7 +582,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const KeyDesc *kd = &rv.kd;
     const R *__restrict__ f = static_cast<const R *>(rv.bi.f);
     R *__restrict__ out = static_cast<R *>(rv.bi.out);
-    const int64_t N = kd->N, Tg = kd->Tg, V = kd->V, nseg = kd->nseg;
+    const int64_t N = kd->N, Tg = kd->Tg, V = kd->V;
     const int periodic = __builtin_amdgcn_readfirstlane(kd->periodic);
     const int nscale = kd->nscale, cph = kd->cph;
     const int32_t *__restrict__ scale_ids = kd->scale_ids;
