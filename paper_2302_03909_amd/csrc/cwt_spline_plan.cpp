@@ -214,10 +214,10 @@ static std::vector<cd> a19_coeffs(const Wavelet &w, double h, int K, double chi)
 // R) rows (positions delta apart); the S tile holds R (I + ntap) values plus
 // one spare row per 16, and the taps follow it in LDS.  Wide tiles measured
 // best although they repeat more halo rows per output: R = 32 against 16
-// took the tap kernel 0.36 against 0.39 ms (Mexican hat, 53 taps) and 1.10
-// against 1.19 ms (Morlet, 155 taps) at N = 2^20, 64 scales; R = 8 and 4
-// were slower (0.45, 0.64 ms Mexican hat).  Each row's R outputs are one
-// store run, and each thread's H loads are R-lane runs.
+// took the tap kernel 0.36 against 0.39 ms (Mexican hat, 53 taps, N = 2^20,
+// 64 scales); R = 8 and 4 were slower (0.45, 0.64 ms).  Each row's R outputs
+// are one store run, and each thread's H loads are R-lane runs.  (Morlet's
+// 155-tap tiles do not fit 32 columns and stay at 16.)
 static void add_tiles(Plan &p, int j, SplineScaleDev &sc, int64_t delta, int ntap) {
     auto tile_fits = [&](int r) {
         const int rows_s = 16 * (256 / r) + ntap;
