@@ -42,13 +42,14 @@ struct ColumnDesc {
     int64_t taba, tabb;  // offsets of the spectrum samples of sa / sb
 };
 
-// A group of scales transformed with the same segment length L = 2^lgL.
+// A group of scales transformed with the same segment length: L = 2^lgL
+// (LOCAL), or L = cL 2^lgL with cL odd (BAND).
 //   LOCAL: full L-point spectrum, fused kernel (NCOL segments per workgroup)
 //   BAND:  spectrum needed on [klo, klo + B) only, B <= P, L = P * Q
 struct SegGroup {
     enum Kind { LOCAL = 0, BAND = 1 };
     int32_t kind = LOCAL;
-    int32_t L = 0, lgL = 0, P = 0;
+    int32_t L = 0, lgL = 0, P = 0, cL = 1;
     int64_t Tg = 0, V = 0, nseg = 0;
     int64_t klo = 0;
     int32_t B = 0, nchunk = 1, iters = 1;
@@ -68,13 +69,16 @@ struct SegGroup {
 
 // device copy of a BAND group's parameters
 struct SegGroupDev {
-    int32_t lgL, B, nchunk, iters;
+    int32_t lgL, B, nchunk, iters;  // lgL: k of the segment length L = c 2^k
     int32_t unit0, nunits;
     int32_t colpair, cshift;
     int32_t colodd, inv0;   // inv0: index of the group's first inverse work item
     int64_t V, Tg, klo, nseg;
     int64_t xp_off, x_off;  // workspace byte offsets of the partial and reduced band spectra
     int64_t gtw_off;        // byte offset of the column factors in the twiddle allocation
+    int64_t L, Q;           // segment length and column count L / P
+    int64_t wsm_off;        // c > 1: byte offset of w_L^z, z < c, in the twiddle allocation
+    int32_t cL, pad2;       // odd factor c of L
 };
 
 // one output unit of a BAND group: a scale, or a pair of real-wavelet scales

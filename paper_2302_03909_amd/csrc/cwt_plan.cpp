@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <limits>
 #include <map>
 #include <tuple>
 #include <mutex>
@@ -252,6 +253,15 @@ static std::complex<double> w23_at(int64_t x, int lg) {
     const std::complex<double> a(t.first[2 * (y >> 11)], t.first[2 * (y >> 11) + 1]);
     const std::complex<double> b(t.second[2 * (y & 2047)], t.second[2 * (y & 2047) + 1]);
     return a * b;
+}
+// e^{+2 pi i x / L} for a segment length L = c 2^lg (FP64; the split tables
+// when c = 1, else from long double)
+static std::complex<double> wL_at(int64_t x, int64_t L, int c, int lg) {
+    if (c == 1) return w23_at(x, lg);
+    int64_t r = x % L;
+    if (r < 0) r += L;
+    const long double a = 2.0L * M_PIl * (long double)r / (long double)L;
+    return {(double)std::cos(a), (double)std::sin(a)};
 }
 static void push_w23(TableBuilder &tb, int64_t &hi_off, int64_t &lo_off) {
     const auto &t = w23_tables();
@@ -718,6 +728,56 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         g.B = (int32_t)(khi - klo + 1);
         g.P = (int32_t)std::max<int64_t>(64, next_pow2(g.B));
         for (int j : js) g.Tg = std::max(g.Tg, p.T[j]);
+        // Segment length: of L = 2^lg and the shorter L = c 2^k (c odd, at most
+        // 15, 2^k >= 32 P so that Q = L / P is a multiple of 32) whose band
+        // still fits P, the one that computes the fewest positions, nseg L.
+        // The power of two set by the halo (about 8 T) can leave the last
+        // segment, or a single segment holding the whole signal, mostly beyond
+        // the signal's end.
+        {
+            auto band_at = [&](int64_t Lc, int64_t &lo, int64_t &hi) {
+                lo = std::numeric_limits<int64_t>::max();
+                hi = std::numeric_limits<int64_t>::min();
+                for (int j : js) {
+                    const double s = p.scales[j];
+                    lo = std::min(lo, (int64_t)std::floor(Lc * ulo / (2.0 * M_PI * s)) - 1);
+                    hi = std::max(hi, (int64_t)std::ceil(Lc * uhi / (2.0 * M_PI * s)) + 1);
+                }
+            };
+            auto cost_of = [&](int64_t Lc) {
+                if (p.boundary == CWT_ZERO && Lc >= p.N + g.Tg + 1) return Lc;  // single segment
+                const int64_t V = Lc - 2 * align_halo(g.Tg, p.pair_real && !fp64 ? 32 : 16);
+                return V > 0 ? (p.N + V - 1) / V * Lc : std::numeric_limits<int64_t>::max();
+            };
+            int64_t best = cost_of(g.L), bestL = g.L;
+            int bestc = 1, bestk = g.lgL;
+            for (int c = 3; c <= 15; c += 2)
+                for (int k = 0; (int64_t(c) << k) < g.L; ++k) {
+                    const int64_t Lc = int64_t(c) << k;
+                    if ((int64_t(1) << k) < 32 * (int64_t)g.P) continue;
+                    int64_t lo, hi;
+                    band_at(Lc, lo, hi);
+                    if (hi - lo + 1 > g.P) continue;
+                    const int64_t cst = cost_of(Lc);
+                    if (cst < best) {
+                        best = cst;
+                        bestL = Lc;
+                        bestc = c;
+                        bestk = k;
+                    }
+                }
+            if (bestc != 1) {
+                int64_t lo, hi;
+                band_at(bestL, lo, hi);
+                g.L = (int32_t)bestL;
+                g.cL = bestc;
+                g.lgL = bestk;
+                klo = lo;
+                khi = hi;
+                g.klo = lo;
+                g.B = (int32_t)(hi - lo + 1);
+            }
+        }
         const int64_t Q = g.L / g.P;
         const int64_t iters_total = Q / 16;
         // Real FP32 output with rows of at least 32 columns: the inverse packs
@@ -743,6 +803,7 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         // often on another XCD with its own L2.
         int64_t nchunk = 1;
         while (nchunk * 4 <= iters_total && nchunk * 2 <= 256 && g.nseg * nchunk < 2048) nchunk *= 2;
+        while (iters_total % nchunk != 0) --nchunk;  // whole chunks (Q / 16 need not be a power of two)
         g.nchunk = (int32_t)nchunk;
         g.iters = (int32_t)(iters_total / nchunk);
         // column shift of a single-row unit: its row starts dsh elements past
@@ -773,9 +834,9 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
             for (int gg = 0; gg < 16; ++gg)
                 for (int k = 0; k < g.B; ++k) {
                     const std::complex<double> v =
-                        g.colpair ? w23_at((g.klo + k) * 2 * gg, g.lgL) *
-                                        (1.0 + std::complex<double>(0.0, 1.0) * w23_at(g.klo + k, g.lgL))
-                                  : w23_at((g.klo + k) * gg, g.lgL);
+                        g.colpair ? wL_at((g.klo + k) * 2 * gg, g.L, g.cL, g.lgL) *
+                                        (1.0 + std::complex<double>(0.0, 1.0) * wL_at(g.klo + k, g.L, g.cL, g.lgL))
+                                  : wL_at((g.klo + k) * gg, g.L, g.cL, g.lgL);
                     gt[2 * ((size_t)gg * g.B + k)] = v.real();
                     gt[2 * ((size_t)gg * g.B + k) + 1] = v.imag();
                 }
@@ -840,6 +901,20 @@ static void build_seg_plan(Plan &p, const Wavelet &w) {
         gd.xp_off = (int64_t)g.ws_xp_off;
         gd.x_off = (int64_t)g.ws_x_off;
         gd.gtw_off = g.gtw_off;
+        gd.L = g.L;
+        gd.Q = g.L / g.P;
+        gd.cL = g.cL;
+        if (g.cL > 1) {
+            // w_L^z, z < c: with w_L^{c y + z} = w_{2^k}^y w_L^z the kernels
+            // take the rest from the 2^23 split tables
+            std::vector<double> sm(2 * (size_t)g.cL);
+            for (int z = 0; z < g.cL; ++z) {
+                const std::complex<double> v = wL_at(z, g.L, g.cL, g.lgL);
+                sm[2 * (size_t)z] = v.real();
+                sm[2 * (size_t)z + 1] = v.imag();
+            }
+            gd.wsm_off = tb.add(sm.data(), sm.size() * sizeof(double));
+        }
         sl->gdev.push_back(gd);
         sl->groups.push_back((int32_t)p.segs.size());
         sl->out_rows += (double)js.size();

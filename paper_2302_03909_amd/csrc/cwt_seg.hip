@@ -50,8 +50,9 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
     load_twl<C, P, NT>(twl, static_cast<const C *>(kd->twl));
     const SegWork w = cload(kd->work + rv.local);
     const SegGroupDev gd = cload(kd->groups + w.g);
-    const int64_t L = int64_t(1) << gd.lgL, Q = L >> log2_exact(P);
-    const int sh = 23 - gd.lgL;
+    const int64_t L = gd.L, Q = gd.Q;
+    const int cL = __builtin_amdgcn_readfirstlane(gd.cL), kL = __builtin_amdgcn_readfirstlane(gd.lgL);
+    const double2 *__restrict__ wsm = reinterpret_cast<const double2 *>(kd->twbase + gd.wsm_off);
     const int tid = threadIdx.x;
     const int B = gd.B;
     // bins of this thread: step = w_L^{-m}, step2 = w_L^{-2m}, w14 =
@@ -62,18 +63,18 @@ __global__ __launch_bounds__(NT) void seg_forward_kernel(const BatchArgs a) {
     double cc2 = 0.0;  // 2 cos(2 theta), theta = 2 pi m / L
     int kap = 0, kam = 0;
     if (tid < B) {
-        int64_t mm = (gd.klo + tid) & (L - 1);
-        kap = (int)(mm & (P - 1));
+        const int64_t mm = mod_seg(gd.klo + tid, cL, L);
+        kap = (int)(mm & (P - 1));  // P divides L
         kam = (P - kap) & (P - 1);
-        double2 s1 = w23(whi, wlo, mm << sh);
+        double2 s1 = w_seg(whi, wlo, wsm, cL, kL, mm);
         step = make_double2(s1.x, -s1.y);
         step2 = cmul(step, step);
         cc2 = 2.0 * step2.x;
-        double2 s14 = w23(whi, wlo, ((14 * mm) & (L - 1)) << sh);
+        double2 s14 = w_seg(whi, wlo, wsm, cL, kL, mod_seg(14 * mm, cL, L));
         w14 = make_double2(s14.x, -s14.y);
-        double2 s16 = w23(whi, wlo, ((16 * mm) & (L - 1)) << sh);
+        double2 s16 = w_seg(whi, wlo, wsm, cL, kL, mod_seg(16 * mm, cL, L));
         w16 = make_double2(s16.x, -s16.y);
-        double2 b = w23(whi, wlo, ((q0 * mm) & (L - 1)) << sh);
+        double2 b = w_seg(whi, wlo, wsm, cL, kL, mod_seg(q0 * mm, cL, L));
         base0 = make_double2(b.x, -b.y);
         base = base0;
     }

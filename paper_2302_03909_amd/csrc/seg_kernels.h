@@ -26,6 +26,21 @@ __device__ __forceinline__ double2 w23(const double2 *__restrict__ hi, const dou
     return cmul(hi[x >> 11], lo[x & 2047]);
 }
 
+// w_L^x, x in [0, L), for a segment length L = c 2^k: w_{2^k}^y w_L^z with
+// x = c y + z (wsm[z] = w_L^z, read only when c > 1)
+__device__ __forceinline__ double2 w_seg(const double2 *__restrict__ hi, const double2 *__restrict__ lo,
+                                         const double2 *__restrict__ wsm, int c, int k, int64_t x) {
+    if (c == 1) return w23(hi, lo, x << (23 - k));
+    const uint32_t y = (uint32_t)x / (uint32_t)c, z = (uint32_t)x - y * (uint32_t)c;
+    return cmul(w23(hi, lo, (int64_t)y << (23 - k)), wsm[z]);
+}
+// v modulo the segment length L = c 2^k (either sign of v)
+__device__ __forceinline__ int64_t mod_seg(int64_t v, int c, int64_t L) {
+    if (c == 1) return v & (L - 1);
+    const int64_t r = v % L;
+    return r < 0 ? r + L : r;
+}
+
 template <typename C> __device__ __forceinline__ C mul_i_pow(C a, int q) {
     switch (q & 3) {
         case 1: return mk<C>(-a.y, a.x);
@@ -299,8 +314,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const bool cp = PAIR && gd.colpair;              // column pairs of one scale (uniform)
     const bool shf = gd.cshift && (CPLX || cp);      // shifted single-row units (uniform)
     const bool codd = cp && gd.colodd;               // column pairs of an odd-length signal (uniform)
-    const int64_t L = int64_t(1) << gd.lgL, Q = L >> log2_exact(P);
-    const int sh = 23 - gd.lgL;
+    const int64_t L = gd.L, Q = gd.Q;
+    const int cL = __builtin_amdgcn_readfirstlane(gd.cL), kL = __builtin_amdgcn_readfirstlane(gd.lgL);
+    const double2 *__restrict__ wsm = reinterpret_cast<const double2 *>(twbase + gd.wsm_off);
     const int tid = threadIdx.x;
     const int B = gd.B;
     const int64_t r0 = w.idx;
@@ -328,9 +344,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     // band spectrum of the segment times w_L^{m r0}, staged in LDS (reuses buf)
     C *xs = buf;
     if (tid < B) {
-        int64_t mm = (gd.klo + tid) & (L - 1);
+        const int64_t mm = mod_seg(gd.klo + tid, cL, L);
         const double2 *X = reinterpret_cast<const double2 *>(ws + gd.x_off);
-        xs[tid] = to_c<C>(cmul(X[(int64_t)w.seg * B + tid], w23(whi, wlo, ((mm * r0) & (L - 1)) << sh)));
+        xs[tid] = to_c<C>(cmul(X[(int64_t)w.seg * B + tid], w_seg(whi, wlo, wsm, cL, kL, mod_seg(mm * r0, cL, L))));
     }
     load_twl<C, P, NT>(twl, static_cast<const C *>(kd->twl));
     const __amdgpu_buffer_rsrc_t kr = make_rsrc(ktab, 0x7ffffff0u);
