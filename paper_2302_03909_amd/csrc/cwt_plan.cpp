@@ -543,7 +543,7 @@ static void build_fft_plan(Plan &p, const Wavelet &w, int64_t fft_len_opt) {
 // (T its half-support, at least 64 samples).  If the spectrum of its wavelet
 // at that length spans a sixteenth of L or more, the scale joins a LOCAL
 // group (full-spectrum fused kernel); otherwise a BAND group keyed by (L, P)
-// with P >= the band width.
+// with P >= the band width, whose length may then shrink to c 2^k (c odd).
 // Halo of a segment group, rounded up to 16 samples: the kept outputs of
 // every segment then start on a 16-sample boundary (V = L - 2 Tg is a
 // multiple of 16 too), so the 16-column output runs of the kernels fill whole

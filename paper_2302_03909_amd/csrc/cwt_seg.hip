@@ -2,9 +2,10 @@
 //
 // The product W = IDFT(DFT(f) * conj(Psi_s)) of Sec. 3.1 (Eq.
 // discrete_CWT_conv, with the aliased spectrum of the sampled wavelet) is
-// evaluated segment by segment: a segment of L = 2^l samples starting Tg
-// before its first output yields V = L - 2 Tg valid outputs, because the
-// wavelet at every scale of the group is negligible beyond Tg samples.
+// evaluated segment by segment: a segment of L samples starting Tg before
+// its first output yields V = L - 2 Tg valid outputs, because the wavelet at
+// every scale of the group is negligible beyond Tg samples (L = 2^l for the
+// small scales, L = c 2^l with c odd for the larger ones).
 //
 // Small scales (wide spectrum relative to L): local2_kernel takes the full
 // L-point FFT of NCOL segments per workgroup, keeps the spectra in registers

@@ -252,3 +252,31 @@ def test_wps_workspace_and_rejections_host_only():
     wp = cwt.Plan(4096, "periodic", "morlet", [3.0, 30.0], fft_mode="whole", host_only=True)
     assert cwt.wps_workspace_bytes(wp) == 0
     assert lib.cwt_exec_wps(None, None, None, thr, 1, None, None, None, None) == cwt.CWT_EINVAL
+
+
+def test_band_lengths_never_compute_more_positions_than_the_power_of_two():
+    # a band group's length is c 2^k (c odd, at most 15; 2^k >= 32 P when
+    # c > 1), chosen only where nseg L is below the power of two's count
+    scales = np.geomspace(2, 2 ** 16, 128)
+    seen_odd = False
+    for n, bc, wav, par in [(1 << 22, "zero", "morlet", 6.0), ((1 << 22) - 3, "periodic", "dog", 2.0),
+                            (123457, "zero", "morlet", 6.0), (20000, "zero", "dog", 2.0)]:
+        p = cwt.Plan(n, bc, wav, scales[scales < n / 4], param=par, precision="fp32", host_only=True)
+        for ln in p.describe().splitlines():
+            if not ln.startswith("band"):
+                continue
+            kv = {k: int(v) for k, v in (t.split("=") for t in ln.split()[1:] if "=" in t)}
+            L, P, Tg, V, nseg = kv["L"], kv["P"], kv["Tg"], kv["V"], kv["nseg"]
+            c = L // (L & -L)
+            assert c % 2 == 1 and c <= 15
+            assert nseg * V >= n > (nseg - 1) * V
+            if c == 1:
+                continue
+            seen_odd = True
+            assert (L // c) >= 32 * P and (L // P) % 32 == 0
+            L2 = 1 << (L - 1).bit_length()
+            if nseg == 1 and Tg == 0:
+                continue  # single zero-boundary segment: the power of two is longer
+            nseg2 = -(-n // (L2 - 2 * Tg))
+            assert nseg * L <= nseg2 * L2
+    assert seen_odd

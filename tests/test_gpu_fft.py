@@ -264,3 +264,54 @@ def test_full_size_fp32_rows_off_the_line_grid_sampled(torch_cuda):
     assert "shift=1" in plan.describe()
     print(f"fp32 N={n} dog2 max err", err.max())
     assert err.max() <= 1e-5
+
+
+def _band_groups(plan):
+    out = []
+    for ln in plan.describe().splitlines():
+        if ln.startswith("band"):
+            kv = dict(t.split("=") for t in ln.split()[1:] if "=" in t)
+            out.append({k: int(v) for k, v in kv.items() if k in ("L", "P", "B", "Tg", "V", "nseg")})
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,bc,wav,par,scales", [
+    (20000, "zero", "dog", 2.0, [100.0, 900.0]),
+    (6000, "zero", "mexhat", None, [50.0, 200.0, 500.0]),
+    (30001, "zero", "morlet", 6.0, [64.0, 1500.0]),
+    (12345, "periodic", "dog", 2.0, [30.0, 800.0]),
+])
+def test_band_lengths_off_powers_of_two_all_outputs(torch_cuda, precision, n, bc, wav, par, scales):
+    # single segments of c 2^k samples (c odd > 1): every output against the direct sum
+    import paper_2302_03909_amd as cwt
+    p = cwt.Plan(n, bc, wav, scales, param=par, precision=precision, host_only=True)
+    assert any(g["L"] & (g["L"] - 1) for g in _band_groups(p))
+    f = synth.lognormal_field(n) if bc == "zero" else synth.tones_noise(n)
+    check_full(torch_cuda, f, bc, wav, par, scales, precision)
+
+
+@pytest.mark.parametrize("n,bc,scales", [(300000, "zero", [3000.0, 4500.0]), (250000, "periodic", [3000.0, 4500.0])])
+def test_band_lengths_off_powers_of_two_segment_edges(torch_cuda, n, bc, scales):
+    # several segments of c 2^k samples: the outputs on both sides of every
+    # segment boundary, the row ends and random positions against the direct sum
+    import paper_2302_03909_amd as cwt
+    import torch as T
+    f = synth.lognormal_field(n) if bc == "zero" else synth.tones_noise(n)
+    for precision in ("fp64", "fp32"):
+        print(f"case N={n} bc={bc} morlet S={len(scales)} {precision}", flush=True)
+        plan, w = gpu_cwt(torch_cuda, f, bc, "morlet", 6.0, scales, precision)
+        groups = _band_groups(plan)
+        odd = [g for g in groups if g["L"] & (g["L"] - 1) and g["nseg"] >= 2]
+        assert odd
+        edges = [k * g["V"] + d for g in odd for k in range(1, g["nseg"]) for d in (-2, -1, 0, 1)]
+        rng = np.random.default_rng(11)
+        pos = np.unique(np.concatenate([[0, 1, n - 2, n - 1], edges, rng.integers(0, n, 24)]))
+        pos = pos[(pos >= 0) & (pos < n)]
+        si = np.repeat(np.arange(len(scales)), pos.size)
+        ps = np.tile(pos, len(scales))
+        got = w[T.as_tensor(si, device="cuda"), T.as_tensor(ps, device="cuda")].cpu().numpy()
+        ref = oracle.cwt_points(ref_input(f, precision), bc, "morlet", scales, si, ps, param=6.0)
+        err = per_scale_rel_l2(got.reshape(len(scales), pos.size), ref.reshape(len(scales), pos.size))
+        print("  max rel L2", err.max())
+        assert err.max() <= TOL[precision], err
