@@ -139,8 +139,10 @@ extern "C" {
 #define CWT_METHOD_V97 3
 
 /* How the FFT method organises the transform:
- *   CWT_FFT_SEGMENTED -- overlap-save segments of L = 2^l samples per group of
- *                        scales (L about 8x the wavelet half-support); each
+ *   CWT_FFT_SEGMENTED -- overlap-save segments of L samples per group of
+ *                        scales (L = 2^l about 8x the wavelet half-support, or
+ *                        for the larger scales the length c 2^k, c odd, that
+ *                        computes the fewest positions); each
  *                        segment's spectrum is taken once per group, only on
  *                        the band the group's wavelets occupy, and inverted
  *                        per scale with short band-limited FFTs.
