@@ -552,6 +552,14 @@ def bench_wps(args):
     wps, _ = step()
     torch.cuda.synchronize()
     wps = wps.cpu().numpy()
+    # the global spectrum alone by Parseval (cwt_global_wps, whole-signal plan):
+    # one forward FFT and a band sum per scale instead of the transform
+    wplan = cwt.Plan(n, "periodic", wav, scales, param=par, precision="fp32", fft_mode="whole")
+    wws = wplan.empty_workspace(dev)
+    warm_up(lambda: cwt.global_wps(wplan, x, wws), 3)
+    ms_pars, per_pars = timed_steps(lambda: cwt.global_wps(wplan, x, wws), args.steps)
+    g_pars = cwt.global_wps(wplan, x, wws).cpu().numpy()
+    del wws, wplan
     name, (cnt, tot_ms, bpl) = max(kern.items(), key=lambda kv: kv[1][1])
     avg_s = tot_ms / cnt * 1e-3
     flops = fft_flops(plan, name)
@@ -576,6 +584,9 @@ def bench_wps(args):
                            "ms_per_step_with_kernel_events": round(ms_ev, 4),
                            "kernels": {k: {"launches": v[0], "ms_per_step": round(v[1] / args.steps, 4),
                                            "bytes_per_launch": v[2]} for k, v in kern.items()},
+                           "global_by_parseval": {
+                               "ms": round(ms_pars, 4), "ms_median": round(float(np.median(per_pars)), 4),
+                               "max_rel_diff_vs_epilogue": float(np.max(np.abs(g_pars - wps[:, -1]) / wps[:, -1]))},
                            "env_over_global_first_last_scale": [
                                [round(float(wps[0, b] / wps[0, -1]), 4) for b in range(len(thr) + 1)],
                                [round(float(wps[-1, b] / wps[-1, -1]), 4) for b in range(len(thr) + 1)]]},

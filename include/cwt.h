@@ -333,6 +333,27 @@ int cwt_exec_wps(cwt_plan_t plan, const void *signal, const void *env, const dou
                  double *wps, int64_t *counts, void *workspace, void *stream);
 
 /*
+ * cwt_global_wps -- the global wavelet power spectrum (Sec. 5, Eq.
+ * global_wps), P(s) = (1/N) sum_b |W(s, b)|^2, of a periodic signal without
+ * the transform: by Parseval's identity for the circular correlation of Eq.
+ * discrete_CWT_conv (aliased spectrum), P(s) = (1/N^2) sum_m |F[m]|^2
+ * Psi_s(omega_m)^2 with F the N-point DFT of the period, summed over the bins
+ * of each scale's band (FP64 sums in a fixed order).  The same quantity as
+ * column nthr + 1 of cwt_exec_wps, at the cost of one forward FFT.  The
+ * plan's workspace (cwt_workspace_bytes) includes the per-chunk sums.
+ *   signal:    device, N values of the plan's precision.
+ *   wps:       device, S doubles.
+ *   workspace: device, cwt_workspace_bytes(plan) bytes, 256-byte aligned.
+ * Supported for plans of the FFT method with fft_mode CWT_FFT_WHOLE, periodic
+ * boundary, psi_mode CWT_PSI_ALIASED, a band-limited wavelet (not CBSW) and
+ * N = 2^a * {1,3,5,9}, 2^a >= 64 (the FFT length is then N), with at least
+ * one scale that uses the whole-signal spectrum; otherwise CWT_EUNSUPPORTED.
+ * Errors: CWT_EINVAL for NULL or misaligned pointers or a host-only plan;
+ * CWT_EDEVICE when a launch fails.  Streams and events as for cwt_exec.
+ */
+int cwt_global_wps(cwt_plan_t plan, const void *signal, double *wps, void *workspace, void *stream);
+
+/*
  * cwt_exec_batch -- transform n independent signals, each with its own plan
  * (lengths, scales, wavelets, boundaries and precisions may differ), in one
  * enqueue on `stream`.  signals[i], outs[i] as for cwt_exec with plans[i].

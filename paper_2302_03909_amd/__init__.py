@@ -49,7 +49,7 @@ EXPORTS = ["cwt_plan", "cwt_destroy", "cwt_out_is_complex", "cwt_out_elems", "cw
            "cwt_workspace_bytes", "cwt_footprint_bytes", "cwt_exec", "cwt_batch_workspace_bytes",
            "cwt_exec_batch", "cwt_plan_fft_len", "cwt_plan_spline_delta", "cwt_plan_spline_taps", "cwt_plan_spline_hstar",
            "cwt_plan_scale_path", "cwt_plan_describe", "cwt_plan_timing_enable", "cwt_plan_timing_read", "cwt_last_error",
-           "cwt_exec_scratch", "cwt_scratch_bytes", "cwt_wps_workspace_bytes", "cwt_exec_wps"]
+           "cwt_exec_scratch", "cwt_scratch_bytes", "cwt_wps_workspace_bytes", "cwt_exec_wps", "cwt_global_wps"]
 
 _lib = None
 
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cwt_wps_workspace_bytes.argtypes = [vp]
     lib.cwt_wps_workspace_bytes.restype = ctypes.c_size_t
     lib.cwt_exec_wps.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp, vp, vp, vp]
+    lib.cwt_global_wps.argtypes = [vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -298,6 +299,24 @@ def exec_wps(plan: Plan, signal, env=None, thresholds=(0.0,), workspace=None, st
                                ctypes.c_void_p(counts.data_ptr() if counts is not None else 0),
                                ctypes.c_void_p(workspace.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
     return wps, counts
+
+
+def global_wps(plan: Plan, signal, workspace=None, stream=None):
+    """``cwt_global_wps``: the global wavelet power spectrum (Sec. 5) of a
+    periodic device signal by Parseval from its DFT, for a whole-signal
+    periodic plan.  Returns a float64 [S] tensor."""
+    import torch
+    sdt, _ = plan._dtypes()
+    if signal.dtype != sdt or signal.device.type != "cuda" or signal.numel() != plan.n:
+        raise ValueError(f"signal must be a cuda {sdt} tensor of {plan.n} values")
+    signal = signal.contiguous()
+    wps = torch.empty(plan.num_scales, dtype=torch.float64, device=signal.device)
+    if workspace is None:
+        workspace = plan.empty_workspace(signal.device)
+    st = stream if stream is not None else torch.cuda.current_stream(signal.device)
+    _check(load().cwt_global_wps(plan.handle, ctypes.c_void_p(signal.data_ptr()), ctypes.c_void_p(wps.data_ptr()),
+                                 ctypes.c_void_p(workspace.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
+    return wps
 
 
 def exec_scratch(plan: Plan, signal, out=None, stream=None):

@@ -199,6 +199,14 @@ struct SpecJob {
 };
 hipError_t launch_spectrum_tables(const SpecWavelet &w, const SpecJob *jobs, int njobs, int64_t blocks, void *tab,
                                   bool fp64, hipStream_t st);
+// global power spectrum of a periodic signal by Parseval from its M-point
+// DFT F (plan precision, natural order): wps[j] = sum_m |F[m]|^2
+// Psi_{s_j}(omega_m)^2 / M^2, from per-chunk sums part[j][c] (S x
+// parseval_chunks(M) doubles of workspace) added in a fixed order
+constexpr int64_t kParsevalChunk = 16384;  // signed bins per workgroup
+inline int parseval_chunks(int64_t M) { return (int)((M + kParsevalChunk - 1) / kParsevalChunk); }
+hipError_t launch_parseval_wps(const SpecWavelet &w, const void *F, int64_t M, const double *scales, int S,
+                               double *part, double *wps, bool fp64, hipStream_t st);
 
 struct ColumnLaunch {
     int32_t P = 0, G = 0;
@@ -324,6 +332,12 @@ struct Plan {
     int64_t twM64_hi_off = -1, twM64_lo_off = -1;       // FP64, bytes
     void *d_dtab = nullptr;                             // spline d_s (complex FP64)
     std::vector<void *> d_extra;                        // other owned allocations
+    // periodic whole-signal plans with M = N (cwt_global_wps): the wavelet's
+    // spectral amplitude and band, and the scales on the device
+    SpecWavelet spec_w{};
+    bool spec_ok = false;
+    const double *d_scales64 = nullptr;
+    size_t ws_pars_off = 0;  // per-chunk sums of cwt_global_wps in the workspace
 
     // launch timing (benchmarks only)
     struct TimingRec {

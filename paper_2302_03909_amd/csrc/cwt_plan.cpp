@@ -1258,6 +1258,25 @@ static Plan *make_plan(int64_t N, int32_t boundary, cwt_wavelet wv, const double
             p->fft_mode = fft_mode;
             if (p->fft_mode == CWT_FFT_WHOLE) build_fft_plan(*p, w, fft_len);
             else build_seg_plan(*p, w);
+            // cwt_global_wps: a periodic whole-signal plan whose FFT is the
+            // DFT of the period, the aliased spectrum of a band-limited wavelet
+            if (p->fft_mode == CWT_FFT_WHOLE && boundary == CWT_PERIODIC && p->M == N &&
+                psi_mode == CWT_PSI_ALIASED && w.band_limited()) {
+                double ulo, uhi;
+                spectral_band(w, p->rel, ulo, uhi);
+                p->spec_w = SpecWavelet{w.kind, w.m, w.w0, w.cmor, w.kappa, w.gnorm, w.cn, ulo, uhi};
+                p->spec_ok = true;
+                // the chunk sums follow the transform's workspace
+                p->ws_pars_off = (p->ws_bytes + 255) & ~size_t(255);
+                p->ws_bytes = p->ws_pars_off + (size_t)S * parseval_chunks(p->M) * sizeof(double);
+                if (!p->host_only) {
+                    void *d = nullptr;
+                    HIPCHK(hipMalloc(&d, (size_t)S * sizeof(double)));
+                    p->d_extra.push_back(d);
+                    HIPCHK(hipMemcpy(d, scales, (size_t)S * sizeof(double), hipMemcpyHostToDevice));
+                    p->d_scales64 = static_cast<const double *>(d);
+                }
+            }
         } else if (method == CWT_METHOD_V97) {
             build_v97_plan(*p, w);
         } else {
@@ -1952,6 +1971,32 @@ static int exec_wps_impl(cwt_plan_t plan, const void *signal, const void *env, c
 }  // namespace cwt
 
 extern "C" {
+
+int cwt_global_wps(cwt_plan_t plan, const void *signal, double *wps, void *workspace, void *stream) {
+    return guarded([&]() -> int {
+        if (!plan) cwt::fail(CWT_EINVAL, "plan is NULL");
+        if (!signal || !wps || !workspace) cwt::fail(CWT_EINVAL, "signal/wps/workspace is NULL");
+        cwt::Plan &p = *plan->p;
+        if (!p.spec_ok)
+            cwt::fail(CWT_EUNSUPPORTED, "cwt_global_wps needs a periodic plan of the FFT method with fft_mode WHOLE, "
+                                        "psi_mode ALIASED, a band-limited wavelet and N of the form 2^a * {1,3,5,9}, "
+                                        "2^a >= 64, with at least one scale on the whole-signal spectrum");
+        if (p.host_only) cwt::fail(CWT_EINVAL, "plan was built host-only");
+        if (p.S > 65535) cwt::fail(CWT_EUNSUPPORTED, "cwt_global_wps takes at most 65535 scales");
+        const size_t ealign = p.precision == CWT_FP64 ? 8 : 4;
+        if ((uintptr_t)signal % ealign || (uintptr_t)wps % 8) cwt::fail(CWT_EINVAL, "signal/wps misaligned");
+        if ((uintptr_t)workspace % 256) cwt::fail(CWT_EINVAL, "workspace not 256-byte aligned");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        hipError_t e = cwt::launch_forward(p, signal, workspace, st);
+        if (e != hipSuccess) cwt::fail(CWT_EDEVICE, std::string("forward launch: ") + hipGetErrorString(e));
+        char *w = static_cast<char *>(workspace);
+        e = cwt::launch_parseval_wps(p.spec_w, w + p.ws_F_off, p.M, p.d_scales64, p.S,
+                                     reinterpret_cast<double *>(w + p.ws_pars_off), wps, p.precision == CWT_FP64, st);
+        if (e != hipSuccess) cwt::fail(CWT_EDEVICE, std::string("Parseval launch: ") + hipGetErrorString(e));
+        cwt::note_use(p, st);
+        return CWT_OK;
+    });
+}
 
 size_t cwt_wps_workspace_bytes(cwt_plan_t plan) {
     if (!plan || !cwt::wps_plan_ok(*plan->p)) return 0;

@@ -280,3 +280,22 @@ def test_band_lengths_never_compute_more_positions_than_the_power_of_two():
             nseg2 = -(-n // (L2 - 2 * Tg))
             assert nseg * L <= nseg2 * L2
     assert seen_odd
+
+
+def test_global_wps_rejections_host_only():
+    # Parseval's global spectrum needs a periodic whole-signal plan whose FFT
+    # is the period's DFT; everything else is rejected before device work
+    lib = cwt.load()
+    dummy = ctypes.c_void_p(256)
+    sc = np.geomspace(2.0, 4096.0, 24)
+    ok = cwt.Plan(1 << 16, "periodic", "morlet", sc, fft_mode="whole", host_only=True)
+    assert ok.fft_len == 1 << 16
+    assert lib.cwt_global_wps(ok.handle, dummy, dummy, dummy, None) == cwt.CWT_EINVAL  # host-only
+    assert lib.cwt_global_wps(ok.handle, None, dummy, dummy, None) == cwt.CWT_EINVAL
+    assert lib.cwt_global_wps(None, dummy, dummy, dummy, None) == cwt.CWT_EINVAL
+    for p in (cwt.Plan(1 << 16, "periodic", "morlet", sc, host_only=True),                    # segmented
+              cwt.Plan(1 << 16, "zero", "morlet", sc, fft_mode="whole", host_only=True),      # zero boundary
+              cwt.Plan(1000, "periodic", "morlet", sc[:10], fft_mode="whole", host_only=True),  # N not 2^a*{1,3,5,9}
+              cwt.Plan(1 << 16, "periodic", "morlet", sc, fft_mode="whole", psi_mode="analytic", host_only=True),
+              cwt.Plan(1 << 16, "periodic", "mexhat", sc, method="spline", host_only=True)):
+        assert lib.cwt_global_wps(p.handle, dummy, dummy, dummy, None) == cwt.CWT_EUNSUPPORTED

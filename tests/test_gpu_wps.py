@@ -182,3 +182,47 @@ def test_wps_headline_size(torch_cuda, wav, par, bc):
     del out
     torch.cuda.synchronize()
     check(got.cpu().numpy(), ref, cnt.cpu().numpy(), rcnt, n, 2 * TOL["fp32"], f"headline {wav}")
+
+
+# ---- global spectrum by Parseval (cwt_global_wps) ----------------------------
+# For a periodic signal the mean of |W(s, b)|^2 over the period equals
+# (1/N^2) sum_m |F[m]|^2 Psi_s(omega_m)^2: no transform is taken.  The same
+# derived bound (the q = 1 case, 2 eps + eps^2 with the 1e-3 floor) applies.
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("wav,par", [("morlet", 6.0), ("dog", 2.0), ("mexhat", None), ("cwgdw", None),
+                                     ("gdw", None), ("mw", None)])
+def test_parseval_global_spectrum_against_oracle(torch_cuda, precision, wav, par):
+    import paper_2302_03909_amd as cwt
+    n = 1 << 16
+    f = synth.zeldovich_field(n)
+    scales = synth.log_scales(2.0, n / 8.0, 24)
+    print(f"case parseval N={n} {wav} {precision}", flush=True)
+    plan = cwt.Plan(n, "periodic", wav, scales, param=par, precision=precision, fft_mode="whole")
+    dt = torch_cuda.float64 if precision == "fp64" else torch_cuda.float32
+    got = cwt.global_wps(plan, torch_cuda.as_tensor(f, dtype=dt, device="cuda")).cpu().numpy()
+    fr = f.astype(np.float32).astype(np.float64) if precision == "fp32" else f
+    ref, counts = oracle.cwt_wps(fr, "periodic", wav, scales, thresholds=(), param=par, spectral=True)
+    b = bound(ref, counts, n, TOL[precision])[:, -1]
+    rel = np.abs(got - ref[:, -1]) / ref[:, -1]
+    print(f"  max rel err {rel.max():.3e}, worst err/bound {np.max(rel / b):.3f}")
+    assert np.all(rel <= 1.05 * b + 1e-13)
+
+
+def test_parseval_matches_the_epilogue_at_the_headline_size(torch_cuda):
+    # N = 2^22, 128 scales, CW-GDW, FP32: Parseval on a whole-signal plan
+    # against the global column of cwt_exec_wps on the segmented plan
+    import paper_2302_03909_amd as cwt
+    n = 1 << 22
+    f = synth.zeldovich_field(n)
+    scales = synth.log_scales(2.0, 2.0 ** 16, 128)
+    x = torch_cuda.as_tensor(f, dtype=torch_cuda.float32, device="cuda")
+    whole = cwt.Plan(n, "periodic", "cwgdw", scales, precision="fp32", fft_mode="whole")
+    seg = cwt.Plan(n, "periodic", "cwgdw", scales, precision="fp32")
+    a = cwt.global_wps(whole, x).cpu().numpy()
+    w, _ = cwt.exec_wps(seg, x, thresholds=(), with_counts=False)
+    b = w.cpu().numpy()[:, -1]
+    rel = np.abs(a - b) / b
+    print(f"parseval vs epilogue, N=2^22: max rel diff {rel.max():.3e}")
+    # each side within the FP32 bar of the FP64 value: 2 (2 eps + eps^2)
+    assert rel.max() <= 2 * (2e-5 + 1e-10)
