@@ -226,13 +226,33 @@ constexpr int ns_before(int p, int pass) {
     return ns;
 }
 
-// LDS layout: one padding element every 16.  The radix-16 first pass has
-// each lane write 16 consecutive elements (lane stride 16); with the padding
-// that stride becomes 17 elements, an odd number of 8-byte words, so the 16
-// lanes served together hit distinct banks.  Unit-stride accesses stay
-// contiguous within each run of 16.
+// LDS layout: one padding element every 16.  The LDS has 64 banks of 4
+// bytes and serves an 8-byte access 32 lanes at a time.  The radix-16 first
+// pass has each lane write 16 consecutive elements (lane stride 16); with the
+// padding that stride becomes 17 elements, odd, so 32 lanes of one column hit
+// distinct banks.  Unit-stride accesses stay contiguous within each run of 16
+// (32 lanes of them span 33 slots, so one slot is hit twice).
 __device__ __forceinline__ int lidx(int j) { return j + (j >> 4); }
 constexpr int lds_len(int p) { return p + p / 16 + 1; }
+
+// Columns start at c LD, except in the skewed layout of 16 columns of 256
+// 8-byte points (stride kLdSkew256 = 272, 16 mod 32 elements): column c starts at
+// c 272 + 2 floor(c / 2), i.e. at element 2 sigma(c) modulo 32 with
+// sigma(c) = floor(c / 2) + 8 (c mod 2) a permutation of 0..15.  Then the
+// radix-16 first pass (columns 2h and 2h + 1 in one 32-lane half, 16 elements
+// apart) and the column-fastest last pass (columns 0..15 at one position in
+// 16 lanes, the next position in the other 16) both touch 32 distinct 8-byte
+// slots per half-wave; with the plain stride 273 the first pass conflicts
+// two-way.  The columns need 16 LD + 14 elements.
+constexpr int kLdSkew256 = 272;
+template <int LD> __device__ __forceinline__ int col0(int c) {
+    if constexpr (LD == kLdSkew256) return c * LD + (c & ~1);
+    else return c * LD;
+}
+constexpr int cols_len(int ncol, int ld) { return ld == kLdSkew256 ? ncol * ld + 2 * ((ncol - 1) / 2) : ncol * ld; }
+
+// element j of column c
+template <int LD> __device__ __forceinline__ int lds_at(int c, int j) { return col0<LD>(c) + lidx(j); }
 
 // One Stockham pass over NCOL columns held in LDS (column c starts at c*LD).
 template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int R, int NS>

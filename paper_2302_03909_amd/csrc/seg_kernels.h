@@ -287,12 +287,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     const BatchArgs a) {
     using C = cplx_t<R>;
     constexpr int G = 16;
-    constexpr int LD = lds_len(P);
+    // skewed columns for 8-byte elements (a 16-byte access is served 16
+    // lanes at a time, where the plain stride is already conflict-free)
+    constexpr int LD = P == 256 && sizeof(C) == 8 ? kLdSkew256 : lds_len(P);
     constexpr int MAXU = 32;
     constexpr int NB = P / 16;  // pass-0 butterflies per column
     constexpr int KLS = seg_kls_elems(sizeof(R), P);
     static_assert(NT == P, "one pass-0 butterfly per thread");
-    __shared__ C buf[G * LD];
+    __shared__ C buf[cols_len(G, LD)];
     __shared__ C twl[twl_len(P)];
     // spectrum samples of the group's units (and pair partners); complex
     // samples of shifted units in chunks of kls_chunk units
