@@ -65,7 +65,7 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
         if (NB % NT == 0 || gb < NB) {
             int c = gb / (P / R), i = gb % (P / R);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[lds_at<LD>(c, i + r * (P / R))];
+            for (int r = 0; r < R; ++r) v[q][r] = buf[c * LD + lidx(i + r * (P / R)) + col_skew<LD>(c)];
         }
     }
     lds_barrier();
@@ -79,7 +79,7 @@ __device__ __forceinline__ void cols_pass_mid(C *buf, const C *twl) {
             dftR<R, SIGN>(v[q]);
             int base = (i - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[lds_at<LD>(c, base + r * NS)] = v[q][r];
+            for (int r = 0; r < R; ++r) buf[c * LD + lidx(base + r * NS) + col_skew<LD>(c)] = v[q][r];
         }
     }
     lds_barrier();
@@ -107,7 +107,7 @@ __device__ __forceinline__ void cols_pass_last(C *buf, const C *twl, F &emit) {
         if (NB % NT == 0 || gb < NB) {
             int c = POSFAST ? gb / (P / R) : gb % NCOL, i = POSFAST ? gb % (P / R) : gb / NCOL;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[lds_at<LD>(c, i + r * (P / R))];
+            for (int r = 0; r < R; ++r) v[q][r] = buf[c * LD + lidx(i + r * (P / R)) + col_skew<LD>(c)];
         }
     }
     if constexpr (SYNC) lds_barrier();
@@ -170,7 +170,7 @@ __device__ __forceinline__ void cols_pass0_regs(C *buf, C *v) {
     const int c = threadIdx.x / (P / 16), i = threadIdx.x % (P / 16);
     dftR<16, SIGN>(v);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) buf[lds_at<LD>(c, i * 16 + r)] = v[r];
+    for (int r = 0; r < 16; ++r) buf[c * LD + lidx(i * 16 + r) + col_skew<LD>(c)] = v[r];
     lds_barrier();
 }
 

@@ -245,14 +245,17 @@ constexpr int lds_len(int p) { return p + p / 16 + 1; }
 // slots per half-wave; with the plain stride 273 the first pass conflicts
 // two-way.  The columns need 16 LD + 14 elements.
 constexpr int kLdSkew256 = 272;
-template <int LD> __device__ __forceinline__ int col0(int c) {
-    if constexpr (LD == kLdSkew256) return c * LD + (c & ~1);
-    else return c * LD;
-}
 constexpr int cols_len(int ncol, int ld) { return ld == kLdSkew256 ? ncol * ld + 2 * ((ncol - 1) / 2) : ncol * ld; }
 
-// element j of column c
-template <int LD> __device__ __forceinline__ int lds_at(int c, int j) { return col0<LD>(c) + lidx(j); }
+// the shift of column c beyond c LD (element c LD + lidx(j) + col_skew(c));
+// added last, so that the code of every unskewed layout stays as it was
+// (written as one function of the column start, the same addresses led the
+// compiler to a different register allocation, with spills, in the local
+// kernels)
+template <int LD> __device__ __forceinline__ int col_skew(int c) {
+    if constexpr (LD == kLdSkew256) return c & ~1;
+    else return 0;
+}
 
 // One Stockham pass over NCOL columns held in LDS (column c starts at c*LD).
 template <typename C, int P, int NCOL, int NT, int LD, int SIGN, int R, int NS>
