@@ -409,6 +409,11 @@ def main():
                 "frac": round(achieved / FP64_PEAK_TFS, 4), "traffic": measured_traffic(name, workload),
                 "kernel": name, "avg_launch_ms": round(tot_ms / cnt, 4),
                 "algorithmic_flops_per_launch": flops, "output_write_gbs": round(bpl / avg_s / 1e9, 1)}
+        if roof["traffic"]:
+            # the counted HBM bytes (running sums read, outputs written) over
+            # this run's launch time: the rate that bounds the kernel
+            roof["traffic_gbs"] = round(roof["traffic"] / avg_s / 1e9, 1)
+            roof["traffic_frac_of_hbm_peak"] = round(roof["traffic"] / avg_s / 1e9 / HBM_PEAK_GBS, 4)
     else:
         achieved = bpl / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
